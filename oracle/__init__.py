@@ -1,0 +1,15 @@
+"""FP64 CPU oracle for multi-tone phase-calibration extraction.
+
+TEST INFRASTRUCTURE ONLY.  The tests, the smoke check and the benchmark's
+CPU-baseline leg import this package; the product library (the HIP path and
+its Python binding) never does, and the two share no code.
+
+* :mod:`oracle.core` -- ctypes wrapper over ``pcal_oracle.c``: the plain
+  per-tone correlation ``C_k = sum_n x[n] exp(-j 2 pi (k f_comb + f_offset) n / fs)``
+  in FP64, the integer fold of Eq. 2, and the packed-sample decoder.
+* :mod:`oracle.fit` -- amplitude, phase and delay from the C_k (numpy, FP64).
+* :mod:`oracle.params` -- rotator period (Eq. 4) and phase step (Eq. 5).
+"""
+from .core import build, correlate, correlate_f64, decode, fold_int, max_threads  # noqa: F401
+from .fit import delay_fit, in_band, results, tone_freqs  # noqa: F401
+from .params import ntones, phase_step, rotator_period  # noqa: F401
