@@ -1,0 +1,178 @@
+"""Benchmark of the PCal extraction hot path on one MI355X.
+
+A step is one whole integration of the 2-bit workload fs = 64 MHz,
+f_comb = 1 MHz (N = 64 tones), f_offset = 10 kHz (rotator period 6400),
+2^30 samples (256 MiB packed): reset, the fused unpack-rotate-fold kernel
+with its cross-workgroup reduction, the FP64 DFT/amplitude/phase/delay
+finalize, and the copy of the results to the host.  Inputs are resident in
+HBM before timing starts and rotate over four distinct 256 MiB buffers so
+the 256 MB last-level cache cannot serve them.
+
+Prints one JSON line (see the keys below).  ``--gpus N`` with N > 1 exits:
+this build runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gsamples/s and % HBM peak, 2-bit fold @1e-4 rad; p99 latency per integration"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "fold2_64M_10k"
+KERNEL_SRC = os.path.join(ROOT, "paper_2501_05993_amd", "csrc", "pcal_kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "fold_kernel_fold2_64M_10k_pmc.md")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def pmc_traffic():
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it matches this kernel source."""
+    try:
+        with open(PMC_SUMMARY) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("|") and "=" not in line:
+            continue
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(host_bytes, spec, target_s=12.0):
+    """The FP64 oracle timed on this host on a bounded prefix of the same stream."""
+    import oracle
+
+    threads = oracle.max_threads()
+    n = 1 << 20
+    t0 = time.perf_counter()
+    oracle.correlate(host_bytes[: n // 4], 2, n, spec.fs, spec.f_comb, spec.f_offset)
+    dt = time.perf_counter() - t0
+    n2 = int(min(len(host_bytes) * 4, max(n, n * target_s / max(dt, 1e-6))))
+    n2 -= n2 % (1 << 20)
+    t0 = time.perf_counter()
+    oracle.correlate(host_bytes[: n2 // 4], 2, n2, spec.fs, spec.f_comb, spec.f_offset)
+    dt2 = time.perf_counter() - t0
+    return {"value": round(n2 / dt2 / 1e9, 6), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d samples (2^%.1f) of the same 2-bit stream, all %d tones, FP64 per-tone "
+                      "correlation, %.1f s" % (n2, np.log2(n2), spec.ntones, dt2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the extraction of one stream does not span GPUs in this build "
+              "(see DESIGN.md, 'More than one GPU')", file=sys.stderr)
+        sys.exit(2)
+
+    global np
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2501_05993_amd import pcal
+
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[WORKLOAD]
+    spec, L = w["spec"], w["nsamples"]
+    nbytes = L * spec.nbits // 8
+    print("[bench] generating 4 x %d MiB input buffers" % (nbytes >> 20), file=sys.stderr, flush=True)
+    bufs = []
+    for i in range(4):
+        s = synth.CombSpec(spec.fs, spec.f_comb, spec.f_offset, spec.nbits, amp=spec.amp, t_d=spec.t_d,
+                           sigma=spec.sigma, jitter=spec.jitter, seed=tuple(spec.seed) + (i,))
+        bufs.append(synth.make_stream_device(s, L))
+    torch.cuda.synchronize()
+
+    h = pcal.PCal(spec.fs, spec.f_comb, spec.f_offset, spec.nbits)
+    stream = torch.cuda.current_stream()
+
+    def step(i, ev=None):
+        h.reset()
+        if ev is not None:
+            ev[0].record(stream)
+        h.extract(bufs[i % 4], L)
+        if ev is not None:
+            ev[1].record(stream)
+        return h.results()
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        res = step(i, evs[i])
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in evs]
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = L / (ms_per_step * 1e-3) / 1e9
+    kavg_s = float(np.mean(kern_ms)) * 1e-3
+    achieved = nbytes / kavg_s / 1e9
+    traffic = pmc_traffic()
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u2->i32 fold, f64 rotate/DFT", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "fs_hz": spec.fs, "f_comb_hz": spec.f_comb,
+                   "f_offset_hz": spec.f_offset, "nbits": spec.nbits, "nsamples": L, "ntones": spec.ntones,
+                   "rotator_period": 6400, "input_buffers": 4, "method": "period_fold", "precision": "f64"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "fold_kernel<2>",
+                     "kernel_avg_us": round(kavg_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": nbytes},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
+                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 4),
+                       "per": "integration of 2^30 samples (reset + extract + results)"},
+    }
+    if not args.no_accuracy:
+        import oracle
+
+        C = h.spectrum()
+        host = bufs[(args.steps - 1) % 4].cpu().numpy()
+        tones = [1, 31]
+        n0 = h.info()["samples_total"] - L   # the handle's global sample index keeps counting
+        Co = oracle.correlate(host, 2, L, spec.fs, spec.f_comb, spec.f_offset, n0=n0, tones=tones)
+        out["accuracy_vs_oracle"] = {
+            "tones": tones,
+            "amp_rel_err_max": float(np.max(np.abs(np.abs(C[tones]) - np.abs(Co)) / np.abs(Co))),
+            "phase_err_rad_max": float(np.max(np.abs(np.angle(C[tones] * np.conj(Co))))),
+        }
+    if not args.no_cpu_baseline:
+        host = bufs[0].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(host, spec)
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * pcal.h -- C ABI of libpcal, a gfx950 (MI355X) implementation of fast
+ * multi-tone phase-calibration (PCal) extraction (Wagner & Pogrebenko,
+ * "Fast Multi-tone Phase Calibration Signal Extraction", arXiv:2501.05993).
+ *
+ * Method (Section 2 of the paper).  A real baseband stream x[n] sampled at fs
+ * carries a comb of N = fs / f_comb tones at k*f_comb + f_offset (Eq. 1).
+ * Rotating by exp(-j*w_offset*n) (Eq. 3, w_offset = 2*pi*f_offset/fs, Eq. 5)
+ * moves every tone onto a multiple of f_comb; folding the rotated samples
+ * into N bins by n mod N (Eq. 2) and taking one N-point DFT of the bins
+ * (Section 2, DFT(P)) gives each tone's complex response
+ *
+ *     C_k = sum_n x[n] * exp(-j * 2*pi * (k*f_comb + f_offset) * n / fs).
+ *
+ * The sampled rotator repeats after fs / gcd(fs, f_offset) samples (Eq. 4).
+ *
+ * Conventions shared by every entry point:
+ *   - Frequencies are integer Hz (Eq. 4 needs integers).
+ *   - Samples: nbits = 2 -> offset-binary codes 0..3 meaning levels
+ *     -3,-1,+1,+3, four per byte, sample 4j+q in bits [2q, 2q+1] of byte j;
+ *     nbits = 8 -> two's-complement int8.
+ *   - Sample indices are global: each pcal_extract continues where the
+ *     previous call on the handle stopped, so splitting a stream into calls
+ *     does not change the result (phase continuity).
+ *   - Every function returns a status code (enum pcal_status); nothing
+ *     throws across the ABI.  A HIP failure returns PCAL_EHIP and its text
+ *     is kept for pcal_last_error().
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Device pointers are HIP device (or managed) addresses; host pointers
+ *     are ordinary process memory.
+ */
+#ifndef PCAL_H
+#define PCAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pcal_ctx *pcal_t; /* opaque handle, owned by the library */
+typedef void *pcal_stream_t;     /* a hipStream_t; NULL means the null stream */
+
+enum pcal_status {
+    PCAL_OK = 0,
+    PCAL_EINVAL = -1,  /* an argument is out of range or inconsistent */
+    PCAL_ENOMEM = -2,  /* device or host allocation failed */
+    PCAL_EHIP = -3,    /* a HIP runtime call failed; see pcal_last_error() */
+    PCAL_EAGAIN = -4,  /* admission refused for now (memory budget); retry later */
+    PCAL_ESTATE = -5,  /* call not valid in the handle's current state */
+    PCAL_ENOTSUP = -6  /* parameters valid but no kernel form supports them */
+};
+
+/* How the rotation of Eq. 3 is carried out.
+ *  PERIOD_FOLD: fold integer samples over the joint period S = lcm(N, R)
+ *      (R from Eq. 4) and rotate each of the S positions once; by
+ *      distributivity this is the precomputed-rotator method with the rotation
+ *      moved after the accumulation (Section 4.1, the N_rotator-sample
+ *      accumulator folded outside the sample loop).
+ *  LUT: multiply every sample by a precomputed rotator table value (Eq. 4
+ *      table, Section 4.1), accumulate in FP32.
+ *  OSC: multiply every sample by a recurrence sinewave generator (Eq. 6-7
+ *      direct-form resonator), re-seeded exactly at intervals.
+ *  AUTO: PERIOD_FOLD when the joint period fits, else OSC. */
+enum pcal_method {
+    PCAL_METHOD_AUTO = 0,
+    PCAL_METHOD_PERIOD_FOLD = 1,
+    PCAL_METHOD_LUT = 2,
+    PCAL_METHOD_OSC = 3
+};
+
+/* Arithmetic of the rotation and the per-block fold.  The cross-block
+ * reduction, the N-point DFT and the delay fit always run in FP64 except in
+ * PCAL_PREC_F32, the all-FP32 comparison form.
+ *  F64:   rotator table in FP64, products and per-block sums in FP64.
+ *  MIXED: rotator table in FP16, FP32 products, Kahan-compensated FP32
+ *         per-block sums; FP64 from the cross-block reduction on.
+ *  F32:   FP32 table, plain FP32 sums, FP32 reduction and DFT. */
+enum pcal_precision { PCAL_PREC_F64 = 0, PCAL_PREC_MIXED = 1, PCAL_PREC_F32 = 2 };
+
+/* Create a handle for one stream.
+ *   fs_hz > 0, f_comb_hz > 0, fs_hz % f_comb_hz == 0 (N integer, Section 2),
+ *   0 <= f_offset_hz < fs_hz, N <= 4096, nbits in {2, 8},
+ *   sideband = +1 (upper) or -1 (lower: results are complex-conjugated, so
+ *   phases and delay change sign).
+ * Allocates the handle's tables and accumulators on the current HIP device.
+ * Returns PCAL_EINVAL without touching the GPU when a parameter is invalid. */
+int pcal_create(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband,
+                pcal_t *out);
+
+/* As pcal_create with an explicit kernel form and precision. */
+int pcal_create_ex(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband,
+                   int method, int precision, pcal_t *out);
+
+/* Enqueue the unpack-rotate-fold of nsamples packed samples at dev_ptr on
+ * stream.  nsamples must be a multiple of the samples per byte (4 at 2-bit);
+ * dev_ptr needs no particular alignment (a misaligned head is handled
+ * separately).  Asynchronous: dev_ptr must stay valid until the stream has
+ * passed the enqueued work.  Work on a stream other than the previous call's
+ * is ordered after it.  nsamples == 0 is a no-op. */
+int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t stream);
+
+/* Finish the current integration: FP64 N-point DFT of the bins, then for
+ * every tone k (k = 0..N-1, tone frequency f_offset + k*f_comb)
+ *   amp[k]   = |C_k| / L  (L = samples since the last reset),
+ *   phase[k] = arg C_k in (-pi, pi] (radians),
+ * and delay[0] = slope / (2*pi) of the least-squares line through the
+ * phases unwrapped along increasing frequency over the tones with
+ * 0 < f_k < fs/2 (seconds).  Any output pointer may be NULL.  Synchronises
+ * the handle's last stream; does not reset the accumulators. */
+int pcal_results(pcal_t h, double *amp, double *phase, double *delay);
+
+/* The raw C_k (k = 0..N-1) of the current integration, FP64 real and imaginary
+ * parts (after the sideband convention).  Synchronises. */
+int pcal_spectrum(pcal_t h, double *re, double *im);
+
+/* The rotated, folded bins P[b] (b = 0..N-1) of Eq. 2-3 in FP64.  When
+ * f_offset == 0 and int_bins != NULL, also the exact integer bins of Eq. 2
+ * (int64).  Synchronises. */
+int pcal_bins(pcal_t h, double *re, double *im, int64_t *int_bins);
+
+/* Start a new integration: zero the accumulators; the global sample index
+ * keeps counting (rotator phase stays continuous).  Ordered on the handle's
+ * last stream. */
+int pcal_reset(pcal_t h);
+
+/* Release the handle and everything it owns (synchronises first). */
+int pcal_destroy(pcal_t h);
+
+/* Number of tones N of the handle. */
+int pcal_num_tones(pcal_t h, int *n);
+
+/* Derived quantities of a handle, for reporting and tests. */
+typedef struct {
+    int64_t ntones;          /* N = fs / f_comb */
+    int64_t rotator_period;  /* R = fs / gcd(fs, f_offset), Eq. 4 */
+    int64_t joint_period;    /* S = lcm(N, R) */
+    int64_t fold_period;     /* S' = lcm(S, samples per 16-byte vector) */
+    int64_t method;          /* enum pcal_method actually used */
+    int64_t precision;       /* enum pcal_precision */
+    int64_t samples_total;   /* global samples consumed so far */
+    int64_t samples_integ;   /* samples in the current integration */
+    int64_t block_threads;   /* fold kernel workgroup size */
+    int64_t row_vectors;     /* 16-byte vectors per fold row */
+    int64_t col_tiles;       /* workgroups across one fold row */
+    int64_t lds_positions;   /* period positions held per workgroup */
+    int64_t device_bytes;    /* device memory owned by the handle */
+} pcal_info_t;
+
+int pcal_info(pcal_t h, pcal_info_t *info);
+
+/* Host-only planning (no GPU call): fills info for the given parameters as
+ * pcal_create_ex would, without allocating.  For tests and admission. */
+int pcal_plan(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int method,
+              int precision, pcal_info_t *info);
+
+/* Launch geometry of one pcal_extract call (host-only, no GPU call): the
+ * numbers the fused kernel is launched with for nsamples samples at a device
+ * address whose low bits are addr_low (only addr_low mod 16 matters) when
+ * samples_before samples were consumed earlier.  For tests and tools that
+ * check the kernel's index arithmetic on the CPU. */
+typedef struct {
+    int64_t grid;            /* workgroups */
+    int64_t threads;         /* threads per workgroup */
+    int64_t lds_bytes;       /* dynamic LDS per workgroup */
+    int64_t head_bytes;      /* bytes before the first 16-byte aligned vector */
+    int64_t nvec;            /* full 16-byte vectors */
+    int64_t tail_bytes;      /* bytes after the last full vector */
+    int64_t rows_total;      /* rows of row_vectors vectors (last may be partial) */
+    int64_t rows_per_group;  /* rows walked by one workgroup */
+    int64_t q0;              /* global index of the first vector sample, mod fold_period */
+    int64_t head_q;          /* global index of the first head sample, mod fold_period */
+    int64_t tail_q;          /* global index of the first tail sample, mod fold_period */
+} pcal_launch_t;
+
+int pcal_plan_launch(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int method,
+                     int precision, uint64_t addr_low, int64_t samples_before, int64_t nsamples,
+                     pcal_launch_t *out);
+
+/* Text of a status code. */
+const char *pcal_strerror(int code);
+
+/* Text of the last HIP error seen by the library in this thread ("" if none). */
+const char *pcal_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCAL_H */

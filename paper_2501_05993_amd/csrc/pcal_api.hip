@@ -1,0 +1,590 @@
+// Host side of libpcal: parameter checks, planning of the fold geometry,
+// FP64 rotator tables, device memory, stream ordering and the C ABI of pcal.h.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "pcal.h"
+#include "pcal_internal.h"
+
+namespace pcal {
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+void set_error(const char *what, hipError_t e) {
+    snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+}
+
+#define PCAL_HIP(call)                      \
+    do {                                    \
+        hipError_t e_ = (call);             \
+        if (e_ != hipSuccess) {             \
+            set_error(#call, e_);           \
+            return PCAL_EHIP;               \
+        }                                   \
+    } while (0)
+
+int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a < 0 ? -a : a;
+}
+
+// lcm, or -1 on overflow past limit
+int64_t lcm_capped(int64_t a, int64_t b, int64_t limit) {
+    const int64_t g = gcd64(a, b);
+    const int64_t q = a / g;
+    if (q > limit / b) return -1;
+    return q * b;
+}
+
+// exp(-j 2 pi num / den) for 0 <= num < den, argument reduced to [-pi, pi].
+void phasor(int64_t num, int64_t den, double *re, double *im) {
+    const double two_pi = 6.283185307179586476925286766559;
+    double ang;
+    if (2 * num <= den)
+        ang = two_pi * static_cast<double>(num) / static_cast<double>(den);
+    else
+        ang = -two_pi * static_cast<double>(den - num) / static_cast<double>(den);
+    *re = cos(ang);
+    *im = -sin(ang);
+}
+
+// Tuning knobs (defaults chosen by measurement; environment overrides for sweeps).
+int env_int(const char *name, int dflt) {
+    const char *s = getenv(name);
+    return (s && *s) ? atoi(s) : dflt;
+}
+
+struct Plan {
+    int64_t fs, fc, fo;
+    int nbits, sideband, method, prec;
+    int64_t N, R, S, Sp, M;
+    FoldGeom geom;
+    int target_blocks;
+    int max_blocks;
+};
+
+constexpr int64_t kMaxFoldPeriod = int64_t(1) << 26;  // S' samples
+constexpr int64_t kMaxTableRows = int64_t(1) << 20;   // u table entries
+
+int check_params(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband) {
+    if (fs <= 0 || fc <= 0 || fs % fc) return PCAL_EINVAL;
+    if (fo < 0 || fo >= fs) return PCAL_EINVAL;
+    if (fs / fc > kMaxTones) return PCAL_EINVAL;
+    if (nbits != 2 && nbits != 8) return PCAL_EINVAL;
+    if (sideband != 1 && sideband != -1) return PCAL_EINVAL;
+    return PCAL_OK;
+}
+
+// Fold geometry.  One tile holds the whole period when it fits the LDS
+// position budget: then a row is k periods long and the workgroup size is
+// picked to waste the fewest lanes.  Otherwise a row is one period, split
+// into equal column tiles of at most the budget.
+FoldGeom plan_geom(int64_t Sp, int nbits) {
+    FoldGeom g{};
+    g.spv = spv_of(nbits);
+    const int64_t W = Sp / g.spv;  // vectors per period
+    const int pref = env_int("PCAL_FOLD_THREADS", 0);
+    if (Sp <= kMaxLdsPositions && W <= kMaxFoldThreads) {
+        int best_t = 0;
+        double best = -1.0;
+        for (int t = 256; t <= kMaxFoldThreads; t += 64) {
+            if (pref && t != pref) continue;
+            const int64_t k = t / W;
+            if (k < 1) continue;
+            const double eff = static_cast<double>(k * W) / t;
+            if (eff > best + 1e-9) {
+                best = eff;
+                best_t = t;
+            }
+        }
+        if (best_t == 0) best_t = static_cast<int>(((W + 63) / 64) * 64);
+        const int k = static_cast<int>(std::max<int64_t>(1, best_t / W));
+        g.threads = best_t;
+        g.row_vecs = static_cast<int>(k * W);
+        g.tile_vecs = g.row_vecs;
+        g.col_tiles = 1;
+        g.pos_cols = static_cast<int>(W);
+        g.npos = static_cast<int>(Sp);
+    } else {
+        const int tile_max = std::min(kMaxFoldThreads, kMaxLdsPositions / g.spv);
+        const int64_t tiles = (W + tile_max - 1) / tile_max;
+        const int64_t tile = (W + tiles - 1) / tiles;
+        g.row_vecs = static_cast<int>(W);
+        g.tile_vecs = static_cast<int>(tile);
+        g.col_tiles = static_cast<int>(tiles);
+        g.pos_cols = g.tile_vecs;
+        g.npos = g.tile_vecs * g.spv;
+        g.threads = static_cast<int>(((tile + 63) / 64) * 64);
+    }
+    return g;
+}
+
+int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int method, int prec,
+              Plan *p) {
+    int rc = check_params(fs, fc, fo, nbits, sideband);
+    if (rc) return rc;
+    if (method < PCAL_METHOD_AUTO || method > PCAL_METHOD_OSC) return PCAL_EINVAL;
+    if (prec < PCAL_PREC_F64 || prec > PCAL_PREC_F32) return PCAL_EINVAL;
+    p->fs = fs;
+    p->fc = fc;
+    p->fo = fo;
+    p->nbits = nbits;
+    p->sideband = sideband;
+    p->prec = prec;
+    p->N = fs / fc;
+    p->R = fs / gcd64(fs, fo);  // Eq. 4 (gcd(fs, 0) = fs gives R = 1)
+    p->S = lcm_capped(p->N, p->R, kMaxFoldPeriod);
+    p->Sp = p->S > 0 ? lcm_capped(p->S, spv_of(nbits), kMaxFoldPeriod) : -1;
+    p->M = p->Sp > 0 ? p->Sp / p->N : -1;
+    const bool fold_ok = p->Sp > 0 && p->M <= kMaxTableRows;
+    if (method == PCAL_METHOD_AUTO) method = PCAL_METHOD_PERIOD_FOLD;
+    if (method != PCAL_METHOD_PERIOD_FOLD) return PCAL_ENOTSUP;
+    if (!fold_ok) return PCAL_ENOTSUP;
+    p->method = method;
+    p->geom = plan_geom(p->Sp, nbits);
+    p->target_blocks = env_int("PCAL_TARGET_BLOCKS", 1024);
+    if (p->target_blocks < 1) p->target_blocks = 1;
+    p->max_blocks = std::max(p->geom.col_tiles, p->target_blocks) + p->geom.col_tiles;
+    return PCAL_OK;
+}
+
+// Launch geometry of one extract call.
+pcal_launch_t plan_launch(const Plan &p, uint64_t addr, int64_t n_before, int64_t nsamples) {
+    const FoldGeom &g = p.geom;
+    const int spb = 8 / p.nbits;
+    pcal_launch_t L{};
+    const int64_t nbytes = nsamples / spb;
+    int64_t head = static_cast<int64_t>((16 - (addr & 15)) & 15);
+    if (head > nbytes) head = nbytes;
+    L.head_bytes = head;
+    L.nvec = (nbytes - head) / 16;
+    L.tail_bytes = nbytes - head - 16 * L.nvec;
+    const int64_t g0 = n_before + head * spb;  // global index of the first full-vector sample
+    L.rows_total = (L.nvec + g.row_vecs - 1) / g.row_vecs;
+    const int64_t groups_want = std::max<int64_t>(1, p.target_blocks / g.col_tiles);
+    const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(groups_want, L.rows_total));
+    L.rows_per_group = L.rows_total > 0 ? (L.rows_total + groups - 1) / groups : 1;
+    const int64_t ngroups = L.rows_total > 0 ? (L.rows_total + L.rows_per_group - 1) / L.rows_per_group : 1;
+    L.grid = ngroups * g.col_tiles;
+    L.threads = g.threads;
+    L.lds_bytes = static_cast<int64_t>(fold_lds_bytes(g.npos, g.spv, g.threads, p.M));
+    L.q0 = g0 % p.Sp;
+    L.head_q = n_before % p.Sp;
+    L.tail_q = (g0 + L.nvec * g.spv) % p.Sp;
+    return L;
+}
+
+void fill_info(const Plan &p, pcal_info_t *info) {
+    memset(info, 0, sizeof(*info));
+    info->ntones = p.N;
+    info->rotator_period = p.R;
+    info->joint_period = p.S;
+    info->fold_period = p.Sp;
+    info->method = p.method;
+    info->precision = p.prec;
+    info->block_threads = p.geom.threads;
+    info->row_vectors = p.geom.row_vecs;
+    info->col_tiles = p.geom.col_tiles;
+    info->lds_positions = p.geom.npos;
+}
+
+}  // namespace
+}  // namespace pcal
+
+using namespace pcal;
+
+struct pcal_ctx {
+    Plan plan;
+    int device = 0;
+    double2 *u64 = nullptr;
+    float2 *u32 = nullptr;
+    __half2 *u16 = nullptr;
+    double2 *v = nullptr;
+    double2 *tw = nullptr;
+    double2 *acc = nullptr;
+    long long *acc_int = nullptr;
+    float2 *accf = nullptr;
+    unsigned *counters = nullptr;  // [0] finalize
+    double *out = nullptr;         // device results [4N + 1]
+    double *host_out = nullptr;    // pinned copy
+    int64_t n_total = 0;
+    int64_t n_integ = 0;
+    hipStream_t last_stream = nullptr;
+    hipEvent_t ev = nullptr;
+    bool have_ev = false;
+    size_t device_bytes = 0;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(pcal_ctx *h, T **p, size_t count) {
+    const size_t bytes = sizeof(T) * (count ? count : 1);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), bytes);
+    if (e != hipSuccess) {
+        set_error("hipMalloc", e);
+        return e == hipErrorOutOfMemory ? PCAL_ENOMEM : PCAL_EHIP;
+    }
+    h->device_bytes += bytes;
+    return PCAL_OK;
+}
+
+void release(pcal_ctx *h) {
+    void *ptrs[] = {h->u64, h->u32, h->u16, h->v, h->tw, h->acc, h->acc_int, h->accf, h->counters, h->out};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (h->host_out) (void)hipHostFree(h->host_out);
+    if (h->ev) (void)hipEventDestroy(h->ev);
+    delete h;
+}
+
+int build(pcal_ctx *h) {
+    const Plan &p = h->plan;
+    const int64_t N = p.N, M = p.M;
+    int rc;
+    if ((rc = dalloc(h, &h->u64, M)) || (rc = dalloc(h, &h->u32, M)) || (rc = dalloc(h, &h->u16, M)) ||
+        (rc = dalloc(h, &h->v, N)) || (rc = dalloc(h, &h->tw, N)) || (rc = dalloc(h, &h->acc, kAccSlots * N)) ||
+        (rc = dalloc(h, &h->acc_int, kAccSlots * N)) || (rc = dalloc(h, &h->accf, kAccSlots * N)) || (rc = dalloc(h, &h->counters, 1)) ||
+        (rc = dalloc(h, &h->out, 4 * N + 1)))
+        return rc;
+    {
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->host_out), sizeof(double) * (4 * N + 1),
+                                     hipHostMallocDefault);
+        if (e != hipSuccess) {
+            set_error("hipHostMalloc", e);
+            return PCAL_ENOMEM;
+        }
+    }
+    // Rotator factors from exact integer phase indices, in FP64 (Eq. 3-5):
+    //   u[m] = exp(-j 2 pi (f_o N m mod fs) / fs),  v[b] = exp(-j 2 pi (f_o b mod fs) / fs),
+    //   tw[j] = exp(-j 2 pi j / N)  (DFT twiddles).
+    std::vector<double2> u(M), v(N), tw(N);
+    std::vector<float2> uf(M);
+    std::vector<__half2> uh(M);
+    const int64_t step_u = static_cast<int64_t>((static_cast<unsigned __int128>(p.fo) * N) % p.fs);
+    int64_t idx = 0;
+    for (int64_t m = 0; m < M; ++m) {
+        phasor(idx, p.fs, &u[m].x, &u[m].y);
+        uf[m] = make_float2(static_cast<float>(u[m].x), static_cast<float>(u[m].y));
+        const _Float16 hx = static_cast<_Float16>(u[m].x), hy = static_cast<_Float16>(u[m].y);
+        memcpy(reinterpret_cast<char *>(&uh[m]), &hx, 2);
+        memcpy(reinterpret_cast<char *>(&uh[m]) + 2, &hy, 2);
+        idx += step_u;
+        if (idx >= p.fs) idx -= p.fs;
+    }
+    idx = 0;
+    for (int64_t b = 0; b < N; ++b) {
+        phasor(idx, p.fs, &v[b].x, &v[b].y);
+        idx += p.fo;
+        if (idx >= p.fs) idx -= p.fs;
+        phasor(b, N, &tw[b].x, &tw[b].y);
+    }
+    PCAL_HIP(hipMemcpy(h->u64, u.data(), sizeof(double2) * M, hipMemcpyHostToDevice));
+    PCAL_HIP(hipMemcpy(h->u32, uf.data(), sizeof(float2) * M, hipMemcpyHostToDevice));
+    PCAL_HIP(hipMemcpy(h->u16, uh.data(), sizeof(__half2) * M, hipMemcpyHostToDevice));
+    PCAL_HIP(hipMemcpy(h->v, v.data(), sizeof(double2) * N, hipMemcpyHostToDevice));
+    PCAL_HIP(hipMemcpy(h->tw, tw.data(), sizeof(double2) * N, hipMemcpyHostToDevice));
+    PCAL_HIP(hipMemset(h->acc, 0, sizeof(double2) * kAccSlots * N));
+    PCAL_HIP(hipMemset(h->acc_int, 0, sizeof(long long) * kAccSlots * N));
+    PCAL_HIP(hipMemset(h->accf, 0, sizeof(float2) * kAccSlots * N));
+    PCAL_HIP(hipMemset(h->counters, 0, sizeof(unsigned)));
+    PCAL_HIP(hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
+    return PCAL_OK;
+}
+
+// Order work on `s` after the handle's previous work (possibly on another stream).
+int order_on(pcal_ctx *h, hipStream_t s) {
+    if (h->have_ev && s != h->last_stream) PCAL_HIP(hipStreamWaitEvent(s, h->ev, 0));
+    return PCAL_OK;
+}
+
+int mark(pcal_ctx *h, hipStream_t s) {
+    PCAL_HIP(hipEventRecord(h->ev, s));
+    h->have_ev = true;
+    h->last_stream = s;
+    return PCAL_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int run_finalize(pcal_ctx *h) {
+    const Plan &p = h->plan;
+    const int N = static_cast<int>(p.N);
+    FinArgs f{};
+    f.acc = h->acc;
+    f.tw = h->tw;
+    f.N = N;
+    f.prec = p.prec;
+    f.sideband = p.sideband;
+    f.inv_L = h->n_integ > 0 ? 1.0 / static_cast<double>(h->n_integ) : 0.0;
+    // in-band tones 0 < f_o + k f_c < fs / 2
+    int k_lo = N, k_hi = 0;
+    for (int k = 0; k < N; ++k) {
+        const int64_t fk = p.fo + int64_t(k) * p.fc;
+        if (fk > 0 && 2 * fk < p.fs) {
+            k_lo = std::min(k_lo, k);
+            k_hi = std::max(k_hi, k + 1);
+        }
+    }
+    if (k_hi <= k_lo) k_lo = k_hi = 0;
+    f.k_lo = k_lo;
+    f.k_hi = k_hi;
+    f.f_comb = static_cast<double>(p.fc);
+    f.out = h->out;
+    f.accf = h->accf;
+    f.counter = h->counters;
+    hipStream_t s = h->last_stream;
+    launch_finalize(f, s);
+    PCAL_HIP(hipGetLastError());
+    PCAL_HIP(hipMemcpyAsync(h->host_out, h->out, sizeof(double) * (4 * p.N + 1), hipMemcpyDeviceToHost, s));
+    PCAL_HIP(hipStreamSynchronize(s));
+    return PCAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcal_plan(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int method, int precision,
+              pcal_info_t *info) {
+    if (!info) return PCAL_EINVAL;
+    Plan p{};
+    const int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, 1, method, precision, &p);
+    if (rc) return rc;
+    fill_info(p, info);
+    return PCAL_OK;
+}
+
+int pcal_plan_launch(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int method,
+                     int precision, uint64_t addr_low, int64_t samples_before, int64_t nsamples,
+                     pcal_launch_t *out) {
+    if (!out || samples_before < 0 || nsamples < 0) return PCAL_EINVAL;
+    Plan p{};
+    const int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, 1, method, precision, &p);
+    if (rc) return rc;
+    if (nsamples % (8 / nbits)) return PCAL_EINVAL;
+    *out = plan_launch(p, addr_low, samples_before, nsamples);
+    return PCAL_OK;
+}
+
+int pcal_create_ex(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband, int method,
+                   int precision, pcal_t *out) {
+    if (!out) return PCAL_EINVAL;
+    *out = nullptr;
+    Plan p{};
+    int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, method, precision, &p);
+    if (rc) return rc;
+    pcal_ctx *h = new (std::nothrow) pcal_ctx();
+    if (!h) return PCAL_ENOMEM;
+    h->plan = p;
+    {
+        hipError_t e = hipGetDevice(&h->device);
+        if (e != hipSuccess) {
+            set_error("hipGetDevice", e);
+            delete h;
+            return PCAL_EHIP;
+        }
+    }
+    rc = build(h);
+    if (rc) {
+        release(h);
+        return rc;
+    }
+    *out = h;
+    return PCAL_OK;
+}
+
+int pcal_create(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband, pcal_t *out) {
+    return pcal_create_ex(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_AUTO, PCAL_PREC_F64, out);
+}
+
+int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t stream) {
+    if (!h || nsamples < 0) return PCAL_EINVAL;
+    const Plan &p = h->plan;
+    const int spb = 8 / p.nbits;
+    if (nsamples % spb) return PCAL_EINVAL;
+    if (nsamples == 0) return PCAL_OK;
+    if (!dev_ptr) return PCAL_EINVAL;
+    DeviceGuard guard(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = order_on(h, s);
+    if (rc) return rc;
+
+    const FoldGeom &g = p.geom;
+    const pcal_launch_t L = plan_launch(p, reinterpret_cast<uintptr_t>(dev_ptr), h->n_total, nsamples);
+    if (L.grid > p.max_blocks) return PCAL_EINVAL;  // cannot happen by construction
+
+    FoldArgs a{};
+    a.data = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(dev_ptr) + L.head_bytes);
+    a.nvec = L.nvec;
+    a.rows_total = L.rows_total;
+    a.rows_per_group = L.rows_per_group;
+    a.row_vecs = g.row_vecs;
+    a.tile_vecs = g.tile_vecs;
+    a.col_tiles = g.col_tiles;
+    a.pos_cols = g.pos_cols;
+    a.npos = g.npos;
+    a.N = static_cast<int>(p.N);
+    a.nbits = p.nbits;
+    a.prec = p.prec;
+    a.int_bins = p.fo == 0 ? 1 : 0;
+    a.Sp = p.Sp;
+    a.M = p.M;
+    a.q0 = L.q0;
+    a.u64 = h->u64;
+    a.u32 = h->u32;
+    a.u16 = h->u16;
+    a.v = h->v;
+    a.head = static_cast<const uint8_t *>(dev_ptr);
+    a.head_bytes = static_cast<int>(L.head_bytes);
+    a.head_q = L.head_q;
+    a.tail = static_cast<const uint8_t *>(dev_ptr) + L.head_bytes + 16 * L.nvec;
+    a.tail_bytes = static_cast<int>(L.tail_bytes);
+    a.tail_q = L.tail_q;
+    a.acc = h->acc;
+    a.acc_int = h->acc_int;
+    a.accf = h->accf;
+    launch_fold(a, p.nbits, static_cast<int>(L.grid), g.threads, static_cast<size_t>(L.lds_bytes), s);
+    PCAL_HIP(hipGetLastError());
+    h->n_total += nsamples;
+    h->n_integ += nsamples;
+    return mark(h, s);
+}
+
+int pcal_results(pcal_t h, double *amp, double *phase, double *delay) {
+    if (!h) return PCAL_EINVAL;
+    DeviceGuard guard(h->device);
+    int rc = run_finalize(h);
+    if (rc) return rc;
+    const size_t N = static_cast<size_t>(h->plan.N);
+    if (amp) memcpy(amp, h->host_out, sizeof(double) * N);
+    if (phase) memcpy(phase, h->host_out + N, sizeof(double) * N);
+    if (delay) *delay = h->host_out[4 * N];
+    return PCAL_OK;
+}
+
+int pcal_spectrum(pcal_t h, double *re, double *im) {
+    if (!h) return PCAL_EINVAL;
+    DeviceGuard guard(h->device);
+    int rc = run_finalize(h);
+    if (rc) return rc;
+    const size_t N = static_cast<size_t>(h->plan.N);
+    if (re) memcpy(re, h->host_out + 2 * N, sizeof(double) * N);
+    if (im) memcpy(im, h->host_out + 3 * N, sizeof(double) * N);
+    return PCAL_OK;
+}
+
+int pcal_bins(pcal_t h, double *re, double *im, int64_t *int_bins) {
+    if (!h) return PCAL_EINVAL;
+    if (int_bins && h->plan.fo != 0) return PCAL_ESTATE;
+    DeviceGuard guard(h->device);
+    const size_t N = static_cast<size_t>(h->plan.N);
+    hipStream_t s = h->last_stream;
+    const size_t NS = N * kAccSlots;
+    std::vector<double2> b(NS);
+    std::vector<float2> bf(NS);
+    std::vector<long long> ib(NS);
+    if (h->plan.prec == PCAL_PREC_F32)
+        PCAL_HIP(hipMemcpyAsync(bf.data(), h->accf, sizeof(float2) * NS, hipMemcpyDeviceToHost, s));
+    else
+        PCAL_HIP(hipMemcpyAsync(b.data(), h->acc, sizeof(double2) * NS, hipMemcpyDeviceToHost, s));
+    if (int_bins) PCAL_HIP(hipMemcpyAsync(ib.data(), h->acc_int, sizeof(long long) * NS, hipMemcpyDeviceToHost, s));
+    PCAL_HIP(hipStreamSynchronize(s));
+    // add the accumulator slots in slot order (as the finalize does)
+    for (size_t i = 0; i < N; ++i) {
+        double sr = 0.0, si = 0.0;
+        float fr = 0.f, fi = 0.f;
+        long long sn = 0;
+        for (size_t k = 0; k < static_cast<size_t>(kAccSlots); ++k) {
+            if (h->plan.prec == PCAL_PREC_F32) {
+                fr += bf[k * N + i].x;
+                fi += bf[k * N + i].y;
+            } else {
+                sr += b[k * N + i].x;
+                si += b[k * N + i].y;
+            }
+            sn += ib[k * N + i];
+        }
+        if (h->plan.prec == PCAL_PREC_F32) {
+            sr = fr;
+            si = fi;
+        }
+        if (re) re[i] = sr;
+        if (im) im[i] = si;
+        if (int_bins) int_bins[i] = sn;
+    }
+    return PCAL_OK;
+}
+
+int pcal_reset(pcal_t h) {
+    if (!h) return PCAL_EINVAL;
+    DeviceGuard guard(h->device);
+    hipStream_t s = h->last_stream;
+    launch_zero(h->acc, sizeof(double2) * kAccSlots * h->plan.N, s);
+    launch_zero(h->acc_int, sizeof(long long) * kAccSlots * h->plan.N, s);
+    launch_zero(h->accf, sizeof(float2) * kAccSlots * h->plan.N, s);
+    PCAL_HIP(hipGetLastError());
+    h->n_integ = 0;
+    return mark(h, s);
+}
+
+int pcal_destroy(pcal_t h) {
+    if (!h) return PCAL_EINVAL;
+    {
+        DeviceGuard guard(h->device);
+        if (h->have_ev) (void)hipEventSynchronize(h->ev);
+        release(h);
+    }
+    return PCAL_OK;
+}
+
+int pcal_num_tones(pcal_t h, int *n) {
+    if (!h || !n) return PCAL_EINVAL;
+    *n = static_cast<int>(h->plan.N);
+    return PCAL_OK;
+}
+
+int pcal_info(pcal_t h, pcal_info_t *info) {
+    if (!h || !info) return PCAL_EINVAL;
+    fill_info(h->plan, info);
+    info->samples_total = h->n_total;
+    info->samples_integ = h->n_integ;
+    info->device_bytes = static_cast<int64_t>(h->device_bytes);
+    return PCAL_OK;
+}
+
+const char *pcal_strerror(int code) {
+    switch (code) {
+        case PCAL_OK: return "ok";
+        case PCAL_EINVAL: return "invalid argument";
+        case PCAL_ENOMEM: return "out of memory";
+        case PCAL_EHIP: return "HIP runtime error";
+        case PCAL_EAGAIN: return "resources busy, try again";
+        case PCAL_ESTATE: return "invalid state for this call";
+        case PCAL_ENOTSUP: return "parameters not supported by any kernel form";
+        default: return "unknown status";
+    }
+}
+
+const char *pcal_last_error(void) { return g_last_error; }
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal definitions shared by the libpcal host code and its gfx950 kernels.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcal {
+
+// Samples per 16-byte vector load for each sample format.
+constexpr int spv_of(int nbits) { return nbits == 2 ? 64 : 16; }
+
+// Largest number of period positions a fold workgroup keeps in LDS (int32 each).
+constexpr int kMaxLdsPositions = 12288;
+// Rotator rows (u table) kept in LDS by the fold kernel when the table is at most this long.
+constexpr int kLdsTableRows = 512;
+// Per-thread LDS scratch of the fold epilogue (a partial bin sum in every precision).
+constexpr int kEpilogueScratch = 40;
+// Copies of the integration bins that fold workgroups add into (workgroup mod
+// kAccSlots), summed by the finalize: spreads same-address atomics.
+constexpr int kAccSlots = 16;
+// Largest workgroup of the fold kernel.
+constexpr int kMaxFoldThreads = 1024;
+// Largest number of tones (bins) supported.
+constexpr int kMaxTones = 4096;
+
+// Geometry of the period-fold kernel for one handle (host-computed at create time).
+//
+// The packed stream is viewed as rows of `row_vecs` 16-byte vectors; row_vecs is a
+// multiple of the fold period S' expressed in vectors, so a thread that always reads
+// the same column of successive rows always meets the same period positions and can
+// keep one integer counter per position in registers.  A row is split into
+// `col_tiles` tiles of `tile_vecs` columns, one thread per column.
+struct FoldGeom {
+    int spv;         // samples per vector (64 at 2-bit, 16 at 8-bit)
+    int row_vecs;    // vectors per row (a multiple of S'/spv)
+    int tile_vecs;   // columns per workgroup
+    int col_tiles;   // workgroups across a row
+    int pos_cols;    // columns per distinct set of positions (S'/spv when one tile holds the period)
+    int npos;        // period positions held per workgroup = pos_cols * spv
+    int threads;     // workgroup size (multiple of 64, >= tile_vecs)
+};
+
+// Dynamic LDS of the fold kernel: skewed position sums (one pad word per vector)
+// overlaid by the epilogue scratch, then the rotator rows when they fit.
+__host__ __device__ constexpr size_t fold_front_bytes(int npos, int spv, int threads) {
+    return ((static_cast<size_t>(npos + npos / spv) * 4 > static_cast<size_t>(threads) * kEpilogueScratch
+                 ? static_cast<size_t>(npos + npos / spv) * 4
+                 : static_cast<size_t>(threads) * kEpilogueScratch) +
+            15) & ~static_cast<size_t>(15);
+}
+__host__ __device__ constexpr size_t fold_lds_bytes(int npos, int spv, int threads, int64_t M) {
+    return fold_front_bytes(npos, spv, threads) + (M <= kLdsTableRows ? static_cast<size_t>(M) * 16 : 0);
+}
+
+// Arguments of the fused unpack-rotate-fold kernel (one launch per pcal_extract).
+struct FoldArgs {
+    const uint4 *data;       // 16-byte aligned start of the full vectors
+    int64_t nvec;            // number of full vectors at data
+    int64_t rows_total;      // ceil(nvec / row_vecs)
+    int64_t rows_per_group;  // rows walked by one workgroup
+    int row_vecs, tile_vecs, col_tiles, pos_cols, npos;
+    int N;                   // tones = bins
+    int nbits;               // 2 or 8
+    int prec;                // enum pcal_precision
+    int int_bins;            // f_offset == 0: also keep exact int64 bins
+    int64_t Sp;              // fold period S' (samples)
+    int64_t M;               // S' / N rows of the factorised rotator table
+    int64_t q0;              // period coordinate (global index mod S') of data[0], sample 0
+    const double2 *u64;      // u[m] = exp(-j w_o N m), m < M  (FP64)
+    const float2 *u32;       // same, rounded to FP32
+    const __half2 *u16;      // same, rounded to FP16
+    const double2 *v;        // v[b] = exp(-j w_o b), b < N  (FP64)
+    // Samples outside the full vectors (misaligned head, short tail), <= 15 bytes each.
+    const uint8_t *head;
+    int head_bytes;
+    int64_t head_q;          // period coordinate of the first head sample
+    const uint8_t *tail;
+    int tail_bytes;
+    int64_t tail_q;
+    // Integration accumulators of the handle (each workgroup adds its bins atomically).
+    double2 *acc;            // [kAccSlots][N] rotated, folded bins P[b], FP64
+    float2 *accf;            // [kAccSlots][N] the same in FP32 (PREC_F32 form)
+    long long *acc_int;      // [kAccSlots][N] integer bins of Eq. 2 (int_bins only)
+};
+
+// Arguments of the FP64 finalize (DFT, amplitude, phase, delay).
+struct FinArgs {
+    const double2 *acc;      // [kAccSlots][N] bins (FP64 forms)
+    const float2 *accf;      // [kAccSlots][N] bins (FP32 form)
+    const double2 *tw;       // [N] exp(-j 2 pi j / N)
+    int N;
+    int prec;
+    int sideband;
+    double inv_L;            // 1 / samples in the integration (0 if none)
+    int k_lo, k_hi;          // in-band tones [k_lo, k_hi): 0 < f_k < fs/2
+    double f_comb;           // Hz
+    double *out;             // [4N + 1]: amp, phase, re, im, delay
+    unsigned *counter;
+};
+
+void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds, hipStream_t s);
+void launch_finalize(const FinArgs &a, hipStream_t s);
+void launch_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace pcal

@@ -1,0 +1,619 @@
+// gfx950 kernels of libpcal: fused unpack -> rotate -> fold with a two-level
+// cross-workgroup reduction, and the FP64 finalize (N-point DFT, amplitude,
+// phase, delay).
+//
+// Period fold.  With R = fs / gcd(fs, f_offset) the rotator exp(-j w_o n) of
+// Eq. 3 repeats every R samples (Eq. 4) and the fold index n mod N (Eq. 2)
+// every N, so both repeat every S' (a multiple of lcm(N, R) and of the samples
+// in one 16-byte load).  The sum over the stream of x[n] * rot[n] into bin
+// n mod N therefore equals, by distributivity, first summing the integer
+// samples that share a period position q = n mod S' and then rotating each of
+// the S' position sums once -- the "N_rotator-sample accumulator folded
+// outside the sample loop" of Section 4.1, carried to its end.  The rotator
+// is factorised as rot[q] = u[q / N] * v[q mod N] with u[m] = exp(-j w_o N m)
+// and v[b] = exp(-j w_o b); a workgroup applies u to its position sums and
+// folds them to N bins, and v is applied once per bin in the final reduction.
+//
+// Each thread owns one column of the row view of the stream (rows are a
+// multiple of S' long), so it meets the same period positions on every row
+// and sums the 2-bit codes (or biased 8-bit values) of its 64 (16) positions
+// in SWAR lanes of ordinary registers: the inner loop is a few integer
+// operations per 32-bit word, well under the HBM time of the data it reads.
+#include "pcal_internal.h"
+
+namespace pcal {
+
+namespace {
+
+constexpr uint32_t kM33 = 0x33333333u;
+constexpr uint32_t kM0F = 0x0F0F0F0Fu;
+constexpr uint32_t kM00FF = 0x00FF00FFu;
+// Finalize keeps the twiddles in LDS up to this many tones (bins + twiddles + 4 KiB <= 64 KiB).
+constexpr int kTwLdsMaxTones = 1792;
+
+// The packed stream is read once: non-temporal 16-byte loads keep it from
+// displacing reusable lines in the caches.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 load_stream(const uint4 *p) {
+    const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ int level_of(const uint8_t *p, int nbits, int i) {
+    if (nbits == 2) return 2 * ((p[i >> 2] >> (2 * (i & 3))) & 3) - 3;
+    return static_cast<int>(static_cast<int8_t>(p[i]));
+}
+
+// True in every thread of the workgroup that finishes last (all workgroups
+// call it once, after their global stores).  Self-resetting counter.
+__device__ __forceinline__ bool last_workgroup_done(unsigned *counter) {
+    __shared__ unsigned s_last;
+    // every wave's global stores are complete (acknowledged by L2) before the
+    // barrier, so the single write-back below covers the whole workgroup
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool last = prev == gridDim.x * gridDim.y * gridDim.z - 1;
+        if (last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_last = last ? 1u : 0u;
+    }
+    __syncthreads();
+    return s_last != 0u;
+}
+
+// ---------------------------------------------------------------- 2-bit rows
+
+// Spread the two nibble-lane sums of one 32-bit word into the four byte-lane
+// code sums.  lo holds codes q=0 (even nibbles) and q=2 (odd nibbles) of each
+// byte, hi holds q=1 and q=3.
+__device__ __forceinline__ void nibbles_to_bytes(uint32_t lo, uint32_t hi, uint32_t (&bq)[4]) {
+    bq[0] += lo & kM0F;
+    bq[2] += (lo >> 4) & kM0F;
+    bq[1] += hi & kM0F;
+    bq[3] += (hi >> 4) & kM0F;
+}
+
+// Add the byte-lane code sums of a thread to the workgroup's position sums as
+// levels: sum of (2c - 3) over cnt rows = 2 * sum(c) - 3 * cnt.
+__device__ __forceinline__ void flush2(uint32_t (&bq)[4][4], int cnt, int *Fp) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int s = 16 * w + 4 * j + q;
+                const int val = 2 * static_cast<int>((bq[w][q] >> (8 * j)) & 0xFFu) - 3 * cnt;
+                atomicAdd(&Fp[s], val);
+                bq[w][q] = (j == 3) ? 0u : bq[w][q];
+            }
+}
+
+__device__ __forceinline__ void add_codes(uint4 x, uint32_t (&lo)[4], uint32_t (&hi)[4]) {
+    lo[0] += x.x & kM33;
+    hi[0] += (x.x >> 2) & kM33;
+    lo[1] += x.y & kM33;
+    hi[1] += (x.y >> 2) & kM33;
+    lo[2] += x.z & kM33;
+    hi[2] += (x.z >> 2) & kM33;
+    lo[3] += x.w & kM33;
+    hi[3] += (x.w >> 2) & kM33;
+}
+
+// Walk rows [r0, r1) of column colr, 2-bit samples.  Nibble lanes take five
+// rows of codes (max 15), byte lanes seventeen nibble flushes (max 255).
+__device__ void walk2(const FoldArgs &a, int colr, int64_t r0, int64_t r1, int *Fp) {
+    const uint4 *__restrict__ col = a.data + colr;
+    const int64_t stride = a.row_vecs;
+    const int64_t rfull = a.nvec / stride;
+    const bool last_ok = colr < a.nvec - rfull * stride;
+    const int64_t rend_fast = r1 < rfull ? r1 : rfull;  // rows with every column present
+    uint32_t bq[4][4] = {};
+    int cnt = 0, groups = 0;
+    int64_t r = r0;
+    for (; r + 5 <= rend_fast; r += 5) {
+        uint4 x[5];
+#pragma unroll
+        for (int u = 0; u < 5; ++u) x[u] = load_stream(col + (r + u) * stride);
+        uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int u = 0; u < 5; ++u) add_codes(x[u], lo, hi);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) nibbles_to_bytes(lo[w], hi[w], bq[w]);
+        cnt += 5;
+        if (++groups == 17) {
+            flush2(bq, cnt, Fp);
+            cnt = 0;
+            groups = 0;
+        }
+    }
+    // remaining rows, one at a time (at most 4 full rows plus a partial one)
+    uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
+    int nib = 0;
+    for (; r < r1; ++r) {
+        const bool ok = r < rfull || (r == rfull && last_ok);
+        if (ok) {
+            add_codes(load_stream(col + r * stride), lo, hi);
+            ++cnt;
+            ++nib;
+        }
+    }
+    if (nib) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) nibbles_to_bytes(lo[w], hi[w], bq[w]);
+    }
+    if (cnt) flush2(bq, cnt, Fp);
+}
+
+// ---------------------------------------------------------------- 8-bit rows
+
+// Biased values u = x + 128 (0..255) of bytes 0,2 / 1,3 of each word go to the
+// 16-bit lanes of e / o; 256 rows fit before a lane can overflow.
+__device__ __forceinline__ void add_bytes(uint4 x, uint32_t (&e)[4], uint32_t (&o)[4]) {
+    const uint32_t b0 = x.x ^ 0x80808080u, b1 = x.y ^ 0x80808080u;
+    const uint32_t b2 = x.z ^ 0x80808080u, b3 = x.w ^ 0x80808080u;
+    e[0] += b0 & kM00FF;
+    o[0] += (b0 >> 8) & kM00FF;
+    e[1] += b1 & kM00FF;
+    o[1] += (b1 >> 8) & kM00FF;
+    e[2] += b2 & kM00FF;
+    o[2] += (b2 >> 8) & kM00FF;
+    e[3] += b3 & kM00FF;
+    o[3] += (b3 >> 8) & kM00FF;
+}
+
+__device__ __forceinline__ void flush8(uint32_t (&e)[4], uint32_t (&o)[4], int cnt, int *Fp) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        atomicAdd(&Fp[4 * w + 0], static_cast<int>(e[w] & 0xFFFFu) - 128 * cnt);
+        atomicAdd(&Fp[4 * w + 1], static_cast<int>(o[w] & 0xFFFFu) - 128 * cnt);
+        atomicAdd(&Fp[4 * w + 2], static_cast<int>(e[w] >> 16) - 128 * cnt);
+        atomicAdd(&Fp[4 * w + 3], static_cast<int>(o[w] >> 16) - 128 * cnt);
+        e[w] = 0u;
+        o[w] = 0u;
+    }
+}
+
+__device__ void walk8(const FoldArgs &a, int colr, int64_t r0, int64_t r1, int *Fp) {
+    const uint4 *__restrict__ col = a.data + colr;
+    const int64_t stride = a.row_vecs;
+    const int64_t rfull = a.nvec / stride;
+    const bool last_ok = colr < a.nvec - rfull * stride;
+    const int64_t rend_fast = r1 < rfull ? r1 : rfull;
+    uint32_t e[4] = {0u, 0u, 0u, 0u}, o[4] = {0u, 0u, 0u, 0u};
+    int cnt = 0;
+    int64_t r = r0;
+    for (; r + 8 <= rend_fast; r += 8) {
+        uint4 x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = load_stream(col + (r + u) * stride);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) add_bytes(x[u], e, o);
+        cnt += 8;
+        if (cnt == 256) {
+            flush8(e, o, cnt, Fp);
+            cnt = 0;
+        }
+    }
+    for (; r < r1; ++r) {
+        const bool ok = r < rfull || (r == rfull && last_ok);
+        if (ok) {
+            add_bytes(load_stream(col + r * stride), e, o);
+            if (++cnt == 256) {
+                flush8(e, o, cnt, Fp);
+                cnt = 0;
+            }
+        }
+    }
+    if (cnt) flush8(e, o, cnt, Fp);
+}
+
+// ---------------------------------------------------------------- per-workgroup bins
+
+// A partial bin sum in the arithmetic of one precision form (enum pcal_precision):
+//   0 (F64):   FP64 table, FP64 products and sums;
+//   1 (MIXED): FP16 table (held as FP32), FP32 products, Kahan-compensated FP32 sums;
+//   2 (F32):   FP32 table, plain FP32 products and sums.
+// si carries the exact integer sum (the Eq. 2 bin when f_offset = 0).
+template <int PREC>
+struct BinAcc;
+
+template <>
+struct BinAcc<0> {
+    using Tab = double2;
+    double re = 0.0, im = 0.0;
+    long long si = 0;
+    __device__ __forceinline__ void add(int f, Tab u) {
+        re += f * u.x;
+        im += f * u.y;
+        si += f;
+    }
+    __device__ __forceinline__ void merge(const BinAcc &o) {
+        re += o.re;
+        im += o.im;
+        si += o.si;
+    }
+    __device__ __forceinline__ double2 value() const { return make_double2(re, im); }
+};
+
+template <>
+struct BinAcc<1> {
+    using Tab = float2;
+    float sr = 0.f, cr = 0.f, sm = 0.f, cm = 0.f;
+    long long si = 0;
+    __device__ __forceinline__ void kahan(float y, float &s, float &c) {
+        const float yc = y - c;
+        const float t = s + yc;
+        c = (t - s) - yc;
+        s = t;
+    }
+    __device__ __forceinline__ void add(int f, Tab u) {
+        kahan(static_cast<float>(f) * u.x, sr, cr);
+        kahan(static_cast<float>(f) * u.y, sm, cm);
+        si += f;
+    }
+    __device__ __forceinline__ void merge(const BinAcc &o) {
+        kahan(o.sr - o.cr, sr, cr);
+        kahan(o.sm - o.cm, sm, cm);
+        si += o.si;
+    }
+    __device__ __forceinline__ double2 value() const {
+        return make_double2(static_cast<double>(sr) - static_cast<double>(cr),
+                            static_cast<double>(sm) - static_cast<double>(cm));
+    }
+};
+
+template <>
+struct BinAcc<2> {
+    using Tab = float2;
+    float sr = 0.f, sm = 0.f;
+    long long si = 0;
+    __device__ __forceinline__ void add(int f, Tab u) {
+        sr += static_cast<float>(f) * u.x;
+        sm += static_cast<float>(f) * u.y;
+        si += f;
+    }
+    __device__ __forceinline__ void merge(const BinAcc &o) {
+        sr += o.sr;
+        sm += o.sm;
+        si += o.si;
+    }
+    __device__ __forceinline__ double2 value() const { return make_double2(sr, sm); }
+};
+
+template <int PREC>
+__device__ __forceinline__ typename BinAcc<PREC>::Tab table_row(const FoldArgs &a, int m) {
+    if constexpr (PREC == 0)
+        return a.u64[m];
+    else if constexpr (PREC == 1)
+        return __half22float2(a.u16[m]);
+    else
+        return a.u32[m];
+}
+
+// Add one workgroup's bin b (before v) to the integration accumulators:
+// acc[slot][b] += v[b] * Q  (FP64 atomics; FP32 atomics into accf in the F32
+// form), acc_int[slot][b] += exact integer sum.  Workgroups spread over
+// kAccSlots copies of the bins so that few atomics meet on one address; the
+// finalize adds the slots.
+template <int PREC>
+__device__ __forceinline__ void commit_bin(const FoldArgs &a, int b, const BinAcc<PREC> &q, double2 v) {
+    const double2 Q = q.value();
+    const size_t k = static_cast<size_t>(blockIdx.x % kAccSlots) * a.N + b;
+    if constexpr (PREC == 2) {
+        const float qr = static_cast<float>(Q.x), qi = static_cast<float>(Q.y);
+        const float vr = static_cast<float>(v.x), vi = static_cast<float>(v.y);
+        unsafeAtomicAdd(&a.accf[k].x, qr * vr - qi * vi);
+        unsafeAtomicAdd(&a.accf[k].y, qr * vi + qi * vr);
+    } else {
+        unsafeAtomicAdd(&a.acc[k].x, Q.x * v.x - Q.y * v.y);
+        unsafeAtomicAdd(&a.acc[k].y, Q.x * v.y + Q.y * v.x);
+    }
+    if (a.int_bins)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&a.acc_int[k]), static_cast<unsigned long long>(q.si));
+}
+
+// Samples of the misaligned head and short tail of bin b (workgroup 0 only).
+template <int PREC, typename Tab>
+__device__ void add_edges(const FoldArgs &a, int b, BinAcc<PREC> &q, const Tab *UL, bool u_lds) {
+    for (int part = 0; part < 2; ++part) {
+        const uint8_t *src = part ? a.tail : a.head;
+        const int ns = (part ? a.tail_bytes : a.head_bytes) * (8 / a.nbits);
+        int64_t qq = part ? a.tail_q : a.head_q;
+        int qb = static_cast<int>(qq % a.N);
+        for (int i = 0; i < ns; ++i) {
+            if (qb == b) {
+                const int m = static_cast<int>(qq / a.N);
+                q.add(level_of(src, a.nbits, i), u_lds ? UL[m] : table_row<PREC>(a, m));
+            }
+            if (++qq == a.Sp) qq = 0;
+            if (++qb == a.N) qb = 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- the fused kernel
+
+template <int NBITS, int PREC>
+__global__ void __launch_bounds__(kMaxFoldThreads) fold_kernel(FoldArgs a) {
+    using Acc = BinAcc<PREC>;
+    using Tab = typename Acc::Tab;
+    static_assert(sizeof(Acc) <= kEpilogueScratch, "epilogue scratch");
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr int SPV = NBITS == 2 ? 64 : 16;
+    constexpr int kPre = 4;  // rotator rows prefetched per thread
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int npos_sk = a.npos + a.npos / SPV;
+    int *F = reinterpret_cast<int *>(lds);
+    Tab *UL = reinterpret_cast<Tab *>(lds + fold_front_bytes(a.npos, SPV, nt));
+    const bool u_lds = a.M <= kLdsTableRows;
+    const int M = static_cast<int>(a.M);
+
+    // v[b] of the bin this thread commits (group form), loaded now.
+    const double2 vb = (a.N < nt && t < a.N) ? a.v[t] : make_double2(0.0, 0.0);
+    // Rotator rows: loads issued now, stored to LDS after the walk.
+    Tab upre[kPre];
+#pragma unroll
+    for (int j = 0; j < kPre; ++j)
+        if (u_lds && t + j * nt < M) upre[j] = table_row<PREC>(a, t + j * nt);
+    for (int i = t; i < npos_sk; i += nt) F[i] = 0;
+    __syncthreads();
+
+    const int c = static_cast<int>(blockIdx.x % a.col_tiles);
+    const int64_t g = blockIdx.x / a.col_tiles;
+    const int colr = c * a.tile_vecs + t;
+    const int64_t r0 = g * a.rows_per_group;
+    const int64_t r1 = (r0 + a.rows_per_group) < a.rows_total ? (r0 + a.rows_per_group) : a.rows_total;
+    if (t < a.tile_vecs && colr < a.row_vecs && r0 < r1) {
+        int *Fp = F + (t % a.pos_cols) * (SPV + 1);
+        if constexpr (NBITS == 2)
+            walk2(a, colr, r0, r1, Fp);
+        else
+            walk8(a, colr, r0, r1, Fp);
+    }
+    if (u_lds) {
+#pragma unroll
+        for (int j = 0; j < kPre; ++j)
+            if (t + j * nt < M) UL[t + j * nt] = upre[j];
+        for (int i = t + kPre * nt; i < M; i += nt) UL[i] = table_row<PREC>(a, i);
+    }
+    __syncthreads();
+
+    // Rotate this workgroup's position sums by u and fold them onto the N bins.
+    // Local position p has period coordinate (qb + p) mod S', rotator row
+    // ((qb + p) mod S') / N and bin (qb + p) mod N.
+    const int N = a.N;
+    const int Sp = static_cast<int>(a.Sp);
+    const int qb = static_cast<int>((a.q0 + static_cast<int64_t>(c) * a.tile_vecs * SPV) % a.Sp);
+    const int qbN = qb % N;
+    const bool edges = blockIdx.x == 0 && (a.head_bytes > 0 || a.tail_bytes > 0);
+    if (N >= nt) {
+        for (int b = t; b < N; b += nt) {
+            int p = b >= qbN ? b - qbN : b - qbN + N;
+            int q = qb + p;
+            if (q >= Sp) q -= Sp;
+            int m = q / N;
+            Acc acc;
+            for (; p < a.npos; p += N) {
+                acc.add(F[p + p / SPV], u_lds ? UL[m] : table_row<PREC>(a, m));
+                if (++m == M) m = 0;
+            }
+            if (edges) add_edges<PREC>(a, b, acc, UL, u_lds);
+            commit_bin<PREC>(a, b, acc, a.v[b]);
+        }
+    } else {
+        // G groups of N threads split the positions of every bin; the group
+        // partials are merged in group order (deterministic within the workgroup).
+        const int G = nt / N;
+        const int gi = t / N, b = t % N;
+        Acc acc;
+        if (gi < G) {
+            int p = (b >= qbN ? b - qbN : b - qbN + N) + N * gi;
+            int q = qb + p;
+            if (q >= Sp) q -= Sp;
+            int m = q / N;
+            const int step_m = G % M, step_p = N * G;
+#pragma unroll 4
+            for (; p < a.npos; p += step_p) {
+                acc.add(F[p + p / SPV], u_lds ? UL[m] : table_row<PREC>(a, m));
+                m += step_m;
+                if (m >= M) m -= M;
+            }
+        }
+        __syncthreads();  // every read of F is done: reuse its space
+        Acc *scr = reinterpret_cast<Acc *>(lds);
+        if (gi < G) scr[t] = acc;
+        __syncthreads();
+        if (t < N) {
+            Acc tot = scr[b];
+            for (int k = 1; k < G; ++k) tot.merge(scr[k * N + b]);
+            if (edges) add_edges<PREC>(a, b, tot, UL, u_lds);
+            commit_bin<PREC>(a, b, tot, vb);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- finalize
+
+// One 256-thread workgroup per 64 tones: lane -> tone, the four waves split
+// the N-term DFT sum, twiddles indexed exactly by (k*b) mod N.  The last
+// workgroup unwraps the in-band phases (prefix sum of wrapped differences)
+// and fits the delay by least squares.
+__global__ void __launch_bounds__(256) finalize_kernel(FinArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int N = a.N, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double2 *P = reinterpret_cast<double2 *>(lds);
+    const bool tw_lds = N <= kTwLdsMaxTones;
+    double2 *TW = tw_lds ? P + N : nullptr;
+    double2 *red = P + (tw_lds ? 2 * N : N);
+    const bool f32 = a.prec == 2;
+    for (int i = t; i < N; i += 256) {
+        // add the accumulator slots in slot order
+        double re = 0.0, im = 0.0;
+        float fr = 0.f, fi = 0.f;
+        for (int k = 0; k < kAccSlots; ++k) {
+            if (f32) {
+                fr += a.accf[k * N + i].x;
+                fi += a.accf[k * N + i].y;
+            } else {
+                re += a.acc[k * N + i].x;
+                im += a.acc[k * N + i].y;
+            }
+        }
+        P[i] = f32 ? make_double2(fr, fi) : make_double2(re, im);
+        if (tw_lds) TW[i] = a.tw[i];
+    }
+    __syncthreads();
+    const int k = blockIdx.x * 64 + lane;
+    const int qn = (N + 3) / 4;
+    const int bb = wave * qn;
+    const int be = (bb + qn) < N ? (bb + qn) : N;
+    double re = 0.0, im = 0.0;
+    if (k < N && bb < be) {
+        int idx = static_cast<int>((static_cast<int64_t>(k) * bb) % N);
+        if (f32) {
+            float fr = 0.f, fi = 0.f;
+            for (int b = bb; b < be; ++b) {
+                const double2 p = P[b];
+                const double2 w = tw_lds ? TW[idx] : a.tw[idx];
+                const float pr = static_cast<float>(p.x), pi = static_cast<float>(p.y);
+                const float wr = static_cast<float>(w.x), wi = static_cast<float>(w.y);
+                fr += pr * wr - pi * wi;
+                fi += pr * wi + pi * wr;
+                idx += k;
+                if (idx >= N) idx -= N;
+            }
+            re = fr;
+            im = fi;
+        } else {
+            for (int b = bb; b < be; ++b) {
+                const double2 p = P[b];
+                const double2 w = tw_lds ? TW[idx] : a.tw[idx];
+                re += p.x * w.x - p.y * w.y;
+                im += p.x * w.y + p.y * w.x;
+                idx += k;
+                if (idx >= N) idx -= N;
+            }
+        }
+    }
+    red[wave * 64 + lane] = make_double2(re, im);
+    __syncthreads();
+    if (wave == 0 && k < N) {
+        double cr = 0.0, ci = 0.0;
+        float fr = 0.f, fi = 0.f;
+        for (int w = 0; w < 4; ++w) {
+            const double2 p = red[w * 64 + lane];
+            if (f32) {
+                fr += static_cast<float>(p.x);
+                fi += static_cast<float>(p.y);
+            } else {
+                cr += p.x;
+                ci += p.y;
+            }
+        }
+        if (f32) {
+            cr = fr;
+            ci = fi;
+        }
+        if (a.sideband < 0) ci = -ci;
+        a.out[k] = sqrt(cr * cr + ci * ci) * a.inv_L;
+        a.out[N + k] = atan2(ci, cr);
+        a.out[2 * N + k] = cr;
+        a.out[3 * N + k] = ci;
+    }
+
+    if (!last_workgroup_done(a.counter)) return;
+
+    // Delay: unwrap phases over tones [k_lo, k_hi) and fit phase = a + 2 pi t_d f.
+    const int n = a.k_hi - a.k_lo;
+    double *sh = reinterpret_cast<double *>(lds);  // reuse: [256] segment sums, [256] products
+    const double *ph = a.out + N + a.k_lo;
+    const int seg = (n + 255) / 256;
+    const int s0 = t * seg;
+    const int s1 = (s0 + seg) < n ? (s0 + seg) : n;
+    const double two_pi = 6.283185307179586476925286766559;
+    double dsum = 0.0;
+    for (int i = s0; i < s1; ++i) {
+        if (i == 0) continue;
+        const double d = ph[i] - ph[i - 1];
+        dsum += d - two_pi * rint(d / two_pi);
+    }
+    sh[t] = dsum;
+    __syncthreads();
+    if (t == 0) {  // exclusive prefix of segment sums, in order
+        double run = 0.0;
+        for (int i = 0; i < 256; ++i) {
+            const double v = sh[i];
+            sh[i] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    const double kbar = 0.5 * static_cast<double>(n - 1);
+    double unw = (n > 0 ? ph[0] : 0.0) + sh[t];
+    double sxu = 0.0;
+    for (int i = s0; i < s1; ++i) {
+        if (i > 0) {
+            const double d = ph[i] - ph[i - 1];
+            unw += d - two_pi * rint(d / two_pi);
+        }
+        sxu += (static_cast<double>(i) - kbar) * unw;
+    }
+    __syncthreads();
+    sh[t] = sxu;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        double delay = 0.0;
+        if (n >= 2) {
+            const double dn = static_cast<double>(n);
+            const double sxx = dn * (dn * dn - 1.0) / 12.0;
+            delay = sh[0] / sxx / a.f_comb / two_pi;
+        }
+        a.out[4 * N] = delay;
+    }
+}
+
+__global__ void zero_kernel(uint32_t *p, size_t n) {
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        p[i] = 0u;
+}
+
+}  // namespace
+
+void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds, hipStream_t s) {
+    const dim3 gd(grid), bd(threads);
+    if (nbits == 2) {
+        if (a.prec == 0) hipLaunchKernelGGL((fold_kernel<2, 0>), gd, bd, lds, s, a);
+        else if (a.prec == 1) hipLaunchKernelGGL((fold_kernel<2, 1>), gd, bd, lds, s, a);
+        else hipLaunchKernelGGL((fold_kernel<2, 2>), gd, bd, lds, s, a);
+    } else {
+        if (a.prec == 0) hipLaunchKernelGGL((fold_kernel<8, 0>), gd, bd, lds, s, a);
+        else if (a.prec == 1) hipLaunchKernelGGL((fold_kernel<8, 1>), gd, bd, lds, s, a);
+        else hipLaunchKernelGGL((fold_kernel<8, 2>), gd, bd, lds, s, a);
+    }
+}
+
+void launch_finalize(const FinArgs &a, hipStream_t s) {
+    const int grid = (a.N + 63) / 64;
+    const size_t lds = sizeof(double2) * ((a.N <= kTwLdsMaxTones ? 2 * a.N : a.N) + 256);
+    hipLaunchKernelGGL(finalize_kernel, dim3(grid), dim3(256), lds, s, a);
+}
+
+void launch_zero(void *p, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 4;
+    const int grid = static_cast<int>((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+    hipLaunchKernelGGL(zero_kernel, dim3(grid > 0 ? grid : 1), dim3(256), 0, s,
+                       static_cast<uint32_t *>(p), n);
+}
+
+}  // namespace pcal

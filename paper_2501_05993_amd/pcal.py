@@ -1,0 +1,210 @@
+"""ctypes binding of libpcal (include/pcal.h): argument marshalling only.
+
+Every step of the extraction runs in the library's HIP kernels; this module
+passes device pointers, sizes and stream handles through.  PyTorch provides
+device memory and streams.  torch is imported before the library is loaded
+so that libpcal resolves ``libamdhip64.so.7`` to the HIP runtime torch already
+loaded (one runtime per process: torch's stream handles are valid in it).
+
+There is no CPU fallback: if ``libpcal.so`` is missing, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading libpcal, see module docstring)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcal.so")
+
+OK, EINVAL, ENOMEM, EHIP, EAGAIN, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+METHOD_AUTO, METHOD_PERIOD_FOLD, METHOD_LUT, METHOD_OSC = 0, 1, 2, 3
+PREC_F64, PREC_MIXED, PREC_F32 = 0, 1, 2
+
+_i64 = ctypes.c_int64
+
+
+class Info(ctypes.Structure):
+    _fields_ = [(n, _i64) for n in (
+        "ntones", "rotator_period", "joint_period", "fold_period", "method", "precision",
+        "samples_total", "samples_integ", "block_threads", "row_vectors", "col_tiles",
+        "lds_positions", "device_bytes")]
+
+    def as_dict(self) -> dict:
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [(n, _i64) for n in (
+        "grid", "threads", "lds_bytes", "head_bytes", "nvec", "tail_bytes", "rows_total",
+        "rows_per_group", "q0", "head_q", "tail_q")]
+
+    def as_dict(self) -> dict:
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class PcalError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s failed: %s (%d)%s" % (what, strerror(code), code,
+                                                   (" -- " + last_error()) if code == EHIP else ""))
+
+
+_lib = None
+
+_SIGS = {
+    "pcal_create": ([_i64, _i64, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "pcal_create_ex": ([_i64, _i64, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                        ctypes.c_void_p], ctypes.c_int),
+    "pcal_extract": ([ctypes.c_void_p, ctypes.c_void_p, _i64, ctypes.c_void_p], ctypes.c_int),
+    "pcal_results": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "pcal_spectrum": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "pcal_bins": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "pcal_reset": ([ctypes.c_void_p], ctypes.c_int),
+    "pcal_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "pcal_num_tones": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "pcal_info": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "pcal_plan": ([_i64, _i64, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p],
+                  ctypes.c_int),
+    "pcal_plan_launch": ([_i64, _i64, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _i64,
+                          _i64, ctypes.c_void_p], ctypes.c_int),
+    "pcal_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "pcal_last_error": ([], ctypes.c_char_p),
+}
+
+
+def lib():
+    """The loaded libpcal (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpcal.so is not built (%s); run paper_2501_05993_amd/build.py" % LIB_PATH)
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(l, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = l
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().pcal_strerror(code).decode()
+
+
+def last_error() -> str:
+    return lib().pcal_last_error().decode()
+
+
+def _check(code: int, what: str) -> None:
+    if code != OK:
+        raise PcalError(code, what)
+
+
+def plan(fs: int, f_comb: int, f_offset: int, nbits: int, method: int = METHOD_AUTO,
+         precision: int = PREC_F64) -> dict:
+    info = Info()
+    _check(lib().pcal_plan(fs, f_comb, f_offset, nbits, method, precision, ctypes.byref(info)), "pcal_plan")
+    return info.as_dict()
+
+
+def plan_launch(fs: int, f_comb: int, f_offset: int, nbits: int, nsamples: int, addr_low: int = 0,
+                samples_before: int = 0, method: int = METHOD_AUTO, precision: int = PREC_F64) -> dict:
+    out = Launch()
+    _check(lib().pcal_plan_launch(fs, f_comb, f_offset, nbits, method, precision, addr_low, samples_before,
+                                  nsamples, ctypes.byref(out)), "pcal_plan_launch")
+    return out.as_dict()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class PCal:
+    """One stream's extraction state (a pcal_t handle)."""
+
+    def __init__(self, fs: int, f_comb: int, f_offset: int, nbits: int, sideband: int = 1,
+                 method: int = METHOD_AUTO, precision: int = PREC_F64):
+        self._h = ctypes.c_void_p()
+        _check(lib().pcal_create_ex(fs, f_comb, f_offset, nbits, sideband, method, precision,
+                                    ctypes.byref(self._h)), "pcal_create")
+        self.fs, self.f_comb, self.f_offset, self.nbits, self.sideband = fs, f_comb, f_offset, nbits, sideband
+        self.ntones = fs // f_comb
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def extract(self, data, nsamples: Optional[int] = None, stream=None, byte_offset: int = 0) -> None:
+        """Enqueue packed samples held in a device tensor (or at a raw device address)."""
+        if isinstance(data, torch.Tensor):
+            if not data.is_cuda:
+                raise ValueError("extract needs device memory")
+            if not data.is_contiguous():
+                raise ValueError("extract needs a contiguous tensor")
+            ptr = data.data_ptr() + byte_offset
+            avail = data.numel() * data.element_size() - byte_offset
+            if nsamples is None:
+                nsamples = avail * (8 // self.nbits)
+            if nsamples * self.nbits > avail * 8:
+                raise ValueError("tensor holds fewer than nsamples samples")
+        else:
+            ptr = int(data) + byte_offset
+            if nsamples is None:
+                raise ValueError("nsamples is required with a raw pointer")
+        _check(lib().pcal_extract(self._h, ctypes.c_void_p(ptr), nsamples,
+                                  ctypes.c_void_p(_stream_handle(stream))), "pcal_extract")
+
+    def results(self) -> Tuple[np.ndarray, np.ndarray, float]:
+        amp = np.zeros(self.ntones)
+        phase = np.zeros(self.ntones)
+        delay = np.zeros(1)
+        _check(lib().pcal_results(self._h, amp.ctypes.data, phase.ctypes.data, delay.ctypes.data),
+               "pcal_results")
+        return amp, phase, float(delay[0])
+
+    def spectrum(self) -> np.ndarray:
+        re = np.zeros(self.ntones)
+        im = np.zeros(self.ntones)
+        _check(lib().pcal_spectrum(self._h, re.ctypes.data, im.ctypes.data), "pcal_spectrum")
+        return re + 1j * im
+
+    def bins(self, integer: bool = False):
+        re = np.zeros(self.ntones)
+        im = np.zeros(self.ntones)
+        ib = np.zeros(self.ntones, dtype=np.int64) if integer else None
+        _check(lib().pcal_bins(self._h, re.ctypes.data, im.ctypes.data, ib.ctypes.data if integer else None),
+               "pcal_bins")
+        return (re + 1j * im, ib) if integer else re + 1j * im
+
+    def reset(self) -> None:
+        _check(lib().pcal_reset(self._h), "pcal_reset")
+
+    def info(self) -> dict:
+        info = Info()
+        _check(lib().pcal_info(self._h, ctypes.byref(info)), "pcal_info")
+        return info.as_dict()
+
+    def close(self) -> None:
+        if self._h and self._h.value:
+            _check(lib().pcal_destroy(self._h), "pcal_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,77 @@
+"""The C ABI without a GPU: the library loads, exports every symbol include/pcal.h
+declares, plans launches on the host, and rejects invalid parameters before any
+GPU call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests.conftest import ROOT
+
+pcal = pytest.importorskip("paper_2501_05993_amd.pcal")
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pcal.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcal_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = pcal.lib()
+    names = _declared()
+    assert "pcal_create" in names and "pcal_extract" in names and "pcal_results" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_strerror_and_codes():
+    assert pcal.strerror(pcal.OK) == "ok"
+    assert "invalid" in pcal.strerror(pcal.EINVAL)
+    assert pcal.strerror(12345) == "unknown status"
+
+
+@pytest.mark.parametrize("args", [
+    (0, 1_000_000, 0, 2), (64_000_000, 0, 0, 2), (64_000_000, 3_000_000, 0, 2),
+    (64_000_000, 1_000_000, -1, 2), (64_000_000, 1_000_000, 64_000_000, 2),
+    (64_000_000, 1_000_000, 10_000, 4), (64_000_000, 10_000, 0, 2),  # N = 6400 > 4096
+])
+def test_invalid_parameters_rejected_on_host(args):
+    h = ctypes.c_void_p()
+    rc = pcal.lib().pcal_create(*args, 1, ctypes.byref(h))
+    assert rc == pcal.EINVAL and not h.value
+    with pytest.raises(pcal.PcalError):
+        pcal.plan(*args)
+
+
+def test_invalid_sideband_and_null_out():
+    assert pcal.lib().pcal_create(64_000_000, 1_000_000, 0, 2, 0, ctypes.byref(ctypes.c_void_p())) == pcal.EINVAL
+    assert pcal.lib().pcal_create(64_000_000, 1_000_000, 0, 2, 1, None) == pcal.EINVAL
+    assert pcal.lib().pcal_extract(None, None, 0, None) == pcal.EINVAL
+    assert pcal.lib().pcal_results(None, None, None, None) == pcal.EINVAL
+
+
+@pytest.mark.parametrize("fs,fc,fo,nbits,N,R,S", [
+    (16_000_000, 1_000_000, 10_000, 2, 16, 1600, 1600),       # the paper's benchmark workload
+    (32_000_000, 1_000_000, 0, 2, 32, 1, 32),
+    (64_000_000, 1_000_000, 10_000, 2, 64, 6400, 6400),
+    (1_024_000_000, 1_000_000, 510_000, 8, 1024, 102_400, 102_400),
+    (16_000_000, 1_000_000, 250_000, 2, 16, 64, 64),
+    (24_000_000, 1_000_000, 500_000, 8, 24, 48, 48),
+])
+def test_plan_periods(fs, fc, fo, nbits, N, R, S):
+    info = pcal.plan(fs, fc, fo, nbits)
+    assert info["ntones"] == N
+    assert info["rotator_period"] == R          # Eq. 4
+    assert info["joint_period"] == S
+    spv = 64 if nbits == 2 else 16
+    assert info["fold_period"] % S == 0 and info["fold_period"] % spv == 0
+    assert info["method"] == pcal.METHOD_PERIOD_FOLD
+
+
+def test_unsupported_forms_reported():
+    # a prime offset makes the joint period too long for the period fold
+    with pytest.raises(pcal.PcalError) as e:
+        pcal.plan(1_024_000_000, 1_000_000, 10_007, 8, method=pcal.METHOD_PERIOD_FOLD)
+    assert e.value.code == pcal.ENOTSUP

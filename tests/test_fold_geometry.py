@@ -1,0 +1,166 @@
+"""CPU checks of the fused kernel's launch geometry and index arithmetic.
+
+The library's host planner (``pcal_plan`` / ``pcal_plan_launch``, no GPU
+call) fixes how the fold kernel walks the stream.  These tests replay that
+walk on the CPU with the kernel's own index formulas and check that
+
+* every load stays inside the buffer and every 16-byte vector is read by
+  exactly one (workgroup, thread);
+* the period coordinate a thread assumes for its lanes equals the true global
+  sample index modulo the fold period (the premise of the period fold);
+* LDS indices, workgroup sizes and LDS bytes stay within their limits;
+
+and that the replayed arithmetic (integer position sums, rotation by
+u[q / N], fold to bins, v[b], DFT) reproduces the oracle's C_k.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pcal = pytest.importorskip("paper_2501_05993_amd.pcal")
+
+
+def _levels(packed, nbits):
+    b = np.asarray(packed, dtype=np.uint8)
+    if nbits == 2:
+        return (2 * ((b[:, None] >> np.array([0, 2, 4, 6], dtype=np.uint8)) & 3).astype(np.int64) - 3).reshape(-1)
+    return b.view(np.int8).astype(np.int64)
+
+
+def _walk(info, L):
+    """(block, thread, vector index) of every load the fold kernel issues, in the kernel's formulas."""
+    row_vecs, tile_vecs, col_tiles = info["row_vectors"], L["tile_vecs"], info["col_tiles"]
+    out_b, out_t, out_v = [], [], []
+    rfull = L["nvec"] // row_vecs
+    for blk in range(L["grid"]):
+        c = blk % col_tiles
+        g = blk // col_tiles
+        t = np.arange(L["threads"])
+        colr = c * tile_vecs + t
+        act = (t < tile_vecs) & (colr < row_vecs)
+        r0 = g * L["rows_per_group"]
+        r1 = min(r0 + L["rows_per_group"], L["rows_total"])
+        for r in range(r0, r1):
+            ok = act & ((r < rfull) | ((r == rfull) & (colr < L["nvec"] - rfull * row_vecs)))
+            tt = t[ok]
+            out_b.append(np.full(tt.size, blk))
+            out_t.append(tt)
+            out_v.append(r * row_vecs + colr[ok])
+    if not out_v:
+        return np.zeros(0, int), np.zeros(0, int), np.zeros(0, int)
+    return np.concatenate(out_b), np.concatenate(out_t), np.concatenate(out_v)
+
+
+def _geometry(fs, fc, fo, nbits, nsamples, addr_low=0, before=0):
+    info = pcal.plan(fs, fc, fo, nbits)
+    L = pcal.plan_launch(fs, fc, fo, nbits, nsamples, addr_low=addr_low, samples_before=before)
+    spv = 64 if nbits == 2 else 16
+    L["tile_vecs"] = (info["lds_positions"] // spv) if info["col_tiles"] > 1 else info["row_vectors"]
+    L["pos_cols"] = info["lds_positions"] // spv
+    return info, L, spv
+
+
+CASES = [
+    # fs, f_comb, f_offset, nbits, nsamples, addr_low, samples_before
+    (32_000_000, 1_000_000, 0, 2, 4 * 100_003, 0, 0),
+    (64_000_000, 1_000_000, 10_000, 2, 4 * 400_011, 0, 0),
+    (64_000_000, 1_000_000, 10_000, 2, 4 * 300_000, 5, 4 * 777),
+    (1_024_000_000, 1_000_000, 510_000, 8, 1_000_003, 0, 0),
+    (1_024_000_000, 1_000_000, 510_000, 8, 2_000_000, 9, 123_457),
+    (512_000_000, 1_000_000, 10_000, 2, 4 * 250_001, 3, 4 * 51),
+    (16_000_000, 1_000_000, 250_000, 2, 4 * 50_000, 0, 0),
+    (24_000_000, 1_000_000, 500_000, 8, 333_333, 1, 17),
+    (64_000_000, 1_000_000, 10_000, 2, 4 * 9, 3, 0),        # head and tail only
+    (32_000_000, 1_000_000, 0, 8, 7, 2, 5),                  # fewer samples than one vector
+]
+
+
+@pytest.mark.parametrize("fs,fc,fo,nbits,ns,addr,before", CASES)
+def test_walk_bounds_coverage_and_period(fs, fc, fo, nbits, ns, addr, before):
+    info, L, spv = _geometry(fs, fc, fo, nbits, ns, addr, before)
+    spb = 8 // nbits
+    Sp = info["fold_period"]
+    assert L["head_bytes"] + 16 * L["nvec"] + L["tail_bytes"] == ns // spb
+    assert L["head_bytes"] == min((16 - addr % 16) % 16, ns // spb)
+    assert 0 <= L["tail_bytes"] < 16
+    assert L["threads"] % 64 == 0 and L["threads"] <= 1024
+    assert L["threads"] >= L["tile_vecs"]
+    assert L["lds_bytes"] <= 65536
+    assert info["lds_positions"] <= 12288
+    npos_sk = info["lds_positions"] + info["lds_positions"] // spv     # skewed position sums
+    assert L["lds_bytes"] >= 4 * npos_sk and L["lds_bytes"] >= 40 * L["threads"]
+    assert info["row_vectors"] * spv % Sp == 0          # rows are whole fold periods
+    blk, thr, vec = _walk(info, L)
+    # in bounds, each vector exactly once
+    assert vec.size == L["nvec"]
+    if vec.size:
+        assert vec.min() >= 0 and vec.max() < L["nvec"]
+        assert np.unique(vec).size == vec.size
+    # the period coordinate each thread assumes equals the true one
+    g0 = before + L["head_bytes"] * spb
+    c = blk % info["col_tiles"]
+    qb = (L["q0"] + c * L["tile_vecs"] * spv) % Sp
+    assumed = (qb + (thr % L["pos_cols"]) * spv) % Sp
+    true = (g0 + vec * spv) % Sp
+    np.testing.assert_array_equal(assumed, true)
+    assert np.all((thr % L["pos_cols"]) * spv + spv <= info["lds_positions"])
+    assert np.all((thr % L["pos_cols"]) * (spv + 1) + spv - 1 < npos_sk)  # skewed LDS index in range
+    assert L["q0"] == g0 % Sp and L["head_q"] == before % Sp
+    assert L["tail_q"] == (g0 + L["nvec"] * spv) % Sp
+
+
+@pytest.mark.parametrize("fs,fc,fo,nbits,ns", [
+    (64_000_000, 1_000_000, 10_000, 2, 1 << 30),
+    (32_000_000, 1_000_000, 0, 2, 1 << 24),
+    (1_024_000_000, 1_000_000, 510_000, 8, 1 << 28),
+    (512_000_000, 1_000_000, 510_000, 2, 1 << 26),
+    (16_000_000, 1_000_000, 10_000, 2, 1 << 26),
+])
+def test_full_size_launch_limits(fs, fc, fo, nbits, ns):
+    info, L, spv = _geometry(fs, fc, fo, nbits, ns)
+    assert L["grid"] >= 1 and L["rows_per_group"] * (L["grid"] // info["col_tiles"]) >= L["rows_total"]
+    assert (L["grid"] // info["col_tiles"] - 1) * L["rows_per_group"] < L["rows_total"]
+    assert L["threads"] <= 1024 and L["lds_bytes"] <= 65536
+    assert L["nvec"] * 16 + L["head_bytes"] + L["tail_bytes"] == ns * nbits // 8
+
+
+def _emulate(packed, nbits, ns, fs, fc, fo, addr, before):
+    """The fold kernel's arithmetic replayed in numpy FP64 (position sums -> u -> bins -> v -> DFT)."""
+    info, L, spv = _geometry(fs, fc, fo, nbits, ns, addr, before)
+    spb = 8 // nbits
+    N, Sp = fs // fc, info["fold_period"]
+    M = Sp // N
+    x = _levels(packed, nbits)[:ns]
+    nh = L["head_bytes"] * spb
+    u = np.exp(-2j * np.pi * ((fo * N * np.arange(M)) % fs) / fs)
+    v = np.exp(-2j * np.pi * ((fo * np.arange(N)) % fs) / fs)
+    blk, thr, vec = _walk(info, L)
+    Q = np.zeros(N, complex)
+    for b in np.unique(blk):
+        sel = blk == b
+        F = np.zeros(info["lds_positions"], np.int64)
+        for s in range(spv):
+            np.add.at(F, (thr[sel] % L["pos_cols"]) * spv + s, x[nh + vec[sel] * spv + s])
+        c = b % info["col_tiles"]
+        qb = (L["q0"] + c * L["tile_vecs"] * spv) % Sp
+        q = (qb + np.arange(F.size)) % Sp
+        np.add.at(Q, q % N, F * u[q // N])
+    for start, n, q0 in ((0, nh, L["head_q"]), (nh + L["nvec"] * spv, L["tail_bytes"] * spb, L["tail_q"])):
+        q = (q0 + np.arange(n)) % Sp
+        np.add.at(Q, q % N, x[start:start + n] * u[q // N])
+    P = v * Q
+    k = np.arange(N)
+    return np.exp(-2j * np.pi * np.outer(k, k) / N) @ P
+
+
+@pytest.mark.parametrize("fs,fc,fo,nbits,ns,addr,before", [c for c in CASES if c[4] <= 4 * 400_011])
+def test_emulated_arithmetic_matches_oracle(fs, fc, fo, nbits, ns, addr, before):
+    spec = synth.CombSpec(fs, fc, fo, nbits, amp=0.3 if nbits == 2 else 4.0, t_d=5e-9,
+                          sigma=1.0 if nbits == 2 else 20.0, seed=(77, ns))
+    packed = synth.make_stream(spec, ns + (-ns) % (8 // nbits))
+    got = _emulate(packed, nbits, ns, fs, fc, fo, addr, before)
+    want = oracle.correlate(packed, nbits, ns, fs, fc, fo, n0=before)
+    scale = max(1.0, np.abs(want).max())
+    assert np.max(np.abs(got - want)) <= 1e-9 * scale

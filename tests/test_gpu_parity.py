@@ -1,0 +1,263 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, on the GPU.
+
+Inputs are seeded synthetic streams with the shapes of the evaluation
+workloads.  Small sizes are compared tone by tone against the full oracle;
+full sizes, in the launch configuration the benchmark times, are compared on
+a sample of tones the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import F64_RTOL, assert_spectra, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_05993_amd import pcal
+
+    pcal.lib()
+    return pcal
+
+
+def _dev(packed):
+    return torch.from_numpy(np.ascontiguousarray(packed)).cuda()
+
+
+def _run(pc, spec, dev, nsamples=None, prec=0, sideband=1, chunks=None):
+    h = pc.PCal(spec.fs, spec.f_comb, spec.f_offset, spec.nbits, sideband=sideband, precision=prec)
+    spb = 8 // spec.nbits
+    ns = nsamples if nsamples is not None else dev.numel() * spb
+    if chunks is None:
+        h.extract(dev, ns)
+    else:
+        pos = 0
+        for c in chunks:
+            h.extract(dev, c, byte_offset=pos // spb)
+            pos += c
+        assert pos == ns
+    C = h.spectrum()
+    res = h.results()
+    ib = h.bins(integer=True)[1] if spec.f_offset == 0 else None
+    h.close()
+    return C, res, ib
+
+
+# ------------------------------------------------------------------ small 2-bit, f_offset = 0 (bit-exact)
+
+def test_small_2bit_f0_bit_exact(pc):
+    w = synth.WORKLOADS["small_2bit_fo0"]
+    spec, L = w["spec"], w["nsamples"]
+    say("small_2bit_fo0 L=%d" % L)
+    packed = synth.make_stream(spec, L)
+    C, (amp, ph, delay), ib = _run(pc, spec, _dev(packed))
+    want_bins = oracle.fold_int(packed, 2, L, spec.ntones)
+    np.testing.assert_array_equal(ib, want_bins)
+    Co = oracle.correlate(packed, 2, L, spec.fs, spec.f_comb, spec.f_offset)
+    assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6, what="small_2bit_fo0")
+    ao, po, do = oracle.results(Co, L, spec.fs, spec.f_comb, spec.f_offset)
+    np.testing.assert_allclose(amp, ao, rtol=1e-10, atol=1e-12)
+    k = oracle.in_band(spec.fs, spec.f_comb, spec.f_offset)
+    assert np.max(np.abs(np.angle(np.exp(1j * (ph[k] - po[k]))))) < 1e-9
+    assert abs(delay - do) < 1e-15
+
+
+# ------------------------------------------------------------------ rotated 2-bit, several tiles + ragged tail
+
+@pytest.mark.parametrize("L,offset", [(4 * 1_000_003, 0), (4 * 777_777, 3), (1 << 22, 8)])
+def test_rotated_2bit_small(pc, L, offset):
+    spec = synth.WORKLOADS["fold2_64M_10k"]["spec"]
+    say("fold2_64M_10k L=%d offset=%d" % (L, offset))
+    packed = synth.make_stream(spec, L)
+    buf = np.zeros(packed.size + 16, np.uint8)
+    buf[offset:offset + packed.size] = packed
+    dev = _dev(buf)
+    h = pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2)
+    h.extract(dev, L, byte_offset=offset)
+    C = h.spectrum()
+    amp, ph, delay = h.results()
+    h.close()
+    Co = oracle.correlate(packed, 2, L, spec.fs, spec.f_comb, spec.f_offset)
+    assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="fold2 small")
+    ao, po, do = oracle.results(Co, L, spec.fs, spec.f_comb, spec.f_offset)
+    np.testing.assert_allclose(amp, ao, rtol=1e-9)
+    assert abs(delay - do) < 1e-13
+
+
+# ------------------------------------------------------------------ full size, benchmark launch configuration
+
+def test_fold2_full_size_sampled(pc):
+    w = synth.WORKLOADS["fold2_64M_10k"]
+    spec, L = w["spec"], w["nsamples"]
+    say("fold2_64M_10k full L=%d" % L)
+    dev = synth.make_stream_device(spec, L)
+    h = pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2)
+    h.extract(dev, L)
+    C = h.spectrum()
+    h.close()
+    host = dev.cpu().numpy()
+    tones = [0, 1, 2, 17, 31, 32, 45, 63]
+    Co = oracle.correlate(host, 2, L, spec.fs, spec.f_comb, spec.f_offset, tones=tones)
+    assert_spectra(C[tones], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="fold2 full (sampled tones)")
+
+
+# ------------------------------------------------------------------ 8-bit, N = 1024, column tiles, chunk boundary
+
+def test_wide8_chunks_sampled(pc):
+    w = synth.WORKLOADS["wide8_1024M_510k"]
+    spec = w["spec"]
+    chunk = 1 << 24
+    L = 2 * chunk
+    say("wide8_1024M_510k two chunks of %d" % chunk)
+    dev = synth.make_stream_device(spec, L)
+    h = pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 8)
+    h.extract(dev[:chunk], chunk)
+    h.extract(dev[chunk:], chunk)
+    C = h.spectrum()
+    amp, ph, delay = h.results()
+    h.close()
+    host = dev.cpu().numpy()
+    tones = [0, 1, 100, 255, 511, 512, 777, 1023]
+    Co = oracle.correlate(host, 8, L, spec.fs, spec.f_comb, spec.f_offset, tones=tones)
+    assert_spectra(C[tones], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="wide8 (sampled tones)")
+
+
+def test_wide8_small_all_tones(pc):
+    spec = synth.WORKLOADS["wide8_1024M_510k"]["spec"]
+    L = 3 * 102_400 + 4093
+    say("wide8 small L=%d" % L)
+    packed = synth.make_stream(spec, L)
+    C, (amp, ph, delay), _ = _run(pc, spec, _dev(packed))
+    Co = oracle.correlate(packed, 8, L, spec.fs, spec.f_comb, spec.f_offset)
+    assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="wide8 small")
+    ao, po, do = oracle.results(Co, L, spec.fs, spec.f_comb, spec.f_offset)
+    np.testing.assert_allclose(amp, ao, rtol=1e-9)
+    assert abs(delay - do) < 1e-12
+
+
+# ------------------------------------------------------------------ stream mix of the precision study (all tones)
+
+@pytest.mark.parametrize("s", range(0, 64, 9))
+def test_batch_mix_streams(pc, s):
+    spec = synth.batch_specs()[s]
+    L = 1 << 20
+    say("batch mix stream %d fs=%d fo=%d" % (s, spec.fs, spec.f_offset))
+    packed = synth.make_stream(spec, L)
+    C, res, ib = _run(pc, spec, _dev(packed))
+    Co = oracle.correlate(packed, 2, L, spec.fs, spec.f_comb, spec.f_offset)
+    assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6, what="mix %d" % s)
+    if ib is not None:
+        np.testing.assert_array_equal(ib, oracle.fold_int(packed, 2, L, spec.ntones))
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_chunk_split_invariance_integer(pc):
+    """Any split into extract calls (odd sizes, misaligned starts) gives identical integer bins."""
+    spec = synth.WORKLOADS["small_2bit_fo0"]["spec"]
+    L = 4 * 250_001
+    packed = synth.make_stream(spec, L)
+    dev = _dev(packed)
+    _, _, whole = _run(pc, spec, dev, L)
+    _, _, split = _run(pc, spec, dev, L, chunks=[4, 4 * 1001, 60, 4 * 77_777, 4 * 13, L - 4 - 4 * 1001 - 60
+                                                  - 4 * 77_777 - 4 * 13])
+    np.testing.assert_array_equal(whole, split)
+    np.testing.assert_array_equal(whole, oracle.fold_int(packed, 2, L, spec.ntones))
+
+
+def test_chunk_split_rotated(pc):
+    spec = synth.WORKLOADS["fold2_64M_10k"]["spec"]
+    L = 4 * 300_007
+    packed = synth.make_stream(spec, L)
+    dev = _dev(packed)
+    C1, _, _ = _run(pc, spec, dev, L)
+    chunks = [20, 4 * 99_999, 4 * 100_000]
+    chunks.append(L - sum(chunks))
+    C2, _, _ = _run(pc, spec, dev, L, chunks=chunks)
+    Co = oracle.correlate(packed, 2, L, spec.fs, spec.f_comb, spec.f_offset)
+    assert_spectra(C1, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="whole")
+    assert_spectra(C2, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="split")
+
+
+@pytest.mark.parametrize("nbits,L", [(2, 4), (2, 60), (2, 64), (2, 68), (8, 1), (8, 15), (8, 17)])
+def test_tiny_inputs(pc, nbits, L):
+    spec = synth.CombSpec(64_000_000, 1_000_000, 10_000, nbits, amp=0.5, t_d=1e-9,
+                          sigma=1.0 if nbits == 2 else 20.0, seed=(5, L))
+    packed = synth.make_stream(spec, L + (-L) % (8 // nbits))
+    for off in (0, 1, 7):
+        buf = np.zeros(packed.size + 32, np.uint8)
+        buf[off:off + packed.size] = packed
+        h = pc.PCal(spec.fs, spec.f_comb, spec.f_offset, nbits)
+        h.extract(_dev(buf), L, byte_offset=off)
+        C = h.spectrum()
+        h.close()
+        Co = oracle.correlate(packed, nbits, L, spec.fs, spec.f_comb, spec.f_offset)
+        np.testing.assert_allclose(C, Co, rtol=0, atol=1e-9 * max(1.0, np.abs(Co).max()))
+
+
+def test_empty_and_reset(pc):
+    spec = synth.WORKLOADS["fold2_64M_10k"]["spec"]
+    L = 4 * 100_000
+    packed = synth.make_stream(spec, 2 * L)
+    dev = _dev(packed)
+    h = pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2)
+    h.extract(dev, 0)
+    C0 = h.spectrum()
+    assert np.all(C0 == 0)
+    amp, ph, d = h.results()
+    assert np.all(amp == 0) and d == 0.0
+    h.extract(dev, L)
+    h.reset()
+    h.extract(dev[L // 4:], L)          # second integration continues the global index
+    C = h.spectrum()
+    assert h.info()["samples_total"] == 2 * L and h.info()["samples_integ"] == L
+    h.close()
+    Co = oracle.correlate(packed[L // 4:], 2, L, spec.fs, spec.f_comb, spec.f_offset, n0=L)
+    assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="after reset")
+
+
+def test_lower_sideband_conjugates(pc):
+    spec = synth.WORKLOADS["fold2_64M_10k"]["spec"]
+    L = 1 << 20
+    dev = _dev(synth.make_stream(spec, L))
+    Cu, (au, pu, du), _ = _run(pc, spec, dev, L, sideband=1)
+    Cl, (al, pl, dl), _ = _run(pc, spec, dev, L, sideband=-1)
+    # workgroups add their bins with FP64 atomics: the summation order (not the terms) varies
+    np.testing.assert_allclose(Cl, np.conj(Cu), rtol=1e-13, atol=1e-13 * np.abs(Cu).max())
+    np.testing.assert_allclose(al, au, rtol=1e-13)
+    assert dl == pytest.approx(-du, rel=1e-12, abs=1e-20)
+
+
+def test_streams_ordered(pc):
+    """Calls on different streams are ordered after each other (shared accumulators)."""
+    spec = synth.WORKLOADS["fold2_64M_10k"]["spec"]
+    L = 1 << 22
+    packed = synth.make_stream(spec, L)
+    dev = _dev(packed)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    h = pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2)
+    q = L // 4
+    for i in range(4):
+        h.extract(dev[i * q // 4:], q, stream=streams[i % 3])
+    C = h.spectrum()
+    h.close()
+    Co = oracle.correlate(packed, 2, L, spec.fs, spec.f_comb, spec.f_offset)
+    assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="streams")
+
+
+def test_invalid_calls(pc):
+    spec = synth.WORKLOADS["fold2_64M_10k"]["spec"]
+    h = pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2)
+    dev = _dev(np.zeros(64, np.uint8))
+    with pytest.raises(pc.PcalError) as e:
+        h.extract(dev, 6)                 # not a multiple of 4 samples
+    assert e.value.code == pc.EINVAL
+    with pytest.raises(pc.PcalError):
+        h.bins(integer=True)              # integer bins only exist for f_offset = 0
+    h.close()
