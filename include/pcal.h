@@ -177,6 +177,56 @@ int pcal_plan_launch(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int 
                      int precision, uint64_t addr_low, int64_t samples_before, int64_t nsamples,
                      pcal_launch_t *out);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: many streams, one launch.
+ *
+ * A batch owns member handles (each with its own fs, f_offset, sample format,
+ * tables and accumulators, planned for the batch's workgroup size and the
+ * batch's precision form).  pcal_batch_extract folds one chunk for each of
+ * `count` members in a single launch of the fused kernel over a work-list;
+ * pcal_batch_results finalizes `count` members in a single launch and one
+ * device-to-host transfer.  Members are ordinary handles otherwise
+ * (pcal_batch_handle): pcal_extract/pcal_results on them still work.  The
+ * sample index of every member stays global, exactly as for pcal_extract.
+ * ------------------------------------------------------------------------- */
+typedef struct pcal_batch_ctx *pcal_batch_t;
+
+/* Create an empty batch of at most max_streams members; precision is the
+ * enum pcal_precision every member uses. */
+int pcal_batch_create(int max_streams, int precision, pcal_batch_t *out);
+
+/* Add a member stream (parameters as pcal_create; period-fold form).  *id is
+ * its index.  PCAL_EAGAIN when the batch is full, PCAL_ENOTSUP when the
+ * parameters need a per-sample form. */
+int pcal_batch_add(pcal_batch_t b, int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband,
+                   int *id);
+
+/* The member handle with index id (owned by the batch). */
+int pcal_batch_handle(pcal_batch_t b, int id, pcal_t *h);
+
+/* One launch: for i < count, nsamples[i] samples of member ids[i] at
+ * device address dev_ptrs[i] (each id at most once).  Asynchronous on
+ * stream, ordered after each member's previous work. */
+int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *const *dev_ptrs,
+                       const int64_t *nsamples, pcal_stream_t stream);
+
+/* Finalize members ids[0..count): amp and phase receive N_id values per member,
+ * concatenated in the order of ids (either may be NULL); delay[i] per member.
+ * One launch and one transfer; synchronises. */
+int pcal_batch_results(pcal_batch_t b, int count, const int *ids, double *amp, double *phase, double *delay);
+
+/* The C_k of members ids[0..count), concatenated as in pcal_batch_results. */
+int pcal_batch_spectra(pcal_batch_t b, int count, const int *ids, double *re, double *im);
+
+/* Start a new integration for the listed members (one launch). */
+int pcal_batch_reset(pcal_batch_t b, int count, const int *ids);
+
+/* Number of members. */
+int pcal_batch_size(pcal_batch_t b, int *n);
+
+/* Release the batch and its member handles (synchronises). */
+int pcal_batch_destroy(pcal_batch_t b);
+
 /* Text of a status code. */
 const char *pcal_strerror(int code);
 

@@ -10,6 +10,6 @@ its Python binding) never does, and the two share no code.
 * :mod:`oracle.fit` -- amplitude, phase and delay from the C_k (numpy, FP64).
 * :mod:`oracle.params` -- rotator period (Eq. 4) and phase step (Eq. 5).
 """
-from .core import build, correlate, correlate_f64, decode, fold_int, max_threads  # noqa: F401
+from .core import build, correlate, correlate_f64, correlate_rotator, decode, fold_int, max_threads  # noqa: F401
 from .fit import delay_fit, in_band, results, tone_freqs  # noqa: F401
 from .params import ntones, phase_step, rotator_period  # noqa: F401

@@ -32,8 +32,9 @@ def _bind(path: str):
     lib.orc_correlate_f64.argtypes = [p, i64, i64, i64, i64, i64, i32, p, i32, p, p]
     lib.orc_fold_int.argtypes = [p, i32, i64, i64, i64, p]
     lib.orc_decode.argtypes = [p, i32, i64, p]
+    lib.orc_correlate_rotator.argtypes = [p, i32, i64, i64, i64, i64, p, p, p, p, i32, p, i32, p, p]
     for f in (lib.orc_correlate_packed, lib.orc_correlate_f64, lib.orc_fold_int, lib.orc_decode,
-              lib.orc_max_threads):
+              lib.orc_max_threads, lib.orc_correlate_rotator):
         f.restype = ctypes.c_int
     return lib
 
@@ -128,6 +129,31 @@ def correlate_f64(x, fs: int, fc: int, fo: int, n0: int = 0, tones: Optional[Seq
     im = np.zeros(t.size)
     rc = _load().orc_correlate_f64(_ptr(xs), xs.size, n0, fs, fc, fo, t.size, _ptr(t), nthreads,
                                    _ptr(re), _ptr(im))
+    if rc:
+        raise ValueError("oracle rejected the arguments (code %d)" % rc)
+    return re + 1j * im
+
+
+def correlate_rotator(packed, nbits: int, nsamples: int, nbins: int, u, v, n0: int = 0,
+                      tones: Optional[Sequence[int]] = None, nthreads: int = 0) -> np.ndarray:
+    """C_k with the rotator read from tables: U (rows, complex) times V (nbins, complex).
+
+    Equals :func:`correlate` for the exact tables U[m] = exp(-j w_o N m),
+    V[b] = exp(-j w_o b); with rounded tables it is what an extraction that
+    rotates by the rounded values computes in exact arithmetic.
+    """
+    b = _bytes(packed)
+    u = np.asarray(u, dtype=np.complex128)
+    v = np.asarray(v, dtype=np.complex128)
+    if v.size != nbins:
+        raise ValueError("v needs nbins entries")
+    ur, ui = np.ascontiguousarray(u.real), np.ascontiguousarray(u.imag)
+    vr, vi = np.ascontiguousarray(v.real), np.ascontiguousarray(v.imag)
+    t = np.ascontiguousarray(np.asarray(list(range(nbins)) if tones is None else list(tones), dtype=np.int32))
+    re = np.zeros(t.size)
+    im = np.zeros(t.size)
+    rc = _load().orc_correlate_rotator(_ptr(b), nbits, nsamples, n0, nbins, u.size, _ptr(ur), _ptr(ui), _ptr(vr),
+                                       _ptr(vi), t.size, _ptr(t), nthreads, _ptr(re), _ptr(im))
     if rc:
         raise ValueError("oracle rejected the arguments (code %d)" % rc)
     return re + 1j * im

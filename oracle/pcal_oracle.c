@@ -217,6 +217,81 @@ int orc_correlate_f64(const double *samples, int64_t nsamples, int64_t n0, int64
     return orc_correlate(&src, nsamples, n0, fs, fc, fo, ntones, tones, nthreads, re, im);
 }
 
+/* Per-tone correlation with a supplied rotator in place of exp(-j w_o n):
+ *
+ *     C_k = sum_n x[n] * U[m(n)] * V[n mod N] * exp(-j 2 pi k (n mod N) / N),
+ *     m(n) = (n mod (M*N)) div N,
+ *
+ * i.e. Eq. 3 with the rotator read from a table that repeats every M*N
+ * samples and is split into a row factor U (M entries) and a column factor
+ * V (N entries).  With the exact U[m] = exp(-j w_o N m), V[b] = exp(-j w_o b)
+ * this equals the plain C_k above; with rounded tables it is the exact-
+ * arithmetic value of an extraction that rotates by those rounded values
+ * (used to check reduced-precision forms).  Sums as in orc_correlate. */
+int orc_correlate_rotator(const uint8_t *packed, int nbits, int64_t nsamples, int64_t n0, int64_t nbins,
+                          int64_t rows, const double *u_re, const double *u_im, const double *v_re,
+                          const double *v_im, int ntones, const int32_t *tones, int nthreads, double *re,
+                          double *im)
+{
+    if ((!packed && nsamples > 0) || (nbits != 2 && nbits != 8) || nsamples < 0 || n0 < 0 || nbins <= 0 ||
+        rows <= 0 || !u_re || !u_im || !v_re || !v_im || ntones < 0 || (ntones && (!tones || !re || !im)))
+        return ORC_EINVAL;
+    for (int t = 0; t < ntones; t++)
+        if (tones[t] < 0 || tones[t] >= nbins) return ORC_EINVAL;
+    const int64_t period = rows * nbins;
+    double *tw = (double *)malloc(sizeof(double) * 2 * (size_t)nbins);
+    const int64_t nblk = (nsamples + ORC_BLOCK - 1) / ORC_BLOCK;
+    const int64_t ntask = nblk * (int64_t)ntones;
+    double *pre = (double *)malloc(sizeof(double) * (size_t)(ntask > 0 ? ntask : 1));
+    double *pim = (double *)malloc(sizeof(double) * (size_t)(ntask > 0 ? ntask : 1));
+    if (!tw || !pre || !pim) {
+        free(tw);
+        free(pre);
+        free(pim);
+        return ORC_ENOMEM;
+    }
+    for (int64_t j = 0; j < nbins; j++) orc_phasor(j, nbins, &tw[2 * j], &tw[2 * j + 1]);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t task = 0; task < ntask; task++) {
+        const int64_t b = task / ntones;
+        const int t = (int)(task % ntones);
+        const int64_t k = tones[t];
+        const int64_t i0 = b * ORC_BLOCK;
+        const int64_t i1 = (i0 + ORC_BLOCK < nsamples) ? i0 + ORC_BLOCK : nsamples;
+        int64_t q = (n0 + i0) % period; /* position in the rotator period */
+        orc_acc sr = {0.0, 0.0}, si = {0.0, 0.0};
+        for (int64_t i = i0; i < i1; i++) {
+            const int64_t col = q % nbins, row = q / nbins;
+            /* rotator U[row] * V[col], then the tone's twiddle exp(-j 2 pi k col / N) */
+            const double rr = u_re[row] * v_re[col] - u_im[row] * v_im[col];
+            const double ri = u_re[row] * v_im[col] + u_im[row] * v_re[col];
+            const int64_t w = (k * col) % nbins;
+            const double cr = rr * tw[2 * w] - ri * tw[2 * w + 1];
+            const double ci = rr * tw[2 * w + 1] + ri * tw[2 * w];
+            const double x = (double)orc_level(packed, nbits, i);
+            orc_add(&sr, x * cr);
+            orc_add(&si, x * ci);
+            if (++q == period) q = 0;
+        }
+        pre[t * nblk + b] = sr.s + sr.c;
+        pim[t * nblk + b] = si.s + si.c;
+    }
+    for (int t = 0; t < ntones; t++) {
+        re[t] = orc_pairwise(pre + t * nblk, nblk);
+        im[t] = orc_pairwise(pim + t * nblk, nblk);
+    }
+    free(tw);
+    free(pre);
+    free(pim);
+    return ORC_OK;
+}
+
 /* Eq. 2: P[b] = sum of x[n] over n = b (mod N), n = n0 .. n0+nsamples-1, exact in int64. */
 int orc_fold_int(const uint8_t *packed, int nbits, int64_t nsamples, int64_t n0, int64_t nbins,
                  int64_t *bins)

@@ -8,11 +8,10 @@
 #include <algorithm>
 #include <vector>
 
-#include "pcal.h"
-#include "pcal_internal.h"
+#include "pcal_host.h"
 
 namespace pcal {
-namespace {
+namespace host {
 
 thread_local char g_last_error[256] = "";
 
@@ -20,14 +19,6 @@ void set_error(const char *what, hipError_t e) {
     snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
 }
 
-#define PCAL_HIP(call)                      \
-    do {                                    \
-        hipError_t e_ = (call);             \
-        if (e_ != hipSuccess) {             \
-            set_error(#call, e_);           \
-            return PCAL_EHIP;               \
-        }                                   \
-    } while (0)
 
 int64_t gcd64(int64_t a, int64_t b) {
     while (b) {
@@ -64,18 +55,6 @@ int env_int(const char *name, int dflt) {
     return (s && *s) ? atoi(s) : dflt;
 }
 
-struct Plan {
-    int64_t fs, fc, fo;
-    int nbits, sideband, method, prec;
-    int64_t N, R, S, Sp, M;
-    FoldGeom geom;
-    int target_blocks;
-    int max_blocks;
-};
-
-constexpr int64_t kMaxFoldPeriod = int64_t(1) << 26;  // S' samples
-constexpr int64_t kMaxTableRows = int64_t(1) << 20;   // u table entries
-
 int check_params(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband) {
     if (fs <= 0 || fc <= 0 || fs % fc) return PCAL_EINVAL;
     if (fo < 0 || fo >= fs) return PCAL_EINVAL;
@@ -89,15 +68,15 @@ int check_params(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband) {
 // position budget: then a row is k periods long and the workgroup size is
 // picked to waste the fewest lanes.  Otherwise a row is one period, split
 // into equal column tiles of at most the budget.
-FoldGeom plan_geom(int64_t Sp, int nbits) {
+FoldGeom plan_geom(int64_t Sp, int spv, int64_t max_positions, int max_threads, int force_threads) {
     FoldGeom g{};
-    g.spv = spv_of(nbits);
+    g.spv = spv;
     const int64_t W = Sp / g.spv;  // vectors per period
-    const int pref = env_int("PCAL_FOLD_THREADS", 0);
-    if (Sp <= kMaxLdsPositions && W <= kMaxFoldThreads) {
+    const int pref = force_threads ? force_threads : env_int("PCAL_FOLD_THREADS", 0);
+    if (Sp <= max_positions && W <= max_threads) {
         int best_t = 0;
         double best = -1.0;
-        for (int t = 256; t <= kMaxFoldThreads; t += 64) {
+        for (int t = 256; t <= max_threads; t += 64) {
             if (pref && t != pref) continue;
             const int64_t k = t / W;
             if (k < 1) continue;
@@ -116,21 +95,21 @@ FoldGeom plan_geom(int64_t Sp, int nbits) {
         g.pos_cols = static_cast<int>(W);
         g.npos = static_cast<int>(Sp);
     } else {
-        const int tile_max = std::min(kMaxFoldThreads, kMaxLdsPositions / g.spv);
+        const int tile_max = static_cast<int>(std::min<int64_t>(max_threads, max_positions / g.spv));
         const int64_t tiles = (W + tile_max - 1) / tile_max;
         const int64_t tile = (W + tiles - 1) / tiles;
         g.row_vecs = static_cast<int>(W);
         g.tile_vecs = static_cast<int>(tile);
         g.col_tiles = static_cast<int>(tiles);
         g.pos_cols = g.tile_vecs;
-        g.npos = g.tile_vecs * g.spv;
+        g.npos = static_cast<int>(std::min<int64_t>(int64_t(g.tile_vecs) * g.spv, INT32_MAX));
         g.threads = static_cast<int>(((tile + 63) / 64) * 64);
     }
     return g;
 }
 
-int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int method, int prec,
-              Plan *p) {
+int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int method, int prec, Plan *p,
+              int force_threads) {
     int rc = check_params(fs, fc, fo, nbits, sideband);
     if (rc) return rc;
     if (method < PCAL_METHOD_AUTO || method > PCAL_METHOD_OSC) return PCAL_EINVAL;
@@ -147,11 +126,22 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
     p->Sp = p->S > 0 ? lcm_capped(p->S, spv_of(nbits), kMaxFoldPeriod) : -1;
     p->M = p->Sp > 0 ? p->Sp / p->N : -1;
     const bool fold_ok = p->Sp > 0 && p->M <= kMaxTableRows;
-    if (method == PCAL_METHOD_AUTO) method = PCAL_METHOD_PERIOD_FOLD;
-    if (method != PCAL_METHOD_PERIOD_FOLD) return PCAL_ENOTSUP;
-    if (!fold_ok) return PCAL_ENOTSUP;
+    const bool osc_ok = fs < (int64_t(1) << 32);
+    // The fold pays off while a launch spans many fold periods; for long periods
+    // (offsets sharing few factors with fs, Section 6) AUTO takes the recurrence.
+    if (method == PCAL_METHOD_AUTO)
+        method = (fold_ok && p->Sp <= kAutoFoldPeriod) ? PCAL_METHOD_PERIOD_FOLD : PCAL_METHOD_OSC;
+    if (method == PCAL_METHOD_PERIOD_FOLD && !fold_ok) return PCAL_ENOTSUP;
+    if (method == PCAL_METHOD_LUT && (p->R > kMaxLutPeriod || !osc_ok)) return PCAL_ENOTSUP;
+    if (method == PCAL_METHOD_OSC && !osc_ok) return PCAL_ENOTSUP;
     p->method = method;
-    p->geom = plan_geom(p->Sp, nbits);
+    if (method == PCAL_METHOD_PERIOD_FOLD) {
+        p->geom = plan_geom(p->Sp, spv_of(nbits), kMaxLdsPositions, kMaxFoldThreads, force_threads);
+    } else {
+        // rows of a multiple of lcm(N, 16) samples: every lane keeps its bin
+        const int64_t per = p->N / gcd64(p->N, kRotLanes) * kRotLanes;
+        p->geom = plan_geom(per, kRotLanes, INT64_MAX, kMaxRotThreads, force_threads);
+    }
     p->target_blocks = env_int("PCAL_TARGET_BLOCKS", 1024);
     if (p->target_blocks < 1) p->target_blocks = 1;
     p->max_blocks = std::max(p->geom.col_tiles, p->target_blocks) + p->geom.col_tiles;
@@ -159,28 +149,36 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
 }
 
 // Launch geometry of one extract call.
-pcal_launch_t plan_launch(const Plan &p, uint64_t addr, int64_t n_before, int64_t nsamples) {
+pcal_launch_t plan_launch(const Plan &p, uint64_t addr, int64_t n_before, int64_t nsamples, int target_blocks) {
     const FoldGeom &g = p.geom;
     const int spb = 8 / p.nbits;
     pcal_launch_t L{};
     const int64_t nbytes = nsamples / spb;
-    int64_t head = static_cast<int64_t>((16 - (addr & 15)) & 15);
+    const int64_t vb = static_cast<int64_t>(g.spv) / spb;  // bytes per thread-vector (16 or 4)
+    int64_t head = static_cast<int64_t>((vb - static_cast<int64_t>(addr % vb)) % vb);
     if (head > nbytes) head = nbytes;
     L.head_bytes = head;
-    L.nvec = (nbytes - head) / 16;
-    L.tail_bytes = nbytes - head - 16 * L.nvec;
+    L.nvec = (nbytes - head) / vb;
+    L.tail_bytes = nbytes - head - vb * L.nvec;
     const int64_t g0 = n_before + head * spb;  // global index of the first full-vector sample
     L.rows_total = (L.nvec + g.row_vecs - 1) / g.row_vecs;
-    const int64_t groups_want = std::max<int64_t>(1, p.target_blocks / g.col_tiles);
+    const int64_t groups_want = std::max<int64_t>(1, (target_blocks ? target_blocks : p.target_blocks) / g.col_tiles);
     const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(groups_want, L.rows_total));
     L.rows_per_group = L.rows_total > 0 ? (L.rows_total + groups - 1) / groups : 1;
     const int64_t ngroups = L.rows_total > 0 ? (L.rows_total + L.rows_per_group - 1) / L.rows_per_group : 1;
     L.grid = ngroups * g.col_tiles;
     L.threads = g.threads;
-    L.lds_bytes = static_cast<int64_t>(fold_lds_bytes(g.npos, g.spv, g.threads, p.M));
-    L.q0 = g0 % p.Sp;
-    L.head_q = n_before % p.Sp;
-    L.tail_q = (g0 + L.nvec * g.spv) % p.Sp;
+    if (p.method == PCAL_METHOD_PERIOD_FOLD) {
+        L.lds_bytes = static_cast<int64_t>(fold_lds_bytes(g.npos, g.spv, g.threads, p.M));
+        L.q0 = g0 % p.Sp;
+        L.head_q = n_before % p.Sp;
+        L.tail_q = (g0 + L.nvec * g.spv) % p.Sp;
+    } else {
+        L.lds_bytes = static_cast<int64_t>(sizeof(double2)) * p.N;
+        L.q0 = g0;
+        L.head_q = n_before;
+        L.tail_q = g0 + L.nvec * g.spv;
+    }
     return L;
 }
 
@@ -198,34 +196,6 @@ void fill_info(const Plan &p, pcal_info_t *info) {
     info->lds_positions = p.geom.npos;
 }
 
-}  // namespace
-}  // namespace pcal
-
-using namespace pcal;
-
-struct pcal_ctx {
-    Plan plan;
-    int device = 0;
-    double2 *u64 = nullptr;
-    float2 *u32 = nullptr;
-    __half2 *u16 = nullptr;
-    double2 *v = nullptr;
-    double2 *tw = nullptr;
-    double2 *acc = nullptr;
-    long long *acc_int = nullptr;
-    float2 *accf = nullptr;
-    unsigned *counters = nullptr;  // [0] finalize
-    double *out = nullptr;         // device results [4N + 1]
-    double *host_out = nullptr;    // pinned copy
-    int64_t n_total = 0;
-    int64_t n_integ = 0;
-    hipStream_t last_stream = nullptr;
-    hipEvent_t ev = nullptr;
-    bool have_ev = false;
-    size_t device_bytes = 0;
-};
-
-namespace {
 
 template <typename T>
 int dalloc(pcal_ctx *h, T **p, size_t count) {
@@ -240,7 +210,8 @@ int dalloc(pcal_ctx *h, T **p, size_t count) {
 }
 
 void release(pcal_ctx *h) {
-    void *ptrs[] = {h->u64, h->u32, h->u16, h->v, h->tw, h->acc, h->acc_int, h->accf, h->counters, h->out};
+    void *ptrs[] = {h->u64, h->u32, h->u16, h->v, h->tw, h->acc, h->acc_int, h->accf, h->counters, h->out,
+                    h->rot32, h->rot16, h->w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->host_out) (void)hipHostFree(h->host_out);
@@ -248,10 +219,71 @@ void release(pcal_ctx *h) {
     delete h;
 }
 
+// Mean rounding gain gamma = mean over k of conj(t[k]) * (t_rounded[k] - t[k]) of a
+// rotator table: every tone's response is scaled by 1 + gamma when the table is
+// used rounded, so 1 / (1 + gamma) restores it (returned as re, im).
+void table_gain(const std::vector<double2> &t, const std::vector<__half2> &th, double *re, double *im) {
+    double gr = 0.0, gi = 0.0;
+    for (size_t m = 0; m < t.size(); ++m) {
+        _Float16 hx, hy;
+        memcpy(&hx, reinterpret_cast<const char *>(&th[m]), 2);
+        memcpy(&hy, reinterpret_cast<const char *>(&th[m]) + 2, 2);
+        const double dr = static_cast<double>(hx) - t[m].x, di = static_cast<double>(hy) - t[m].y;
+        gr += t[m].x * dr + t[m].y * di;
+        gi += t[m].x * di - t[m].y * dr;
+    }
+    gr /= static_cast<double>(t.size());
+    gi /= static_cast<double>(t.size());
+    const double den = (1.0 + gr) * (1.0 + gr) + gi * gi;
+    *re = (1.0 + gr) / den;
+    *im = -gi / den;
+}
+
+__half2 to_half2(double2 v) {
+    __half2 r;
+    const _Float16 hx = static_cast<_Float16>(v.x), hy = static_cast<_Float16>(v.y);
+    memcpy(reinterpret_cast<char *>(&r), &hx, 2);
+    memcpy(reinterpret_cast<char *>(&r) + 2, &hy, 2);
+    return r;
+}
+
 int build(pcal_ctx *h) {
     const Plan &p = h->plan;
-    const int64_t N = p.N, M = p.M;
+    const bool fold = p.method == PCAL_METHOD_PERIOD_FOLD;
+    const int64_t N = p.N, M = fold ? p.M : 1;
     int rc;
+    if (!fold) {
+        // per-sample forms: lane factors, recurrence step, rotator table
+        const int64_t dn = static_cast<int64_t>(p.geom.row_vecs) * p.geom.spv;  // samples per row
+        std::vector<double2> w(kRotLanes);
+        for (int i = 0; i < kRotLanes; ++i)
+            phasor(static_cast<int64_t>((static_cast<unsigned __int128>(p.fo) * i) % p.fs), p.fs, &w[i].x, &w[i].y);
+        double br, bi;
+        const int64_t di = static_cast<int64_t>((static_cast<unsigned __int128>(p.fo) * dn) % p.fs);
+        phasor(di, p.fs, &br, &bi);
+        h->back = make_double2(br, -bi);
+        h->c2 = static_cast<float>(2.0 * br);
+        if ((rc = dalloc(h, &h->w, kRotLanes))) return rc;
+        PCAL_HIP(hipMemcpy(h->w, w.data(), sizeof(double2) * kRotLanes, hipMemcpyHostToDevice));
+        if (p.method == PCAL_METHOD_LUT) {
+            const int64_t R = p.R;
+            std::vector<double2> t(R);
+            std::vector<float2> tf(R);
+            std::vector<__half2> th(R);
+            int64_t idx = 0;
+            for (int64_t n = 0; n < R; ++n) {
+                phasor(idx, p.fs, &t[n].x, &t[n].y);
+                tf[n] = make_float2(static_cast<float>(t[n].x), static_cast<float>(t[n].y));
+                th[n] = to_half2(t[n]);
+                idx += p.fo;
+                if (idx >= p.fs) idx -= p.fs;
+            }
+            if (p.prec == PCAL_PREC_MIXED) table_gain(t, th, &h->gain_re, &h->gain_im);
+            if ((rc = dalloc(h, &h->rot32, R)) || (rc = dalloc(h, &h->rot16, R))) return rc;
+            PCAL_HIP(hipMemcpy(h->rot32, tf.data(), sizeof(float2) * R, hipMemcpyHostToDevice));
+            PCAL_HIP(hipMemcpy(h->rot16, th.data(), sizeof(__half2) * R, hipMemcpyHostToDevice));
+        }
+    }
     if ((rc = dalloc(h, &h->u64, M)) || (rc = dalloc(h, &h->u32, M)) || (rc = dalloc(h, &h->u16, M)) ||
         (rc = dalloc(h, &h->v, N)) || (rc = dalloc(h, &h->tw, N)) || (rc = dalloc(h, &h->acc, kAccSlots * N)) ||
         (rc = dalloc(h, &h->acc_int, kAccSlots * N)) || (rc = dalloc(h, &h->accf, kAccSlots * N)) || (rc = dalloc(h, &h->counters, 1)) ||
@@ -276,9 +308,7 @@ int build(pcal_ctx *h) {
     for (int64_t m = 0; m < M; ++m) {
         phasor(idx, p.fs, &u[m].x, &u[m].y);
         uf[m] = make_float2(static_cast<float>(u[m].x), static_cast<float>(u[m].y));
-        const _Float16 hx = static_cast<_Float16>(u[m].x), hy = static_cast<_Float16>(u[m].y);
-        memcpy(reinterpret_cast<char *>(&uh[m]), &hx, 2);
-        memcpy(reinterpret_cast<char *>(&uh[m]) + 2, &hy, 2);
+        uh[m] = to_half2(u[m]);
         idx += step_u;
         if (idx >= p.fs) idx -= p.fs;
     }
@@ -289,6 +319,10 @@ int build(pcal_ctx *h) {
         if (idx >= p.fs) idx -= p.fs;
         phasor(b, N, &tw[b].x, &tw[b].y);
     }
+    // Mixed form: the FP16 rows change every tone's response by the same known
+    // complex gain 1 + gamma, gamma = mean over m of conj(u[m]) * (u16[m] - u[m])
+    // (the rows sum against conj(u[m]) for every tone); the FP64 finalize divides it out.
+    if (fold && p.prec == PCAL_PREC_MIXED) table_gain(u, uh, &h->gain_re, &h->gain_im);
     PCAL_HIP(hipMemcpy(h->u64, u.data(), sizeof(double2) * M, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemcpy(h->u32, uf.data(), sizeof(float2) * M, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemcpy(h->u16, uh.data(), sizeof(__half2) * M, hipMemcpyHostToDevice));
@@ -315,22 +349,14 @@ int mark(pcal_ctx *h, hipStream_t s) {
     return PCAL_OK;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-        else prev = -1;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
 
-int run_finalize(pcal_ctx *h) {
+
+FinArgs fin_args(const pcal_ctx *h, double *out) {
     const Plan &p = h->plan;
     const int N = static_cast<int>(p.N);
     FinArgs f{};
     f.acc = h->acc;
+    f.accf = h->accf;
     f.tw = h->tw;
     f.N = N;
     f.prec = p.prec;
@@ -349,90 +375,26 @@ int run_finalize(pcal_ctx *h) {
     f.k_lo = k_lo;
     f.k_hi = k_hi;
     f.f_comb = static_cast<double>(p.fc);
-    f.out = h->out;
-    f.accf = h->accf;
+    f.gain_re = h->gain_re;
+    f.gain_im = h->gain_im;
+    f.out = out;
     f.counter = h->counters;
+    return f;
+}
+
+int run_finalize(pcal_ctx *h) {
+    const Plan &p = h->plan;
     hipStream_t s = h->last_stream;
-    launch_finalize(f, s);
+    launch_finalize(fin_args(h, h->out), s);
     PCAL_HIP(hipGetLastError());
     PCAL_HIP(hipMemcpyAsync(h->host_out, h->out, sizeof(double) * (4 * p.N + 1), hipMemcpyDeviceToHost, s));
     PCAL_HIP(hipStreamSynchronize(s));
     return PCAL_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int pcal_plan(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int method, int precision,
-              pcal_info_t *info) {
-    if (!info) return PCAL_EINVAL;
-    Plan p{};
-    const int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, 1, method, precision, &p);
-    if (rc) return rc;
-    fill_info(p, info);
-    return PCAL_OK;
-}
-
-int pcal_plan_launch(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int method,
-                     int precision, uint64_t addr_low, int64_t samples_before, int64_t nsamples,
-                     pcal_launch_t *out) {
-    if (!out || samples_before < 0 || nsamples < 0) return PCAL_EINVAL;
-    Plan p{};
-    const int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, 1, method, precision, &p);
-    if (rc) return rc;
-    if (nsamples % (8 / nbits)) return PCAL_EINVAL;
-    *out = plan_launch(p, addr_low, samples_before, nsamples);
-    return PCAL_OK;
-}
-
-int pcal_create_ex(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband, int method,
-                   int precision, pcal_t *out) {
-    if (!out) return PCAL_EINVAL;
-    *out = nullptr;
-    Plan p{};
-    int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, method, precision, &p);
-    if (rc) return rc;
-    pcal_ctx *h = new (std::nothrow) pcal_ctx();
-    if (!h) return PCAL_ENOMEM;
-    h->plan = p;
-    {
-        hipError_t e = hipGetDevice(&h->device);
-        if (e != hipSuccess) {
-            set_error("hipGetDevice", e);
-            delete h;
-            return PCAL_EHIP;
-        }
-    }
-    rc = build(h);
-    if (rc) {
-        release(h);
-        return rc;
-    }
-    *out = h;
-    return PCAL_OK;
-}
-
-int pcal_create(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband, pcal_t *out) {
-    return pcal_create_ex(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_AUTO, PCAL_PREC_F64, out);
-}
-
-int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t stream) {
-    if (!h || nsamples < 0) return PCAL_EINVAL;
+FoldArgs fold_args(const pcal_ctx *h, const pcal_launch_t &L, const void *dev_ptr) {
     const Plan &p = h->plan;
-    const int spb = 8 / p.nbits;
-    if (nsamples % spb) return PCAL_EINVAL;
-    if (nsamples == 0) return PCAL_OK;
-    if (!dev_ptr) return PCAL_EINVAL;
-    DeviceGuard guard(h->device);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    int rc = order_on(h, s);
-    if (rc) return rc;
-
     const FoldGeom &g = p.geom;
-    const pcal_launch_t L = plan_launch(p, reinterpret_cast<uintptr_t>(dev_ptr), h->n_total, nsamples);
-    if (L.grid > p.max_blocks) return PCAL_EINVAL;  // cannot happen by construction
-
     FoldArgs a{};
     a.data = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(dev_ptr) + L.head_bytes);
     a.nvec = L.nvec;
@@ -463,7 +425,125 @@ int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t 
     a.acc = h->acc;
     a.acc_int = h->acc_int;
     a.accf = h->accf;
-    launch_fold(a, p.nbits, static_cast<int>(L.grid), g.threads, static_cast<size_t>(L.lds_bytes), s);
+    return a;
+}
+
+int create(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int method, int prec, int force_threads,
+           pcal_ctx **out) {
+    *out = nullptr;
+    Plan p{};
+    int rc = make_plan(fs, fc, fo, nbits, sideband, method, prec, &p, force_threads);
+    if (rc) return rc;
+    pcal_ctx *h = new (std::nothrow) pcal_ctx();
+    if (!h) return PCAL_ENOMEM;
+    h->plan = p;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        set_error("hipGetDevice", e);
+        delete h;
+        return PCAL_EHIP;
+    }
+    rc = build(h);
+    if (rc) {
+        release(h);
+        return rc;
+    }
+    *out = h;
+    return PCAL_OK;
+}
+
+}  // namespace host
+}  // namespace pcal
+
+using namespace pcal;
+using namespace pcal::host;
+
+extern "C" {
+
+int pcal_plan(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int method, int precision,
+              pcal_info_t *info) {
+    if (!info) return PCAL_EINVAL;
+    Plan p{};
+    const int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, 1, method, precision, &p);
+    if (rc) return rc;
+    fill_info(p, info);
+    return PCAL_OK;
+}
+
+int pcal_plan_launch(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int method,
+                     int precision, uint64_t addr_low, int64_t samples_before, int64_t nsamples,
+                     pcal_launch_t *out) {
+    if (!out || samples_before < 0 || nsamples < 0) return PCAL_EINVAL;
+    Plan p{};
+    const int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, 1, method, precision, &p);
+    if (rc) return rc;
+    if (nsamples % (8 / nbits)) return PCAL_EINVAL;
+    *out = plan_launch(p, addr_low, samples_before, nsamples);
+    return PCAL_OK;
+}
+
+int pcal_create_ex(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband, int method,
+                   int precision, pcal_t *out) {
+    if (!out) return PCAL_EINVAL;
+    return create(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, method, precision, 0, out);
+}
+
+int pcal_create(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband, pcal_t *out) {
+    return pcal_create_ex(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_AUTO, PCAL_PREC_F64, out);
+}
+
+int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t stream) {
+    if (!h || nsamples < 0) return PCAL_EINVAL;
+    const Plan &p = h->plan;
+    const int spb = 8 / p.nbits;
+    if (nsamples % spb) return PCAL_EINVAL;
+    if (nsamples == 0) return PCAL_OK;
+    if (!dev_ptr) return PCAL_EINVAL;
+    DeviceGuard guard(h->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = order_on(h, s);
+    if (rc) return rc;
+
+    const FoldGeom &g = p.geom;
+    const pcal_launch_t L = plan_launch(p, reinterpret_cast<uintptr_t>(dev_ptr), h->n_total, nsamples);
+    if (L.grid > p.max_blocks) return PCAL_EINVAL;  // cannot happen by construction
+
+    if (p.method == PCAL_METHOD_PERIOD_FOLD) {
+        const FoldArgs a = fold_args(h, L, dev_ptr);
+        launch_fold(a, p.nbits, static_cast<int>(L.grid), g.threads, static_cast<size_t>(L.lds_bytes), s);
+    } else {
+        const int64_t vb = static_cast<int64_t>(g.spv) * p.nbits / 8;  // bytes per thread-vector
+        RotArgs a{};
+        a.data = static_cast<const uint8_t *>(dev_ptr) + L.head_bytes;
+        a.nvec = L.nvec;
+        a.rows_total = L.rows_total;
+        a.rows_per_group = L.rows_per_group;
+        a.row_vecs = g.row_vecs;
+        a.tile_vecs = g.tile_vecs;
+        a.col_tiles = g.col_tiles;
+        a.N = static_cast<int>(p.N);
+        a.nbits = p.nbits;
+        a.prec = p.prec;
+        a.method = p.method;
+        a.g0 = L.q0;
+        a.fs = p.fs;
+        a.fo = p.fo;
+        a.R = p.R;
+        a.rot32 = h->rot32;
+        a.rot16 = h->rot16;
+        a.w = h->w;
+        a.back = h->back;
+        a.c2 = h->c2;
+        a.head = static_cast<const uint8_t *>(dev_ptr);
+        a.head_bytes = static_cast<int>(L.head_bytes);
+        a.head_n = L.head_q;
+        a.tail = static_cast<const uint8_t *>(dev_ptr) + L.head_bytes + vb * L.nvec;
+        a.tail_bytes = static_cast<int>(L.tail_bytes);
+        a.tail_n = L.tail_q;
+        a.acc = h->acc;
+        a.accf = h->accf;
+        launch_rotate(a, static_cast<int>(L.grid), g.threads, static_cast<size_t>(L.lds_bytes), s);
+    }
     PCAL_HIP(hipGetLastError());
     h->n_total += nsamples;
     h->n_integ += nsamples;
@@ -495,7 +575,7 @@ int pcal_spectrum(pcal_t h, double *re, double *im) {
 
 int pcal_bins(pcal_t h, double *re, double *im, int64_t *int_bins) {
     if (!h) return PCAL_EINVAL;
-    if (int_bins && h->plan.fo != 0) return PCAL_ESTATE;
+    if (int_bins && (h->plan.fo != 0 || h->plan.method != PCAL_METHOD_PERIOD_FOLD)) return PCAL_ESTATE;
     DeviceGuard guard(h->device);
     const size_t N = static_cast<size_t>(h->plan.N);
     hipStream_t s = h->last_stream;

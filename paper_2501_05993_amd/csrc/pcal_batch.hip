@@ -1,0 +1,326 @@
+// Batched multi-stream form of libpcal: many streams (each its own fs,
+// f_offset, sample format, tables and accumulators) extracted by one launch of
+// the fused kernel over a work-list, finalized by one launch, results copied
+// by one transfer.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "pcal_host.h"
+
+using namespace pcal;
+using namespace pcal::host;
+
+namespace {
+
+constexpr int kBatchThreads = 512;        // workgroup size members are planned for
+constexpr int kBatchTargetBlocks = 1024;  // workgroups per batched launch, split by bytes
+constexpr int kStages = 4;                // pinned staging buffers in flight
+
+// Host staging of one launch's work-list (pinned) and its device copy.
+struct Stage {
+    FoldArgs *h_items = nullptr;
+    int *h_first = nullptr;
+    FinArgs *h_fin = nullptr;
+    ZeroItem *h_zero = nullptr;
+    FoldArgs *d_items = nullptr;
+    int *d_first = nullptr;
+    FinArgs *d_fin = nullptr;
+    ZeroItem *d_zero = nullptr;
+    hipEvent_t done = nullptr;  // the launch that read this stage has been enqueued past this event
+    bool pending = false;
+};
+
+}  // namespace
+
+struct pcal_batch_ctx {
+    int prec = PCAL_PREC_F64;
+    int max_streams = 0;
+    std::vector<pcal_ctx *> members;
+    Stage stage[kStages];
+    int next = 0;
+    double *d_out = nullptr;   // results of a batched finalize
+    double *h_out = nullptr;   // pinned copy
+    size_t out_cap = 0;        // doubles
+    hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+int stage_alloc(Stage &st, int n) {
+    const size_t nf = sizeof(FoldArgs) * n, ni = sizeof(int) * (n + 1), nfin = sizeof(FinArgs) * n,
+                 nz = sizeof(ZeroItem) * 3 * n;
+    PCAL_HIP(hipHostMalloc(reinterpret_cast<void **>(&st.h_items), nf, hipHostMallocDefault));
+    PCAL_HIP(hipHostMalloc(reinterpret_cast<void **>(&st.h_first), ni, hipHostMallocDefault));
+    PCAL_HIP(hipHostMalloc(reinterpret_cast<void **>(&st.h_fin), nfin, hipHostMallocDefault));
+    PCAL_HIP(hipHostMalloc(reinterpret_cast<void **>(&st.h_zero), nz, hipHostMallocDefault));
+    PCAL_HIP(hipMalloc(reinterpret_cast<void **>(&st.d_items), nf));
+    PCAL_HIP(hipMalloc(reinterpret_cast<void **>(&st.d_first), ni));
+    PCAL_HIP(hipMalloc(reinterpret_cast<void **>(&st.d_fin), nfin));
+    PCAL_HIP(hipMalloc(reinterpret_cast<void **>(&st.d_zero), nz));
+    PCAL_HIP(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
+    return PCAL_OK;
+}
+
+void stage_free(Stage &st) {
+    if (st.h_items) (void)hipHostFree(st.h_items);
+    if (st.h_first) (void)hipHostFree(st.h_first);
+    if (st.h_fin) (void)hipHostFree(st.h_fin);
+    if (st.h_zero) (void)hipHostFree(st.h_zero);
+    if (st.d_items) (void)hipFree(st.d_items);
+    if (st.d_first) (void)hipFree(st.d_first);
+    if (st.d_fin) (void)hipFree(st.d_fin);
+    if (st.d_zero) (void)hipFree(st.d_zero);
+    if (st.done) (void)hipEventDestroy(st.done);
+}
+
+// A staging buffer whose previous use has been consumed by the GPU.
+int take_stage(pcal_batch_ctx *b, Stage **out) {
+    Stage &st = b->stage[b->next];
+    b->next = (b->next + 1) % kStages;
+    if (st.pending) PCAL_HIP(hipEventSynchronize(st.done));
+    st.pending = false;
+    *out = &st;
+    return PCAL_OK;
+}
+
+int check_ids(const pcal_batch_ctx *b, int count, const int *ids) {
+    if (count < 0 || (count > 0 && !ids) || count > b->max_streams) return PCAL_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (ids[i] < 0 || ids[i] >= static_cast<int>(b->members.size())) return PCAL_EINVAL;
+    return PCAL_OK;
+}
+
+// Order `s` after every listed member's previous work.
+int order_members(pcal_batch_ctx *b, int count, const int *ids, hipStream_t s) {
+    for (int i = 0; i < count; ++i) {
+        const int rc = order_on(b->members[ids[i]], s);
+        if (rc) return rc;
+    }
+    return PCAL_OK;
+}
+
+int mark_members(pcal_batch_ctx *b, int count, const int *ids, hipStream_t s) {
+    for (int i = 0; i < count; ++i) {
+        const int rc = mark(b->members[ids[i]], s);
+        if (rc) return rc;
+    }
+    b->last_stream = s;
+    return PCAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcal_batch_create(int max_streams, int precision, pcal_batch_t *out) {
+    if (!out || max_streams <= 0 || precision < PCAL_PREC_F64 || precision > PCAL_PREC_F32) return PCAL_EINVAL;
+    *out = nullptr;
+    pcal_batch_ctx *b = new (std::nothrow) pcal_batch_ctx();
+    if (!b) return PCAL_ENOMEM;
+    b->prec = precision;
+    b->max_streams = max_streams;
+    for (int i = 0; i < kStages; ++i) {
+        const int rc = stage_alloc(b->stage[i], max_streams);
+        if (rc) {
+            pcal_batch_destroy(b);
+            return rc;
+        }
+    }
+    *out = b;
+    return PCAL_OK;
+}
+
+int pcal_batch_add(pcal_batch_t b, int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband,
+                   int *id) {
+    if (!b || !id) return PCAL_EINVAL;
+    if (static_cast<int>(b->members.size()) >= b->max_streams) return PCAL_EAGAIN;
+    pcal_ctx *h = nullptr;
+    const int rc = create(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_PERIOD_FOLD, b->prec,
+                          kBatchThreads, &h);
+    if (rc) return rc;
+    b->members.push_back(h);
+    *id = static_cast<int>(b->members.size()) - 1;
+    return PCAL_OK;
+}
+
+int pcal_batch_handle(pcal_batch_t b, int id, pcal_t *h) {
+    if (!b || !h || id < 0 || id >= static_cast<int>(b->members.size())) return PCAL_EINVAL;
+    *h = b->members[id];
+    return PCAL_OK;
+}
+
+int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *const *dev_ptrs,
+                       const int64_t *nsamples, pcal_stream_t stream) {
+    if (!b) return PCAL_EINVAL;
+    int rc = check_ids(b, count, ids);
+    if (rc) return rc;
+    if (count > 0 && (!dev_ptrs || !nsamples)) return PCAL_EINVAL;
+    int64_t total_bytes = 0;
+    for (int i = 0; i < count; ++i) {
+        const Plan &p = b->members[ids[i]]->plan;
+        if (nsamples[i] < 0 || nsamples[i] % (8 / p.nbits) || (nsamples[i] > 0 && !dev_ptrs[i])) return PCAL_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (ids[j] == ids[i]) return PCAL_EINVAL;  // one chunk per stream and launch
+        total_bytes += nsamples[i] * p.nbits / 8;
+    }
+    if (total_bytes == 0) return PCAL_OK;
+    DeviceGuard guard(b->members[ids[0]]->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = order_members(b, count, ids, s))) return rc;
+    Stage *st = nullptr;
+    if ((rc = take_stage(b, &st))) return rc;
+    int n = 0, grid = 0, threads = 64;
+    size_t lds = 0;
+    for (int i = 0; i < count; ++i) {
+        if (nsamples[i] == 0) continue;
+        pcal_ctx *h = b->members[ids[i]];
+        const Plan &p = h->plan;
+        const int64_t bytes = nsamples[i] * p.nbits / 8;
+        const int target = static_cast<int>(std::max<int64_t>(
+            p.geom.col_tiles, (kBatchTargetBlocks * bytes + total_bytes - 1) / total_bytes));
+        const pcal_launch_t L =
+            plan_launch(p, reinterpret_cast<uintptr_t>(dev_ptrs[i]), h->n_total, nsamples[i], target);
+        st->h_items[n] = fold_args(h, L, dev_ptrs[i]);
+        st->h_first[n] = grid;
+        grid += static_cast<int>(L.grid);
+        threads = std::max(threads, p.geom.threads);
+        ++n;
+    }
+    for (int i = 0; i < n; ++i) {
+        const FoldArgs &a = st->h_items[i];
+        lds = std::max(lds, fold_lds_bytes(a.npos, a.nbits == 2 ? 64 : 16, threads, a.M));
+    }
+    st->h_first[n] = grid;
+    PCAL_HIP(hipMemcpyAsync(st->d_items, st->h_items, sizeof(FoldArgs) * n, hipMemcpyHostToDevice, s));
+    PCAL_HIP(hipMemcpyAsync(st->d_first, st->h_first, sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
+    launch_fold_batch(st->d_items, st->d_first, n, b->prec, grid, threads, lds, s);
+    PCAL_HIP(hipGetLastError());
+    PCAL_HIP(hipEventRecord(st->done, s));
+    st->pending = true;
+    for (int i = 0; i < count; ++i) {
+        b->members[ids[i]]->n_total += nsamples[i];
+        b->members[ids[i]]->n_integ += nsamples[i];
+    }
+    return mark_members(b, count, ids, s);
+}
+
+int pcal_batch_results(pcal_batch_t b, int count, const int *ids, double *amp, double *phase, double *delay) {
+    if (!b) return PCAL_EINVAL;
+    int rc = check_ids(b, count, ids);
+    if (rc || count == 0) return rc;
+    DeviceGuard guard(b->members[ids[0]]->device);
+    hipStream_t s = b->members[ids[0]]->last_stream;
+    if ((rc = order_members(b, count, ids, s))) return rc;
+    size_t need = 0;
+    for (int i = 0; i < count; ++i) need += 4 * static_cast<size_t>(b->members[ids[i]]->plan.N) + 1;
+    if (need > b->out_cap) {
+        if (b->d_out) (void)hipFree(b->d_out);
+        if (b->h_out) (void)hipHostFree(b->h_out);
+        b->d_out = nullptr;
+        b->h_out = nullptr;
+        b->out_cap = 0;
+        PCAL_HIP(hipMalloc(reinterpret_cast<void **>(&b->d_out), sizeof(double) * need));
+        PCAL_HIP(hipHostMalloc(reinterpret_cast<void **>(&b->h_out), sizeof(double) * need, hipHostMallocDefault));
+        b->out_cap = need;
+    }
+    Stage *st = nullptr;
+    if ((rc = take_stage(b, &st))) return rc;
+    size_t off = 0;
+    int grid = 0;
+    size_t lds = 0;
+    for (int i = 0; i < count; ++i) {
+        const pcal_ctx *h = b->members[ids[i]];
+        st->h_fin[i] = fin_args(h, b->d_out + off);
+        st->h_first[i] = grid;
+        grid += static_cast<int>((h->plan.N + 63) / 64);
+        lds = std::max(lds, finalize_lds_bytes(static_cast<int>(h->plan.N)));
+        off += 4 * static_cast<size_t>(h->plan.N) + 1;
+    }
+    st->h_first[count] = grid;
+    PCAL_HIP(hipMemcpyAsync(st->d_fin, st->h_fin, sizeof(FinArgs) * count, hipMemcpyHostToDevice, s));
+    PCAL_HIP(hipMemcpyAsync(st->d_first, st->h_first, sizeof(int) * (count + 1), hipMemcpyHostToDevice, s));
+    launch_finalize_batch(st->d_fin, st->d_first, count, grid, lds, s);
+    PCAL_HIP(hipGetLastError());
+    PCAL_HIP(hipEventRecord(st->done, s));
+    st->pending = true;
+    PCAL_HIP(hipMemcpyAsync(b->h_out, b->d_out, sizeof(double) * off, hipMemcpyDeviceToHost, s));
+    PCAL_HIP(hipStreamSynchronize(s));
+    if ((rc = mark_members(b, count, ids, s))) return rc;
+    off = 0;
+    size_t ao = 0;
+    for (int i = 0; i < count; ++i) {
+        const size_t N = static_cast<size_t>(b->members[ids[i]]->plan.N);
+        if (amp) memcpy(amp + ao, b->h_out + off, sizeof(double) * N);
+        if (phase) memcpy(phase + ao, b->h_out + off + N, sizeof(double) * N);
+        if (delay) delay[i] = b->h_out[off + 4 * N];
+        ao += N;
+        off += 4 * N + 1;
+    }
+    return PCAL_OK;
+}
+
+int pcal_batch_spectra(pcal_batch_t b, int count, const int *ids, double *re, double *im) {
+    // C_k of each listed stream, concatenated (runs the batched finalize)
+    if (!b) return PCAL_EINVAL;
+    int rc = pcal_batch_results(b, count, ids, nullptr, nullptr, nullptr);
+    if (rc || count == 0) return rc;
+    size_t off = 0, ao = 0;
+    for (int i = 0; i < count; ++i) {
+        const size_t N = static_cast<size_t>(b->members[ids[i]]->plan.N);
+        if (re) memcpy(re + ao, b->h_out + off + 2 * N, sizeof(double) * N);
+        if (im) memcpy(im + ao, b->h_out + off + 3 * N, sizeof(double) * N);
+        ao += N;
+        off += 4 * N + 1;
+    }
+    return PCAL_OK;
+}
+
+int pcal_batch_reset(pcal_batch_t b, int count, const int *ids) {
+    if (!b) return PCAL_EINVAL;
+    int rc = check_ids(b, count, ids);
+    if (rc || count == 0) return rc;
+    DeviceGuard guard(b->members[ids[0]]->device);
+    hipStream_t s = b->members[ids[0]]->last_stream;
+    if ((rc = order_members(b, count, ids, s))) return rc;
+    Stage *st = nullptr;
+    if ((rc = take_stage(b, &st))) return rc;
+    int n = 0;
+    for (int i = 0; i < count; ++i) {
+        pcal_ctx *h = b->members[ids[i]];
+        const size_t N = static_cast<size_t>(h->plan.N) * kAccSlots;
+        st->h_zero[n++] = ZeroItem{h->acc, sizeof(double2) * N};
+        st->h_zero[n++] = ZeroItem{h->accf, sizeof(float2) * N};
+        st->h_zero[n++] = ZeroItem{h->acc_int, sizeof(long long) * N};
+        h->n_integ = 0;
+    }
+    PCAL_HIP(hipMemcpyAsync(st->d_zero, st->h_zero, sizeof(ZeroItem) * n, hipMemcpyHostToDevice, s));
+    launch_zero_list(st->d_zero, n, s);
+    PCAL_HIP(hipGetLastError());
+    PCAL_HIP(hipEventRecord(st->done, s));
+    st->pending = true;
+    return mark_members(b, count, ids, s);
+}
+
+int pcal_batch_size(pcal_batch_t b, int *n) {
+    if (!b || !n) return PCAL_EINVAL;
+    *n = static_cast<int>(b->members.size());
+    return PCAL_OK;
+}
+
+int pcal_batch_destroy(pcal_batch_t b) {
+    if (!b) return PCAL_EINVAL;
+    for (pcal_ctx *h : b->members) pcal_destroy(h);
+    for (int i = 0; i < kStages; ++i) {
+        if (b->stage[i].pending) (void)hipEventSynchronize(b->stage[i].done);
+        stage_free(b->stage[i]);
+    }
+    if (b->d_out) (void)hipFree(b->d_out);
+    if (b->h_out) (void)hipHostFree(b->h_out);
+    delete b;
+    return PCAL_OK;
+}
+
+}  // extern "C"

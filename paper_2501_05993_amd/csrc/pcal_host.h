@@ -1,0 +1,109 @@
+// Private host-side definitions of libpcal shared by its C ABI translation
+// units (single-stream API, batched and served forms).
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "pcal.h"
+#include "pcal_internal.h"
+
+namespace pcal {
+namespace host {
+
+void set_error(const char *what, hipError_t e);
+
+#define PCAL_HIP(call)                      \
+    do {                                    \
+        hipError_t e_ = (call);             \
+        if (e_ != hipSuccess) {             \
+            set_error(#call, e_);           \
+            return PCAL_EHIP;               \
+        }                                   \
+    } while (0)
+
+int64_t gcd64(int64_t a, int64_t b);
+void phasor(int64_t num, int64_t den, double *re, double *im);
+
+struct Plan {
+    int64_t fs, fc, fo;
+    int nbits, sideband, method, prec;
+    int64_t N, R, S, Sp, M;
+    FoldGeom geom;
+    int target_blocks;
+    int max_blocks;
+};
+
+constexpr int64_t kMaxFoldPeriod = int64_t(1) << 26;  // S' samples
+constexpr int64_t kMaxTableRows = int64_t(1) << 20;   // u table entries
+constexpr int64_t kMaxLutPeriod = int64_t(1) << 24;   // rotator table entries (table method)
+constexpr int kRotLanes = 16;                          // samples per thread-row, per-sample forms
+constexpr int64_t kAutoFoldPeriod = int64_t(1) << 22;  // longest fold period AUTO folds
+
+int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int method, int prec, Plan *p,
+              int force_threads = 0);
+// Launch geometry of one extract call; target_blocks = 0 takes the plan's.
+pcal_launch_t plan_launch(const Plan &p, uint64_t addr, int64_t n_before, int64_t nsamples,
+                          int target_blocks = 0);
+void fill_info(const Plan &p, pcal_info_t *info);
+
+}  // namespace host
+}  // namespace pcal
+
+struct pcal_ctx {
+    pcal::host::Plan plan;
+    int device = 0;
+    double2 *u64 = nullptr;
+    float2 *u32 = nullptr;
+    __half2 *u16 = nullptr;
+    double2 *v = nullptr;
+    double2 *tw = nullptr;
+    double2 *acc = nullptr;
+    long long *acc_int = nullptr;
+    float2 *accf = nullptr;
+    unsigned *counters = nullptr;  // [0] finalize
+    double *out = nullptr;         // device results [4N + 1]
+    double *host_out = nullptr;    // pinned copy
+    float2 *rot32 = nullptr;       // rotator table [R] (table method)
+    __half2 *rot16 = nullptr;
+    double2 *w = nullptr;          // [16] lane factors (per-sample forms)
+    double2 back = {1.0, 0.0};     // exp(+j w_o * samples per row)
+    float c2 = 2.0f;               // 2 cos(w_o * samples per row)
+    double gain_re = 1.0, gain_im = 0.0;  // 1 / (1 + gamma) of the FP16 table (mixed form)
+    int64_t n_total = 0;
+    int64_t n_integ = 0;
+    hipStream_t last_stream = nullptr;
+    hipEvent_t ev = nullptr;
+    bool have_ev = false;
+    size_t device_bytes = 0;
+};
+
+namespace pcal {
+namespace host {
+
+int build(pcal_ctx *h);
+void release(pcal_ctx *h);
+int create(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int method, int prec, int force_threads,
+           pcal_ctx **out);
+// Order work on `s` after the handle's previous work; record it as the handle's last work.
+int order_on(pcal_ctx *h, hipStream_t s);
+int mark(pcal_ctx *h, hipStream_t s);
+// Kernel arguments of one extract call of a period-fold handle.
+FoldArgs fold_args(const pcal_ctx *h, const pcal_launch_t &L, const void *dev_ptr);
+// Finalize arguments writing to `out` (4N + 1 doubles).
+FinArgs fin_args(const pcal_ctx *h, double *out);
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace host
+}  // namespace pcal

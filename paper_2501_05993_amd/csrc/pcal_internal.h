@@ -21,6 +21,9 @@ constexpr int kEpilogueScratch = 40;
 constexpr int kAccSlots = 16;
 // Largest workgroup of the fold kernel.
 constexpr int kMaxFoldThreads = 1024;
+// Largest workgroup of the per-sample rotation kernels (they keep 16 complex lanes
+// and their totals in registers).
+constexpr int kMaxRotThreads = 512;
 // Largest number of tones (bins) supported.
 constexpr int kMaxTones = 4096;
 
@@ -84,6 +87,29 @@ struct FoldArgs {
     long long *acc_int;      // [kAccSlots][N] integer bins of Eq. 2 (int_bins only)
 };
 
+// Arguments of the per-sample rotation kernels (table or recurrence rotator).
+struct RotArgs {
+    const void *data;        // aligned start of the full thread-vectors (16 samples each)
+    int64_t nvec, rows_total, rows_per_group;
+    int row_vecs, tile_vecs, col_tiles;
+    int N, nbits, prec, method;
+    int64_t g0;              // global index of the first full-vector sample
+    int64_t fs, fo, R;       // Hz, Hz, rotator period (Eq. 4)
+    const float2 *rot32;     // rotator table [R] in FP32 (table method)
+    const __half2 *rot16;    // the same in FP16 (mixed form)
+    const double2 *w;        // [16] lane factors exp(-j w_o i)
+    double2 back;            // exp(+j w_o * samples per row): one row back, FP64
+    float c2;                // 2 cos(w_o * samples per row), recurrence coefficient
+    const uint8_t *head;
+    int head_bytes;
+    int64_t head_n;          // global index of the first head sample
+    const uint8_t *tail;
+    int tail_bytes;
+    int64_t tail_n;
+    double2 *acc;            // [kAccSlots][N]
+    float2 *accf;            // [kAccSlots][N] (F32 form)
+};
+
 // Arguments of the FP64 finalize (DFT, amplitude, phase, delay).
 struct FinArgs {
     const double2 *acc;      // [kAccSlots][N] bins (FP64 forms)
@@ -95,12 +121,23 @@ struct FinArgs {
     double inv_L;            // 1 / samples in the integration (0 if none)
     int k_lo, k_hi;          // in-band tones [k_lo, k_hi): 0 < f_k < fs/2
     double f_comb;           // Hz
+    double gain_re, gain_im; // C_k is multiplied by this (1 / (1 + gamma) in the mixed form, else 1)
     double *out;             // [4N + 1]: amp, phase, re, im, delay
     unsigned *counter;
 };
 
 void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds, hipStream_t s);
+void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int prec, int grid, int threads,
+                       size_t lds, hipStream_t s);
+void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStream_t s);
 void launch_finalize(const FinArgs &a, hipStream_t s);
+size_t finalize_lds_bytes(int N);
+void launch_finalize_batch(const FinArgs *items, const int *first, int nitems, int grid, size_t lds, hipStream_t s);
+struct ZeroItem {
+    void *ptr;
+    size_t bytes;  // multiple of 4
+};
+void launch_zero_list(const ZeroItem *items, int n, hipStream_t s);
 void launch_zero(void *p, size_t bytes, hipStream_t s);
 
 }  // namespace pcal

@@ -46,7 +46,7 @@ __device__ __forceinline__ int level_of(const uint8_t *p, int nbits, int i) {
 
 // True in every thread of the workgroup that finishes last (all workgroups
 // call it once, after their global stores).  Self-resetting counter.
-__device__ __forceinline__ bool last_workgroup_done(unsigned *counter) {
+__device__ __forceinline__ bool last_workgroup_done(unsigned *counter, unsigned total) {
     __shared__ unsigned s_last;
     // every wave's global stores are complete (acknowledged by L2) before the
     // barrier, so the single write-back below covers the whole workgroup
@@ -55,7 +55,7 @@ __device__ __forceinline__ bool last_workgroup_done(unsigned *counter) {
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const bool last = prev == gridDim.x * gridDim.y * gridDim.z - 1;
+        const bool last = prev == total - 1;
         if (last) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -302,9 +302,9 @@ __device__ __forceinline__ typename BinAcc<PREC>::Tab table_row(const FoldArgs &
 // kAccSlots copies of the bins so that few atomics meet on one address; the
 // finalize adds the slots.
 template <int PREC>
-__device__ __forceinline__ void commit_bin(const FoldArgs &a, int b, const BinAcc<PREC> &q, double2 v) {
+__device__ __forceinline__ void commit_bin(const FoldArgs &a, int wg, int b, const BinAcc<PREC> &q, double2 v) {
     const double2 Q = q.value();
-    const size_t k = static_cast<size_t>(blockIdx.x % kAccSlots) * a.N + b;
+    const size_t k = static_cast<size_t>(wg % kAccSlots) * a.N + b;
     if constexpr (PREC == 2) {
         const float qr = static_cast<float>(Q.x), qi = static_cast<float>(Q.y);
         const float vr = static_cast<float>(v.x), vi = static_cast<float>(v.y);
@@ -339,12 +339,12 @@ __device__ void add_edges(const FoldArgs &a, int b, BinAcc<PREC> &q, const Tab *
 
 // ---------------------------------------------------------------- the fused kernel
 
+// The fused kernel's work for workgroup `wg` of one stream's launch geometry.
 template <int NBITS, int PREC>
-__global__ void __launch_bounds__(kMaxFoldThreads) fold_kernel(FoldArgs a) {
+__device__ __forceinline__ void fold_body(const FoldArgs &a, const int wg, unsigned char *lds) {
     using Acc = BinAcc<PREC>;
     using Tab = typename Acc::Tab;
     static_assert(sizeof(Acc) <= kEpilogueScratch, "epilogue scratch");
-    extern __shared__ __align__(16) unsigned char lds[];
     constexpr int SPV = NBITS == 2 ? 64 : 16;
     constexpr int kPre = 4;  // rotator rows prefetched per thread
     const int t = threadIdx.x, nt = blockDim.x;
@@ -364,8 +364,8 @@ __global__ void __launch_bounds__(kMaxFoldThreads) fold_kernel(FoldArgs a) {
     for (int i = t; i < npos_sk; i += nt) F[i] = 0;
     __syncthreads();
 
-    const int c = static_cast<int>(blockIdx.x % a.col_tiles);
-    const int64_t g = blockIdx.x / a.col_tiles;
+    const int c = wg % a.col_tiles;
+    const int64_t g = wg / a.col_tiles;
     const int colr = c * a.tile_vecs + t;
     const int64_t r0 = g * a.rows_per_group;
     const int64_t r1 = (r0 + a.rows_per_group) < a.rows_total ? (r0 + a.rows_per_group) : a.rows_total;
@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(kMaxFoldThreads) fold_kernel(FoldArgs a) {
     const int Sp = static_cast<int>(a.Sp);
     const int qb = static_cast<int>((a.q0 + static_cast<int64_t>(c) * a.tile_vecs * SPV) % a.Sp);
     const int qbN = qb % N;
-    const bool edges = blockIdx.x == 0 && (a.head_bytes > 0 || a.tail_bytes > 0);
+    const bool edges = wg == 0 && (a.head_bytes > 0 || a.tail_bytes > 0);
     if (N >= nt) {
         for (int b = t; b < N; b += nt) {
             int p = b >= qbN ? b - qbN : b - qbN + N;
@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(kMaxFoldThreads) fold_kernel(FoldArgs a) {
                 if (++m == M) m = 0;
             }
             if (edges) add_edges<PREC>(a, b, acc, UL, u_lds);
-            commit_bin<PREC>(a, b, acc, a.v[b]);
+            commit_bin<PREC>(a, wg, b, acc, a.v[b]);
         }
     } else {
         // G groups of N threads split the positions of every bin; the group
@@ -433,9 +433,43 @@ __global__ void __launch_bounds__(kMaxFoldThreads) fold_kernel(FoldArgs a) {
             Acc tot = scr[b];
             for (int k = 1; k < G; ++k) tot.merge(scr[k * N + b]);
             if (edges) add_edges<PREC>(a, b, tot, UL, u_lds);
-            commit_bin<PREC>(a, b, tot, vb);
+            commit_bin<PREC>(a, wg, b, tot, vb);
         }
     }
+}
+
+template <int NBITS, int PREC>
+__global__ void __launch_bounds__(kMaxFoldThreads) fold_kernel(FoldArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    fold_body<NBITS, PREC>(a, static_cast<int>(blockIdx.x), lds);
+}
+
+// Index of the work item that owns workgroup `wg`: the last i with first[i] <= wg.
+__device__ __forceinline__ int owner_of(const int *first, int nitems, int wg) {
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= wg)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// One launch over the work items of many streams (each item: one stream's
+// launch geometry, tables and accumulators; first[i] = its first workgroup).
+template <int PREC>
+__global__ void __launch_bounds__(kMaxFoldThreads) fold_batch_kernel(const FoldArgs *items, const int *first,
+                                                                      int nitems) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int wg = static_cast<int>(blockIdx.x);
+    const int i = __builtin_amdgcn_readfirstlane(owner_of(first, nitems, wg));
+    const FoldArgs a = items[i];
+    if (a.nbits == 2)
+        fold_body<2, PREC>(a, wg - first[i], lds);
+    else
+        fold_body<8, PREC>(a, wg - first[i], lds);
 }
 
 // ---------------------------------------------------------------- finalize
@@ -444,8 +478,7 @@ __global__ void __launch_bounds__(kMaxFoldThreads) fold_kernel(FoldArgs a) {
 // the N-term DFT sum, twiddles indexed exactly by (k*b) mod N.  The last
 // workgroup unwraps the in-band phases (prefix sum of wrapped differences)
 // and fits the delay by least squares.
-__global__ void __launch_bounds__(256) finalize_kernel(FinArgs a) {
-    extern __shared__ __align__(16) unsigned char lds[];
+__device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, const int nwg, unsigned char *lds) {
     const int N = a.N, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double2 *P = reinterpret_cast<double2 *>(lds);
     const bool tw_lds = N <= kTwLdsMaxTones;
@@ -469,7 +502,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs a) {
         if (tw_lds) TW[i] = a.tw[i];
     }
     __syncthreads();
-    const int k = blockIdx.x * 64 + lane;
+    const int k = wg * 64 + lane;
     const int qn = (N + 3) / 4;
     const int bb = wave * qn;
     const int be = (bb + qn) < N ? (bb + qn) : N;
@@ -520,6 +553,11 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs a) {
             cr = fr;
             ci = fi;
         }
+        {  // known gain of a rounded rotator table, divided out (identity unless the mixed form)
+            const double gr = cr * a.gain_re - ci * a.gain_im;
+            ci = cr * a.gain_im + ci * a.gain_re;
+            cr = gr;
+        }
         if (a.sideband < 0) ci = -ci;
         a.out[k] = sqrt(cr * cr + ci * ci) * a.inv_L;
         a.out[N + k] = atan2(ci, cr);
@@ -527,7 +565,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs a) {
         a.out[3 * N + k] = ci;
     }
 
-    if (!last_workgroup_done(a.counter)) return;
+    if (!last_workgroup_done(a.counter, static_cast<unsigned>(nwg))) return;
 
     // Delay: unwrap phases over tones [k_lo, k_hi) and fit phase = a + 2 pi t_d f.
     const int n = a.k_hi - a.k_lo;
@@ -582,6 +620,30 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs a) {
     }
 }
 
+__global__ void __launch_bounds__(256) finalize_kernel(FinArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    finalize_body(a, static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), lds);
+}
+
+// Finalize of many streams in one launch: item i owns workgroups
+// [first[i], first[i + 1]), ceil(N_i / 64) of them.
+__global__ void __launch_bounds__(256) finalize_batch_kernel(const FinArgs *items, const int *first, int nitems) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int wg = static_cast<int>(blockIdx.x);
+    const int i = __builtin_amdgcn_readfirstlane(owner_of(first, nitems, wg));
+    const FinArgs a = items[i];
+    finalize_body(a, wg - first[i], (a.N + 63) / 64, lds);
+}
+
+// Zero a list of buffers (one workgroup per buffer, grid-stride inside).
+__global__ void zero_list_kernel(const ZeroItem *items, int n) {
+    for (int j = blockIdx.x; j < n; j += gridDim.x) {
+        uint32_t *p = static_cast<uint32_t *>(items[j].ptr);
+        const size_t w = items[j].bytes / 4;
+        for (size_t i = threadIdx.x; i < w; i += blockDim.x) p[i] = 0u;
+    }
+}
+
 __global__ void zero_kernel(uint32_t *p, size_t n) {
     for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<size_t>(gridDim.x) * blockDim.x)
@@ -603,10 +665,31 @@ void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds
     }
 }
 
+void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int prec, int grid, int threads,
+                       size_t lds, hipStream_t s) {
+    const dim3 gd(grid), bd(threads);
+    if (prec == 0)
+        hipLaunchKernelGGL((fold_batch_kernel<0>), gd, bd, lds, s, items, first, nitems);
+    else if (prec == 1)
+        hipLaunchKernelGGL((fold_batch_kernel<1>), gd, bd, lds, s, items, first, nitems);
+    else
+        hipLaunchKernelGGL((fold_batch_kernel<2>), gd, bd, lds, s, items, first, nitems);
+}
+
 void launch_finalize(const FinArgs &a, hipStream_t s) {
     const int grid = (a.N + 63) / 64;
-    const size_t lds = sizeof(double2) * ((a.N <= kTwLdsMaxTones ? 2 * a.N : a.N) + 256);
+    const size_t lds = finalize_lds_bytes(a.N);
     hipLaunchKernelGGL(finalize_kernel, dim3(grid), dim3(256), lds, s, a);
+}
+
+size_t finalize_lds_bytes(int N) { return sizeof(double2) * ((N <= kTwLdsMaxTones ? 2 * N : N) + 256); }
+
+void launch_finalize_batch(const FinArgs *items, const int *first, int nitems, int grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_batch_kernel, dim3(grid), dim3(256), lds, s, items, first, nitems);
+}
+
+void launch_zero_list(const ZeroItem *items, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_list_kernel, dim3(n < 1024 ? n : 1024), dim3(256), 0, s, items, n);
 }
 
 void launch_zero(void *p, size_t bytes, hipStream_t s) {

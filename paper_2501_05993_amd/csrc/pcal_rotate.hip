@@ -1,0 +1,314 @@
+// Per-sample rotation forms of libpcal: every sample is multiplied by the
+// rotator exp(-j w_o n) of Eq. 3 before it is folded into bin n mod N (Eq. 2).
+// The rotator comes either from a precomputed table of one rotator period
+// (Eq. 4, the precomputed method of Section 4.1) or from the direct-form
+// resonator recurrence y[r+1] = 2 cos(d) y[r] - y[r-1] (Eq. 6-7, the
+// oscillator method), re-seeded exactly at fixed intervals.
+//
+// Layout.  A thread owns 16 consecutive samples of every row (one 16-byte
+// load at 8-bit, one 4-byte load at 2-bit); rows are a multiple of N samples,
+// so each of the thread's 16 lanes always lands in the same bin.  Sample n of
+// lane i in row r is n = n_r + i with n_r the row's first sample of the
+// thread, and exp(-j w_o n) = exp(-j w_o n_r) exp(-j w_o i): the row factor
+// z_r is produced once per row (table read or one recurrence step), every
+// sample costs two FP32 FMAs against it, and the fixed lane factor
+// exp(-j w_o i) is applied once per lane at the end, in FP64.
+#include "pcal_internal.h"
+
+namespace pcal {
+namespace {
+
+constexpr int kLanes = 16;   // samples per thread and row
+constexpr int kRun = 64;     // rows per run: run sums in FP32, then folded into totals
+constexpr int kUnroll = 4;   // rows loaded ahead
+
+__device__ __forceinline__ int edge_level(const uint8_t *p, int nbits, int i) {
+    if (nbits == 2) return 2 * ((p[i >> 2] >> (2 * (i & 3))) & 3) - 3;
+    return static_cast<int>(static_cast<int8_t>(p[i]));
+}
+
+// exp(-j 2 pi (f_o n mod fs) / fs) in FP64 from an exact integer phase index (fs < 2^32).
+__device__ __forceinline__ double2 exact_rotator(int64_t n, int64_t fs, int64_t fo) {
+    const uint64_t nm = static_cast<uint64_t>(n % fs);
+    int64_t idx = static_cast<int64_t>((static_cast<uint64_t>(fo) * nm) % static_cast<uint64_t>(fs));
+    if (2 * idx > fs) idx -= fs;  // reduce the angle to (-pi, pi]
+    const double ang = 6.283185307179586476925286766559 * static_cast<double>(idx) / static_cast<double>(fs);
+    double s, c;
+    sincos(ang, &s, &c);
+    return make_double2(c, -s);
+}
+
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+// The 16 sample values of one thread-row as floats: biased bytes x + 128
+// (8-bit) or offset-binary codes c (2-bit), lane i = sample i.
+template <int NBITS>
+struct RowVec;
+
+template <>
+struct RowVec<8> {
+    uint4 v;
+    __device__ __forceinline__ void load(const void *base, int64_t idx) {
+        const u32x4_t x = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(base) + idx);
+        v = make_uint4(x.x ^ 0x80808080u, x.y ^ 0x80808080u, x.z ^ 0x80808080u, x.w ^ 0x80808080u);
+    }
+    __device__ __forceinline__ float get(int i) const {
+        const uint32_t w = i < 4 ? v.x : i < 8 ? v.y : i < 12 ? v.z : v.w;
+        return static_cast<float>((w >> (8 * (i & 3))) & 0xFFu);
+    }
+};
+
+template <>
+struct RowVec<2> {
+    uint32_t q[4];  // q[j]: byte lanes hold the codes of samples 4*lane + j
+    __device__ __forceinline__ void load(const void *base, int64_t idx) {
+        const uint32_t d = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(base) + idx);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q[j] = (d >> (2 * j)) & 0x03030303u;
+    }
+    __device__ __forceinline__ float get(int i) const {
+        return static_cast<float>((q[i & 3] >> (8 * (i >> 2))) & 0xFFu);
+    }
+};
+
+// Lane totals in the arithmetic of the precision form: FP64 (0), Kahan FP32 (1), FP32 (2).
+template <int PREC>
+struct LaneTot {
+    double r[kLanes], i[kLanes];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int k = 0; k < kLanes; ++k) r[k] = i[k] = 0.0;
+    }
+    __device__ __forceinline__ void add(int k, float a, float b) {
+        r[k] += a;
+        i[k] += b;
+    }
+    __device__ __forceinline__ double2 get(int k) const { return make_double2(r[k], i[k]); }
+};
+
+template <>
+struct LaneTot<1> {
+    float r[kLanes], i[kLanes], cr[kLanes], ci[kLanes];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int k = 0; k < kLanes; ++k) r[k] = i[k] = cr[k] = ci[k] = 0.f;
+    }
+    __device__ __forceinline__ static void kahan(float y, float &s, float &c) {
+        const float yc = y - c;
+        const float t = s + yc;
+        c = (t - s) - yc;
+        s = t;
+    }
+    __device__ __forceinline__ void add(int k, float a, float b) {
+        kahan(a, r[k], cr[k]);
+        kahan(b, i[k], ci[k]);
+    }
+    __device__ __forceinline__ double2 get(int k) const {
+        return make_double2(static_cast<double>(r[k]) - cr[k], static_cast<double>(i[k]) - ci[k]);
+    }
+};
+
+template <>
+struct LaneTot<2> {
+    float r[kLanes], i[kLanes];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int k = 0; k < kLanes; ++k) r[k] = i[k] = 0.f;
+    }
+    __device__ __forceinline__ void add(int k, float a, float b) {
+        r[k] += a;
+        i[k] += b;
+    }
+    __device__ __forceinline__ double2 get(int k) const { return make_double2(r[k], i[k]); }
+};
+
+// Row rotator source: table (METHOD 2) or recurrence (METHOD 3).
+template <int METHOD, int PREC>
+struct RowRot {
+    // table state
+    int64_t idx = 0, step = 0, R = 1;
+    // recurrence state (real and imaginary parts run the same two-term recurrence)
+    float zr = 0.f, zi = 0.f, pr = 0.f, pi = 0.f, c2 = 0.f;
+    int64_t n = 0, dn = 0;  // global index of the row's first lane sample, row stride in samples
+
+    __device__ __forceinline__ float2 table(const RotArgs &a, int64_t k) const {
+        if constexpr (PREC == 1)
+            return __half22float2(a.rot16[k]);
+        else
+            return a.rot32[k];
+    }
+    // exact seed at global sample n (recurrence): z(n) and z(n - dn) in FP64, rounded once
+    __device__ __forceinline__ void seed(const RotArgs &a) {
+        const double2 z = exact_rotator(n, a.fs, a.fo);
+        const double2 zp = make_double2(z.x * a.back.x - z.y * a.back.y, z.x * a.back.y + z.y * a.back.x);
+        zr = static_cast<float>(z.x);
+        zi = static_cast<float>(z.y);
+        pr = static_cast<float>(zp.x);
+        pi = static_cast<float>(zp.y);
+    }
+    // rotators of the next U rows, then move U rows on
+    template <int U>
+    __device__ __forceinline__ void fetch(const RotArgs &a, float2 (&z)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if constexpr (METHOD == 2) {
+                z[u] = table(a, idx);
+                idx += step;
+                if (idx >= R) idx -= R;
+            } else {
+                z[u] = make_float2(zr, zi);
+                // Eq. 7: one FMA per component and row
+                const float nr = fmaf(c2, zr, -pr), ni = fmaf(c2, zi, -pi);
+                pr = zr;
+                pi = zi;
+                zr = nr;
+                zi = ni;
+            }
+        }
+        n += U * dn;
+    }
+};
+
+template <int NBITS, int METHOD, int PREC>
+__global__ void __launch_bounds__(kMaxRotThreads) rot_kernel(RotArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    double2 *bins = reinterpret_cast<double2 *>(lds);  // [N] workgroup bins (FP64)
+    const int t = threadIdx.x, nt = blockDim.x, N = a.N;
+    for (int b = t; b < N; b += nt) bins[b] = make_double2(0.0, 0.0);
+    __syncthreads();
+
+    const int c = static_cast<int>(blockIdx.x % a.col_tiles);
+    const int64_t g = blockIdx.x / a.col_tiles;
+    const int colr = c * a.tile_vecs + t;
+    const int64_t r0 = g * a.rows_per_group;
+    const int64_t r1 = (r0 + a.rows_per_group) < a.rows_total ? (r0 + a.rows_per_group) : a.rows_total;
+    if (t < a.tile_vecs && colr < a.row_vecs && r0 < r1) {
+        const int64_t stride = a.row_vecs;
+        const int64_t rfull = a.nvec / stride;
+        const bool last_ok = colr < a.nvec - rfull * stride;
+        const int64_t rend = r1 < rfull ? r1 : (r1 > rfull && last_ok ? r1 : rfull);
+        RowRot<METHOD, PREC> rot;
+        rot.n = a.g0 + (r0 * stride + colr) * kLanes;
+        rot.dn = stride * kLanes;
+        if constexpr (METHOD == 2) {
+            rot.R = a.R;
+            rot.step = (stride * kLanes) % a.R;
+            rot.idx = rot.n % a.R;
+        } else {
+            rot.c2 = a.c2;
+            rot.seed(a);
+        }
+        LaneTot<PREC> tot;
+        tot.zero();
+        int64_t r = r0;
+        while (r < rend) {
+            const int64_t run_end = (r + kRun) < rend ? (r + kRun) : rend;
+            float ar[kLanes], ai[kLanes];
+#pragma unroll
+            for (int k = 0; k < kLanes; ++k) ar[k] = ai[k] = 0.f;
+            float sr = 0.f, si = 0.f;  // sum of the row rotators of the run (bias term)
+            for (; r + kUnroll <= run_end; r += kUnroll) {
+                float2 z[kUnroll];
+                rot.fetch(a, z);  // table reads are issued with the sample loads
+                RowVec<NBITS> x[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) x[u].load(a.data, (r + u) * stride + colr);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+#pragma unroll
+                    for (int k = 0; k < kLanes; ++k) {
+                        const float xv = x[u].get(k);
+                        ar[k] = fmaf(xv, z[u].x, ar[k]);
+                        ai[k] = fmaf(xv, z[u].y, ai[k]);
+                    }
+                    sr += z[u].x;
+                    si += z[u].y;
+                }
+            }
+            for (; r < run_end; ++r) {
+                float2 z[1];
+                rot.fetch(a, z);
+                RowVec<NBITS> x;
+                x.load(a.data, r * stride + colr);
+#pragma unroll
+                for (int k = 0; k < kLanes; ++k) {
+                    const float xv = x.get(k);
+                    ar[k] = fmaf(xv, z[0].x, ar[k]);
+                    ai[k] = fmaf(xv, z[0].y, ai[k]);
+                }
+                sr += z[0].x;
+                si += z[0].y;
+            }
+            // undo the affine sample map: 8-bit x = u - 128, 2-bit level = 2c - 3
+#pragma unroll
+            for (int k = 0; k < kLanes; ++k) {
+                if constexpr (NBITS == 8)
+                    tot.add(k, ar[k] - 128.f * sr, ai[k] - 128.f * si);
+                else
+                    tot.add(k, 2.f * ar[k] - 3.f * sr, 2.f * ai[k] - 3.f * si);
+            }
+            if constexpr (METHOD == 3) rot.seed(a);  // exact restart of the recurrence
+        }
+        // lane factor exp(-j w_o i) in FP64, then into the workgroup's bins
+        const int bbase = static_cast<int>((a.g0 + static_cast<int64_t>(colr) * kLanes) % N);
+#pragma unroll
+        for (int k = 0; k < kLanes; ++k) {
+            const double2 v = tot.get(k);
+            const double2 w = a.w[k];
+            const int b = (bbase + k) % N;
+            atomicAdd(&bins[b].x, v.x * w.x - v.y * w.y);
+            atomicAdd(&bins[b].y, v.x * w.y + v.y * w.x);
+        }
+    }
+    // samples outside the full vectors: exact FP64 rotator per sample
+    if (blockIdx.x == 0) {
+        for (int part = 0; part < 2; ++part) {
+            const uint8_t *src = part ? a.tail : a.head;
+            const int ns = (part ? a.tail_bytes : a.head_bytes) * (8 / a.nbits);
+            const int64_t n0 = part ? a.tail_n : a.head_n;
+            for (int i = t; i < ns; i += nt) {
+                const double2 z = exact_rotator(n0 + i, a.fs, a.fo);
+                const int x = edge_level(src, a.nbits, i);
+                const int b = static_cast<int>((n0 + i) % N);
+                atomicAdd(&bins[b].x, x * z.x);
+                atomicAdd(&bins[b].y, x * z.y);
+            }
+        }
+    }
+    __syncthreads();
+    const size_t slot = static_cast<size_t>(blockIdx.x % kAccSlots) * N;
+    for (int b = t; b < N; b += nt) {
+        const double2 v = bins[b];
+        if (v.x == 0.0 && v.y == 0.0) continue;
+        if constexpr (PREC == 2) {
+            unsafeAtomicAdd(&a.accf[slot + b].x, static_cast<float>(v.x));
+            unsafeAtomicAdd(&a.accf[slot + b].y, static_cast<float>(v.y));
+        } else {
+            unsafeAtomicAdd(&a.acc[slot + b].x, v.x);
+            unsafeAtomicAdd(&a.acc[slot + b].y, v.y);
+        }
+    }
+}
+
+}  // namespace
+
+void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStream_t s) {
+    const dim3 gd(grid), bd(threads);
+#define PCAL_ROT(NB, ME, PR) hipLaunchKernelGGL((rot_kernel<NB, ME, PR>), gd, bd, lds, s, a)
+    if (a.nbits == 2) {
+        if (a.method == 2) {
+            if (a.prec == 0) PCAL_ROT(2, 2, 0); else if (a.prec == 1) PCAL_ROT(2, 2, 1); else PCAL_ROT(2, 2, 2);
+        } else {
+            if (a.prec == 0) PCAL_ROT(2, 3, 0); else if (a.prec == 1) PCAL_ROT(2, 3, 1); else PCAL_ROT(2, 3, 2);
+        }
+    } else {
+        if (a.method == 2) {
+            if (a.prec == 0) PCAL_ROT(8, 2, 0); else if (a.prec == 1) PCAL_ROT(8, 2, 1); else PCAL_ROT(8, 2, 2);
+        } else {
+            if (a.prec == 0) PCAL_ROT(8, 3, 0); else if (a.prec == 1) PCAL_ROT(8, 3, 1); else PCAL_ROT(8, 3, 2);
+        }
+    }
+#undef PCAL_ROT
+}
+
+}  // namespace pcal

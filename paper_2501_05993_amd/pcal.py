@@ -71,6 +71,18 @@ _SIGS = {
                   ctypes.c_int),
     "pcal_plan_launch": ([_i64, _i64, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _i64,
                           _i64, ctypes.c_void_p], ctypes.c_int),
+    "pcal_batch_create": ([ctypes.c_int, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "pcal_batch_add": ([ctypes.c_void_p, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "pcal_batch_handle": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "pcal_batch_extract": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_void_p], ctypes.c_int),
+    "pcal_batch_results": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_void_p], ctypes.c_int),
+    "pcal_batch_spectra": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                           ctypes.c_int),
+    "pcal_batch_reset": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "pcal_batch_size": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "pcal_batch_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "pcal_last_error": ([], ctypes.c_char_p),
 }
@@ -196,6 +208,90 @@ class PCal:
         if self._h and self._h.value:
             _check(lib().pcal_destroy(self._h), "pcal_destroy")
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class PCalBatch:
+    """Many streams extracted by one launch (pcal_batch_*)."""
+
+    def __init__(self, max_streams: int, precision: int = PREC_F64):
+        self._b = ctypes.c_void_p()
+        _check(lib().pcal_batch_create(max_streams, precision, ctypes.byref(self._b)), "pcal_batch_create")
+        self.ntones = []
+
+    def add(self, fs: int, f_comb: int, f_offset: int, nbits: int, sideband: int = 1) -> int:
+        i = ctypes.c_int()
+        _check(lib().pcal_batch_add(self._b, fs, f_comb, f_offset, nbits, sideband, ctypes.byref(i)),
+               "pcal_batch_add")
+        self.ntones.append(fs // f_comb)
+        return i.value
+
+    def member_info(self, i: int) -> dict:
+        h = ctypes.c_void_p()
+        _check(lib().pcal_batch_handle(self._b, i, ctypes.byref(h)), "pcal_batch_handle")
+        info = Info()
+        _check(lib().pcal_info(h, ctypes.byref(info)), "pcal_info")
+        return info.as_dict()
+
+    @staticmethod
+    def _ids(ids):
+        return np.ascontiguousarray(np.asarray(ids, dtype=np.int32))
+
+    def extract(self, ids, datas, nsamples, stream=None) -> None:
+        """datas: device tensors (or raw addresses); nsamples: samples per chunk."""
+        idv = self._ids(ids)
+        ptrs = np.ascontiguousarray(np.asarray([d.data_ptr() if isinstance(d, torch.Tensor) else int(d)
+                                                for d in datas], dtype=np.uint64))
+        ns = np.ascontiguousarray(np.asarray(nsamples, dtype=np.int64))
+        _check(lib().pcal_batch_extract(self._b, idv.size, idv.ctypes.data, ptrs.ctypes.data, ns.ctypes.data,
+                                        ctypes.c_void_p(_stream_handle(stream))), "pcal_batch_extract")
+
+    def _split(self, ids, flat):
+        out, o = [], 0
+        for i in ids:
+            n = self.ntones[i]
+            out.append(flat[o:o + n])
+            o += n
+        return out
+
+    def results(self, ids):
+        idv = self._ids(ids)
+        tot = sum(self.ntones[i] for i in ids)
+        amp = np.zeros(tot)
+        ph = np.zeros(tot)
+        d = np.zeros(len(ids))
+        _check(lib().pcal_batch_results(self._b, idv.size, idv.ctypes.data, amp.ctypes.data, ph.ctypes.data,
+                                        d.ctypes.data), "pcal_batch_results")
+        return self._split(ids, amp), self._split(ids, ph), d
+
+    def spectra(self, ids):
+        idv = self._ids(ids)
+        tot = sum(self.ntones[i] for i in ids)
+        re = np.zeros(tot)
+        im = np.zeros(tot)
+        _check(lib().pcal_batch_spectra(self._b, idv.size, idv.ctypes.data, re.ctypes.data, im.ctypes.data),
+               "pcal_batch_spectra")
+        return self._split(ids, re + 1j * im)
+
+    def reset(self, ids) -> None:
+        idv = self._ids(ids)
+        _check(lib().pcal_batch_reset(self._b, idv.size, idv.ctypes.data), "pcal_batch_reset")
+
+    def close(self) -> None:
+        if self._b and self._b.value:
+            _check(lib().pcal_batch_destroy(self._b), "pcal_batch_destroy")
+            self._b = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -53,10 +53,10 @@ def _walk(info, L):
     return np.concatenate(out_b), np.concatenate(out_t), np.concatenate(out_v)
 
 
-def _geometry(fs, fc, fo, nbits, nsamples, addr_low=0, before=0):
-    info = pcal.plan(fs, fc, fo, nbits)
-    L = pcal.plan_launch(fs, fc, fo, nbits, nsamples, addr_low=addr_low, samples_before=before)
-    spv = 64 if nbits == 2 else 16
+def _geometry(fs, fc, fo, nbits, nsamples, addr_low=0, before=0, method=0):
+    info = pcal.plan(fs, fc, fo, nbits, method=method)
+    L = pcal.plan_launch(fs, fc, fo, nbits, nsamples, addr_low=addr_low, samples_before=before, method=method)
+    spv = (64 if nbits == 2 else 16) if info["method"] == pcal.METHOD_PERIOD_FOLD else 16
     L["tile_vecs"] = (info["lds_positions"] // spv) if info["col_tiles"] > 1 else info["row_vectors"]
     L["pos_cols"] = info["lds_positions"] // spv
     return info, L, spv
@@ -164,3 +164,51 @@ def test_emulated_arithmetic_matches_oracle(fs, fc, fo, nbits, ns, addr, before)
     want = oracle.correlate(packed, nbits, ns, fs, fc, fo, n0=before)
     scale = max(1.0, np.abs(want).max())
     assert np.max(np.abs(got - want)) <= 1e-9 * scale
+
+
+# ---------------------------------------------------------------- per-sample forms (table / recurrence)
+
+ROT_CASES = [
+    (1_024_000_000, 1_000_000, 510_000, 8, 1_000_003, 0, 0),
+    (1_024_000_000, 1_000_000, 510_000, 8, 3_000_000, 9, 123_457),
+    (64_000_000, 1_000_000, 10_000, 2, 4 * 300_001, 1, 4 * 77),
+    (64_000_000, 2_000_000, 10_007, 8, 555_555, 5, 10 ** 9 + 7),    # prime offset
+    (24_000_000, 1_000_000, 500_000, 2, 4 * 5, 3, 0),               # head and tail only
+    (48_000_000, 1_000_000, 250_000, 8, 200_000, 0, 3),             # N = 48: rows of lcm(48, 16)
+]
+
+
+@pytest.mark.parametrize("method", [2, 3])
+@pytest.mark.parametrize("fs,fc,fo,nbits,ns,addr,before", ROT_CASES)
+def test_per_sample_walk(method, fs, fc, fo, nbits, ns, addr, before):
+    if method == 2 and fo == 10_007:
+        with pytest.raises(pcal.PcalError):   # rotator period fs: no table
+            pcal.plan(fs, fc, fo, nbits, method=method)
+        return
+    info, L, spv = _geometry(fs, fc, fo, nbits, ns, addr, before, method=method)
+    assert info["method"] == method
+    N = fs // fc
+    spb = 8 // nbits
+    vb = 16 // spb                                   # bytes per thread-vector of 16 samples
+    assert L["head_bytes"] == min((vb - addr % vb) % vb, ns // spb)
+    assert L["head_bytes"] + vb * L["nvec"] + L["tail_bytes"] == ns // spb
+    assert 0 <= L["tail_bytes"] < vb
+    assert L["threads"] <= 512 and L["threads"] % 64 == 0 and L["threads"] >= L["tile_vecs"]
+    assert L["lds_bytes"] == 16 * N
+    assert (info["row_vectors"] * 16) % N == 0       # every lane keeps its bin
+    blk, thr, vec = _walk(info, L)
+    assert vec.size == L["nvec"]
+    if vec.size:
+        assert vec.min() >= 0 and vec.max() < L["nvec"] and np.unique(vec).size == vec.size
+        g0 = before + L["head_bytes"] * spb
+        c = blk % info["col_tiles"]
+        colr = c * L["tile_vecs"] + thr
+        # bin the kernel assigns to lane 0 == true bin of the sample
+        np.testing.assert_array_equal((g0 + colr * 16) % N, (g0 + vec * 16) % N)
+    assert L["q0"] == before + L["head_bytes"] * spb
+    assert L["head_q"] == before and L["tail_q"] == L["q0"] + 16 * L["nvec"]
+
+
+def test_auto_prefers_recurrence_for_long_periods():
+    assert pcal.plan(64_000_000, 1_000_000, 10_000, 2)["method"] == pcal.METHOD_PERIOD_FOLD
+    assert pcal.plan(64_000_000, 2_000_000, 10_007, 8)["method"] == pcal.METHOD_OSC

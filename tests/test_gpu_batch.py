@@ -1,0 +1,85 @@
+"""Batched form: many streams in one launch (pcal_batch_*), on the GPU.
+
+The streams are the 64-stream mix of the precision study (fs from 16 to
+512 MHz, f_offset in {0, 10, 250, 510} kHz, 2-bit).  Each member's result
+must match the FP64 oracle, and must be the same alone (its own handle, its
+own launches) and in the mix (one launch for all), within FP64 rounding;
+integer bins (f_offset = 0) must be bit-identical.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import F64_RTOL, assert_spectra, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_05993_amd import pcal
+
+    pcal.lib()
+    return pcal
+
+
+@pytest.fixture(scope="module")
+def mix():
+    specs = synth.batch_specs()
+    L = 1 << 20
+    packed = [synth.make_stream(s, L) for s in specs]
+    return specs, L, packed
+
+
+def test_batch_matches_oracle_and_single(pc, mix):
+    specs, L, packed = mix
+    devs = [torch.from_numpy(p).cuda() for p in packed]
+    ids = []
+    with pc.PCalBatch(len(specs)) as b:
+        for s in specs:
+            ids.append(b.add(s.fs, s.f_comb, s.f_offset, s.nbits))
+        # two chunks per stream, the second misaligned by 3 bytes' worth of samples
+        c1 = 4 * 77_777
+        b.extract(ids, devs, [c1] * len(ids))
+        b.extract(ids, [d.data_ptr() + c1 // 4 for d in devs], [L - c1] * len(ids))
+        Cb = b.spectra(ids)
+        amp_b, ph_b, del_b = b.results(ids)
+    say("batch of %d streams done" % len(ids))
+    for i, s in enumerate(specs):
+        Co = oracle.correlate(packed[i], 2, L, s.fs, s.f_comb, s.f_offset)
+        assert_spectra(Cb[i], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6, what="batch %d" % i)
+        ao, po, do = oracle.results(Co, L, s.fs, s.f_comb, s.f_offset)
+        assert abs(del_b[i] - do) < 1e-12, i
+        np.testing.assert_allclose(amp_b[i], ao, rtol=1e-9, atol=1e-12)
+        if i % 8 == 0:  # alone: own handle, own launch
+            with pc.PCal(s.fs, s.f_comb, s.f_offset, 2) as h:
+                h.extract(devs[i], L)
+                Cs = h.spectrum()
+            np.testing.assert_allclose(Cb[i], Cs, rtol=0, atol=1e-12 * np.abs(Cs).max())
+
+
+def test_batch_integer_bins_and_reset(pc, mix):
+    specs, L, packed = mix
+    f0 = [i for i, s in enumerate(specs) if s.f_offset == 0][:6]
+    assert f0
+    devs = [torch.from_numpy(packed[i]).cuda() for i in f0]
+    with pc.PCalBatch(8) as b:
+        ids = [b.add(specs[i].fs, specs[i].f_comb, 0, 2) for i in f0]
+        b.extract(ids, devs, [L] * len(ids))
+        b.reset(ids[:3])
+        b.extract(ids[:3], devs[:3], [L] * 3)   # second integration, global index continues at L
+        import ctypes
+        for j, i in enumerate(f0):
+            h = ctypes.c_void_p()
+            assert pc.lib().pcal_batch_handle(b._b, ids[j], ctypes.byref(h)) == 0
+            ib = np.zeros(specs[i].ntones, dtype=np.int64)
+            re = np.zeros(specs[i].ntones)
+            im = np.zeros(specs[i].ntones)
+            assert pc.lib().pcal_bins(h, re.ctypes.data, im.ctypes.data, ib.ctypes.data) == 0
+            n0 = L if j < 3 else 0
+            want = oracle.fold_int(packed[i], 2, L, specs[i].ntones, n0=n0)
+            np.testing.assert_array_equal(ib, want)

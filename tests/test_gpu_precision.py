@@ -1,0 +1,76 @@
+"""Reduced-precision forms on the GPU, through the C ABI.
+
+MIXED: FP16 rotator rows, FP32 products with Kahan-compensated per-workgroup
+sums, FP64 cross-workgroup reduction and DFT, the table's known gain divided
+out.  F32: FP32 rows, plain FP32 sums, FP32 reduction and DFT.
+
+Each form is checked twice: tightly against the oracle's rotator-form
+correlation fed with the same rounded tables (rounded here with numpy,
+independently of the library), which isolates the kernel's arithmetic; and
+against the exact FP64 oracle, whose error is reported and bounded.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import compare_spectra, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_05993_amd import pcal
+
+    pcal.lib()
+    return pcal
+
+
+def _tables(spec, info, prec):
+    fs, fo = spec.fs, spec.f_offset
+    N = spec.ntones
+    M = info["fold_period"] // N
+    u = np.exp(-2j * np.pi * ((fo * N * np.arange(M)) % fs) / fs)
+    v = np.exp(-2j * np.pi * ((fo * np.arange(N)) % fs) / fs)
+    if prec == 1:
+        uh = u.real.astype(np.float16).astype(float) + 1j * u.imag.astype(np.float16).astype(float)
+        gamma = np.mean(np.conj(u) * (uh - u))
+        return uh, v, 1.0 / (1.0 + gamma)
+    uf = u.real.astype(np.float32).astype(float) + 1j * u.imag.astype(np.float32).astype(float)
+    vf = v.real.astype(np.float32).astype(float) + 1j * v.imag.astype(np.float32).astype(float)
+    return uf, vf, 1.0
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("s", [0, 3, 4, 8, 9])
+def test_precision_form(pc, prec, s):
+    spec = synth.batch_specs()[s]
+    L = 1 << 22
+    say("precision form %d stream %d fs=%d fo=%d" % (prec, s, spec.fs, spec.f_offset))
+    packed = synth.make_stream(spec, L)
+    dev = torch.from_numpy(packed).cuda()
+    with pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2, precision=prec) as h:
+        h.extract(dev, L)
+        C = h.spectrum()
+        info = h.info()
+    u, v, gain = _tables(spec, info, prec)
+    Cr = oracle.correlate_rotator(packed, 2, L, spec.ntones, u, v) * gain
+    scale = np.abs(Cr).max()
+    err_kernel = np.abs(C - Cr).max() / scale
+    Co = oracle.correlate(packed, 2, L, spec.fs, spec.f_comb, spec.f_offset)
+    amp_e, ph_e, weak = compare_spectra(C, Co, rel_floor=1e-6)
+    say("  kernel vs rounded-table oracle: %.2e; vs FP64 oracle: amp %.2e phase %.2e rad" % (err_kernel, amp_e, ph_e))
+    if prec == 1:
+        # FP32 products and Kahan sums over at most M rows per workgroup: a few FP32 ulps
+        assert err_kernel < 2e-6
+        # FP16 rows: the residual after the gain correction is the mirror-tone
+        # leakage of the row rounding, below 2^-11 relative
+        assert amp_e < 4.9e-4 and ph_e < 4.9e-4
+    else:
+        # FP32 sums over rows, workgroups (atomics) and the N-point DFT
+        assert err_kernel < 1e-4
+        assert amp_e < 1e-3 and ph_e < 1e-3

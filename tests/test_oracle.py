@@ -348,3 +348,49 @@ def test_statistical_recovery(oracle_lib, nbits):
     phi = synth.tone_phases(spec) - np.pi / 2
     err = np.angle(np.exp(1j * (phase[k] - phi[k])))
     assert np.max(np.abs(err)) < 6 * sig / np.min(np.abs(Cexp[k])) + 1e-3
+
+
+# ---------------------------------------------------------------- correlation with a supplied rotator
+
+def _exact_tables(fs, fc, fo, rows):
+    N = fs // fc
+    u = np.exp(-2j * np.pi * ((fo * N * np.arange(rows)) % fs) / fs)
+    v = np.exp(-2j * np.pi * ((fo * np.arange(N)) % fs) / fs)
+    return u, v
+
+
+@pytest.mark.parametrize("fs,fc,fo,nbits,rows,L,n0", [
+    (64_000_000, 1_000_000, 10_000, 2, 100, 4 * 20_011, 4 * 3),
+    (16_000_000, 1_000_000, 250_000, 8, 4, 9_999, 17),
+    (24_000_000, 1_000_000, 500_000, 2, 2, 4 * 777, 0),
+])
+def test_rotator_form_with_exact_tables_is_plain_correlation(oracle_lib, fs, fc, fo, nbits, rows, L, n0):
+    """With the exact factor tables the rotator form reduces to the plain definition."""
+    rng = np.random.default_rng(rows + L)
+    packed = rng.integers(0, 256, size=L * nbits // 8, dtype=np.uint8)
+    u, v = _exact_tables(fs, fc, fo, rows)
+    got = oracle_lib.correlate_rotator(packed, nbits, L, fs // fc, u, v, n0=n0)
+    want = oracle_lib.correlate(packed, nbits, L, fs, fc, fo, n0=n0)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-10 * np.abs(_np_levels(packed, nbits, L)).sum())
+
+
+def test_rotator_form_bruteforce_rounded_tables(oracle_lib):
+    """Perturbed tables: 40-digit brute force of the rotator-form definition."""
+    fs, fc, fo, rows = 16_000_000, 1_000_000, 10_000, 100
+    N = fs // fc
+    u, v = _exact_tables(fs, fc, fo, rows)
+    u = u.real.astype(np.float16).astype(float) + 1j * u.imag.astype(np.float16).astype(float)
+    rng = np.random.default_rng(4)
+    L, n0 = 300, 4 * 401
+    packed = rng.integers(0, 256, size=L // 4, dtype=np.uint8)
+    lv = _np_levels(packed, 2, L)
+    got = oracle_lib.correlate_rotator(packed, 2, L, N, u, v, n0=n0, tones=[0, 5, 15])
+    mp.mp.dps = 40
+    for t, c in zip([0, 5, 15], got):
+        acc = mp.mpc(0)
+        for i, x in enumerate(lv):
+            q = (n0 + i) % (rows * N)
+            col, row = q % N, q // N
+            r = mp.mpc(u[row].real, u[row].imag) * mp.mpc(v[col].real, v[col].imag)
+            acc += int(x) * r * mp.expj(-2 * mp.pi * mp.mpf(t * col) / N)
+        assert abs(c - complex(acc)) < 1e-12 * np.abs(lv).sum()
