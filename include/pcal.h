@@ -110,6 +110,19 @@ int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t 
  * the handle's last stream; does not reset the accumulators. */
 int pcal_results(pcal_t h, double *amp, double *phase, double *delay);
 
+/* Asynchronous form of pcal_results for pipelined integrations: enqueues the
+ * FP64 finalize and a copy of its output to host_out on the handle's last
+ * stream and returns.  host_out (4N + 1 doubles; pinned host memory for the
+ * copy to be asynchronous) receives amp[0..N), phase[N..2N), Re C[2N..3N),
+ * Im C[3N..4N), delay[4N] once the stream has passed the copy (pcal_sync).
+ * reset != 0 also starts the next integration, in the same launch (the
+ * finalize clears the accumulators after reading them).  host_out must stay
+ * valid until then. */
+int pcal_results_async(pcal_t h, double *host_out, int reset);
+
+/* Wait until all work enqueued on the handle has finished. */
+int pcal_sync(pcal_t h);
+
 /* The raw C_k (k = 0..N-1) of the current integration, FP64 real and imaginary
  * parts (after the sideband convention).  Synchronises. */
 int pcal_spectrum(pcal_t h, double *re, double *im);
@@ -145,6 +158,12 @@ typedef struct {
     int64_t col_tiles;       /* workgroups across one fold row */
     int64_t lds_positions;   /* period positions held per workgroup */
     int64_t device_bytes;    /* device memory owned by the handle */
+    int64_t period_vectors;  /* thread-vectors per fold period */
+    int64_t tile_vectors;    /* columns of one period per workgroup */
+    int64_t target_blocks;   /* workgroups one launch aims at: for a fold handle the number of fold
+                                workgroups resident at once on its device (one wave of workgroups,
+                                each walking one block of rows); 1024 from pcal_plan; the
+                                environment variable PCAL_TARGET_BLOCKS overrides both */
 } pcal_info_t;
 
 int pcal_info(pcal_t h, pcal_info_t *info);
@@ -167,10 +186,17 @@ typedef struct {
     int64_t nvec;            /* full 16-byte vectors */
     int64_t tail_bytes;      /* bytes after the last full vector */
     int64_t rows_total;      /* rows of row_vectors vectors (last may be partial) */
-    int64_t rows_per_group;  /* rows walked by one workgroup */
+    int64_t rows_per_group;  /* rows walked by one workgroup (period fold: at most) */
     int64_t q0;              /* global index of the first vector sample, mod fold_period */
     int64_t head_q;          /* global index of the first head sample, mod fold_period */
     int64_t tail_q;          /* global index of the first tail sample, mod fold_period */
+    /* Period fold only: the full rows form groups of 5 (2-bit) or 4 (8-bit)
+     * rows; workgroup g of a column tile walks groups_per_wg groups (one more
+     * if g < extra_groups) from group g*groups_per_wg + min(g, extra_groups).
+     * Rows [odd_start, rows_total) go to the first workgroup of each tile. */
+    int64_t groups_per_wg;
+    int64_t extra_groups;
+    int64_t odd_start;
 } pcal_launch_t;
 
 int pcal_plan_launch(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int method,

@@ -72,39 +72,37 @@ FoldGeom plan_geom(int64_t Sp, int spv, int64_t max_positions, int max_threads, 
     FoldGeom g{};
     g.spv = spv;
     const int64_t W = Sp / g.spv;  // vectors per period
+    g.period_vecs = static_cast<int>(W);
     const int pref = force_threads ? force_threads : env_int("PCAL_FOLD_THREADS", 0);
-    if (Sp <= max_positions && W <= max_threads) {
-        int best_t = 0;
-        double best = -1.0;
-        for (int t = 256; t <= max_threads; t += 64) {
-            if (pref && t != pref) continue;
-            const int64_t k = t / W;
-            if (k < 1) continue;
-            const double eff = static_cast<double>(k * W) / t;
-            if (eff > best + 1e-9) {
-                best = eff;
-                best_t = t;
-            }
-        }
-        if (best_t == 0) best_t = static_cast<int>(((W + 63) / 64) * 64);
-        const int k = static_cast<int>(std::max<int64_t>(1, best_t / W));
-        g.threads = best_t;
-        g.row_vecs = static_cast<int>(k * W);
-        g.tile_vecs = g.row_vecs;
-        g.col_tiles = 1;
-        g.pos_cols = static_cast<int>(W);
-        g.npos = static_cast<int>(Sp);
-    } else {
-        const int tile_max = static_cast<int>(std::min<int64_t>(max_threads, max_positions / g.spv));
+    // columns of one period per workgroup: the whole period when it fits the
+    // LDS position budget and the workgroup, else equal tiles within both
+    int64_t tile = W;
+    if (Sp > max_positions || W > max_threads) {
+        const int64_t tile_max = std::min<int64_t>(max_threads, max_positions / g.spv);
         const int64_t tiles = (W + tile_max - 1) / tile_max;
-        const int64_t tile = (W + tiles - 1) / tiles;
-        g.row_vecs = static_cast<int>(W);
-        g.tile_vecs = static_cast<int>(tile);
-        g.col_tiles = static_cast<int>(tiles);
-        g.pos_cols = g.tile_vecs;
-        g.npos = static_cast<int>(std::min<int64_t>(int64_t(g.tile_vecs) * g.spv, INT32_MAX));
-        g.threads = static_cast<int>(((tile + 63) / 64) * 64);
+        tile = (W + tiles - 1) / tiles;
     }
+    g.tile_vecs = static_cast<int>(tile);
+    g.col_tiles = static_cast<int>((W + tile - 1) / tile);
+    g.pos_cols = g.tile_vecs;
+    g.npos = static_cast<int>(tile * g.spv);
+    // workgroup size: k sub-rows of one tile each, wasting the fewest lanes
+    int best_t = 0;
+    double best = -1.0;
+    for (int t = 256; t <= max_threads; t += 64) {
+        if (pref && t != pref) continue;
+        const int64_t k = t / tile;
+        if (k < 1) continue;
+        const double eff = static_cast<double>(k * tile) / t;
+        if (eff > best + 1e-9) {
+            best = eff;
+            best_t = t;
+        }
+    }
+    if (best_t == 0) best_t = static_cast<int>(((tile + 63) / 64) * 64);
+    const int64_t k = std::max<int64_t>(1, best_t / tile);
+    g.threads = best_t;
+    g.row_vecs = static_cast<int>(k * W);
     return g;
 }
 
@@ -142,8 +140,13 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
         const int64_t per = p->N / gcd64(p->N, kRotLanes) * kRotLanes;
         p->geom = plan_geom(per, kRotLanes, INT64_MAX, kMaxRotThreads, force_threads);
     }
-    p->target_blocks = env_int("PCAL_TARGET_BLOCKS", 1024);
-    if (p->target_blocks < 1) p->target_blocks = 1;
+    {
+        const int sp = env_int("PCAL_SYNC_PAIRS", kSyncPairs);  // power of two or 0
+        p->sync_pairs = (sp > 0 && (sp & (sp - 1)) == 0) ? sp : 0;
+    }
+    p->target_blocks = env_int("PCAL_TARGET_BLOCKS", 0);
+    p->target_from_env = p->target_blocks > 0;
+    if (!p->target_from_env) p->target_blocks = 1024;
     p->max_blocks = std::max(p->geom.col_tiles, p->target_blocks) + p->geom.col_tiles;
     return PCAL_OK;
 }
@@ -164,9 +167,26 @@ pcal_launch_t plan_launch(const Plan &p, uint64_t addr, int64_t n_before, int64_
     L.rows_total = (L.nvec + g.row_vecs - 1) / g.row_vecs;
     const int64_t groups_want = std::max<int64_t>(1, (target_blocks ? target_blocks : p.target_blocks) / g.col_tiles);
     const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(groups_want, L.rows_total));
-    L.rows_per_group = L.rows_total > 0 ? (L.rows_total + groups - 1) / groups : 1;
-    const int64_t ngroups = L.rows_total > 0 ? (L.rows_total + L.rows_per_group - 1) / L.rows_per_group : 1;
-    L.grid = ngroups * g.col_tiles;
+    if (p.method == PCAL_METHOD_PERIOD_FOLD) {
+        // The full rows in groups of whole walker groups (5 rows at 2-bit, 4 at
+        // 8-bit), split as evenly as groups allow over the workgroups of a tile;
+        // the rows after the last group go to the first workgroup of each tile.
+        const int64_t unit = p.nbits == 2 ? 5 : 4;
+        const int64_t wgroups = L.nvec / g.row_vecs / unit;  // whole walker groups of full rows
+        const int64_t fgroups = std::max<int64_t>(1, std::min<int64_t>(groups, wgroups));
+        L.grid = fgroups * g.col_tiles;
+        L.groups_per_wg = wgroups / fgroups;
+        L.extra_groups = wgroups % fgroups;
+        L.odd_start = wgroups * unit;
+        L.rows_per_group = unit * (L.groups_per_wg + (L.extra_groups ? 1 : 0));
+    } else {
+        L.rows_per_group = L.rows_total > 0 ? (L.rows_total + groups - 1) / groups : 1;
+        const int64_t ngroups = L.rows_total > 0 ? (L.rows_total + L.rows_per_group - 1) / L.rows_per_group : 1;
+        L.grid = ngroups * g.col_tiles;
+        L.groups_per_wg = 0;
+        L.extra_groups = 0;
+        L.odd_start = L.rows_total;
+    }
     L.threads = g.threads;
     if (p.method == PCAL_METHOD_PERIOD_FOLD) {
         L.lds_bytes = static_cast<int64_t>(fold_lds_bytes(g.npos, g.spv, g.threads, p.M));
@@ -194,6 +214,9 @@ void fill_info(const Plan &p, pcal_info_t *info) {
     info->row_vectors = p.geom.row_vecs;
     info->col_tiles = p.geom.col_tiles;
     info->lds_positions = p.geom.npos;
+    info->period_vectors = p.geom.period_vecs;
+    info->tile_vectors = p.geom.tile_vecs;
+    info->target_blocks = p.target_blocks;
 }
 
 
@@ -338,12 +361,13 @@ int build(pcal_ctx *h) {
 
 // Order work on `s` after the handle's previous work (possibly on another stream).
 int order_on(pcal_ctx *h, hipStream_t s) {
-    if (h->have_ev && s != h->last_stream) PCAL_HIP(hipStreamWaitEvent(s, h->ev, 0));
+    if (h->have_ev && s != h->last_stream) PCAL_HIP(hipStreamWaitEvent(s, h->wait_ev, 0));
     return PCAL_OK;
 }
 
 int mark(pcal_ctx *h, hipStream_t s) {
     PCAL_HIP(hipEventRecord(h->ev, s));
+    h->wait_ev = h->ev;
     h->have_ev = true;
     h->last_stream = s;
     return PCAL_OK;
@@ -379,6 +403,10 @@ FinArgs fin_args(const pcal_ctx *h, double *out) {
     f.gain_im = h->gain_im;
     f.out = out;
     f.counter = h->counters;
+    f.clear = 0;
+    f.acc_clear = h->acc;
+    f.accf_clear = h->accf;
+    f.acc_int_clear = h->acc_int;
     return f;
 }
 
@@ -392,7 +420,7 @@ int run_finalize(pcal_ctx *h) {
     return PCAL_OK;
 }
 
-FoldArgs fold_args(const pcal_ctx *h, const pcal_launch_t &L, const void *dev_ptr) {
+FoldArgs fold_args(pcal_ctx *h, const pcal_launch_t &L, const void *dev_ptr) {
     const Plan &p = h->plan;
     const FoldGeom &g = p.geom;
     FoldArgs a{};
@@ -405,6 +433,7 @@ FoldArgs fold_args(const pcal_ctx *h, const pcal_launch_t &L, const void *dev_pt
     a.col_tiles = g.col_tiles;
     a.pos_cols = g.pos_cols;
     a.npos = g.npos;
+    a.period_vecs = g.period_vecs;
     a.N = static_cast<int>(p.N);
     a.nbits = p.nbits;
     a.prec = p.prec;
@@ -425,6 +454,10 @@ FoldArgs fold_args(const pcal_ctx *h, const pcal_launch_t &L, const void *dev_pt
     a.acc = h->acc;
     a.acc_int = h->acc_int;
     a.accf = h->accf;
+    a.groups_per_wg = L.groups_per_wg;
+    a.extra_groups = L.extra_groups;
+    a.odd_start = L.odd_start;
+    a.sync_pairs = p.sync_pairs;
     return a;
 }
 
@@ -442,6 +475,18 @@ int create(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int meth
         set_error("hipGetDevice", e);
         delete h;
         return PCAL_EHIP;
+    }
+    if (p.method == PCAL_METHOD_PERIOD_FOLD && !p.target_from_env) {
+        // persistent grid: as many fold workgroups as the device holds at once, so
+        // that the rows claimed at run time go to whichever finishes first
+        int cus = 0;
+        const int per_cu = fold_blocks_per_cu(p.nbits, p.prec, p.geom.threads,
+                                              fold_lds_bytes(p.geom.npos, p.geom.spv, p.geom.threads, p.M));
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+            per_cu > 0 && cus > 0) {
+            h->plan.target_blocks = std::max(per_cu * cus, h->plan.geom.col_tiles);
+            h->plan.max_blocks = std::max(h->plan.geom.col_tiles, h->plan.target_blocks) + h->plan.geom.col_tiles;
+        }
     }
     rc = build(h);
     if (rc) {
@@ -521,6 +566,7 @@ int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t 
         a.row_vecs = g.row_vecs;
         a.tile_vecs = g.tile_vecs;
         a.col_tiles = g.col_tiles;
+        a.period_vecs = g.period_vecs;
         a.N = static_cast<int>(p.N);
         a.nbits = p.nbits;
         a.prec = p.prec;
@@ -559,6 +605,27 @@ int pcal_results(pcal_t h, double *amp, double *phase, double *delay) {
     if (amp) memcpy(amp, h->host_out, sizeof(double) * N);
     if (phase) memcpy(phase, h->host_out + N, sizeof(double) * N);
     if (delay) *delay = h->host_out[4 * N];
+    return PCAL_OK;
+}
+
+int pcal_results_async(pcal_t h, double *host_out, int reset) {
+    if (!h || !host_out) return PCAL_EINVAL;
+    DeviceGuard guard(h->device);
+    const Plan &p = h->plan;
+    hipStream_t s = h->last_stream;
+    FinArgs f = fin_args(h, h->out);
+    f.clear = reset ? 1 : 0;
+    launch_finalize(f, s);
+    PCAL_HIP(hipGetLastError());
+    PCAL_HIP(hipMemcpyAsync(host_out, h->out, sizeof(double) * (4 * p.N + 1), hipMemcpyDeviceToHost, s));
+    if (reset) h->n_integ = 0;
+    return mark(h, s);
+}
+
+int pcal_sync(pcal_t h) {
+    if (!h) return PCAL_EINVAL;
+    DeviceGuard guard(h->device);
+    if (h->have_ev) PCAL_HIP(hipEventSynchronize(h->wait_ev));
     return PCAL_OK;
 }
 
@@ -631,7 +698,7 @@ int pcal_destroy(pcal_t h) {
     if (!h) return PCAL_EINVAL;
     {
         DeviceGuard guard(h->device);
-        if (h->have_ev) (void)hipEventSynchronize(h->ev);
+        if (h->have_ev) (void)hipEventSynchronize(h->wait_ev);
         release(h);
     }
     return PCAL_OK;

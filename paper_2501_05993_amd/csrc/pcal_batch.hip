@@ -45,6 +45,7 @@ struct pcal_batch_ctx {
     double *h_out = nullptr;   // pinned copy
     size_t out_cap = 0;        // doubles
     hipStream_t last_stream = nullptr;
+    hipEvent_t ev = nullptr;   // recorded after each batched call
 };
 
 namespace {
@@ -102,10 +103,14 @@ int order_members(pcal_batch_ctx *b, int count, const int *ids, hipStream_t s) {
     return PCAL_OK;
 }
 
+// One event for the whole call: each member's last work is at or before it.
 int mark_members(pcal_batch_ctx *b, int count, const int *ids, hipStream_t s) {
+    PCAL_HIP(hipEventRecord(b->ev, s));
     for (int i = 0; i < count; ++i) {
-        const int rc = mark(b->members[ids[i]], s);
-        if (rc) return rc;
+        pcal_ctx *h = b->members[ids[i]];
+        h->wait_ev = b->ev;
+        h->have_ev = true;
+        h->last_stream = s;
     }
     b->last_stream = s;
     return PCAL_OK;
@@ -122,6 +127,14 @@ int pcal_batch_create(int max_streams, int precision, pcal_batch_t *out) {
     if (!b) return PCAL_ENOMEM;
     b->prec = precision;
     b->max_streams = max_streams;
+    {
+        hipError_t e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            set_error("hipEventCreateWithFlags", e);
+            delete b;
+            return PCAL_EHIP;
+        }
+    }
     for (int i = 0; i < kStages; ++i) {
         const int rc = stage_alloc(b->stage[i], max_streams);
         if (rc) {
@@ -312,6 +325,7 @@ int pcal_batch_size(pcal_batch_t b, int *n) {
 
 int pcal_batch_destroy(pcal_batch_t b) {
     if (!b) return PCAL_EINVAL;
+    if (b->ev) (void)hipEventSynchronize(b->ev);
     for (pcal_ctx *h : b->members) pcal_destroy(h);
     for (int i = 0; i < kStages; ++i) {
         if (b->stage[i].pending) (void)hipEventSynchronize(b->stage[i].done);
@@ -319,6 +333,7 @@ int pcal_batch_destroy(pcal_batch_t b) {
     }
     if (b->d_out) (void)hipFree(b->d_out);
     if (b->h_out) (void)hipHostFree(b->h_out);
+    if (b->ev) (void)hipEventDestroy(b->ev);
     delete b;
     return PCAL_OK;
 }

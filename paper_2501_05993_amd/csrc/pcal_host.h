@@ -32,9 +32,12 @@ struct Plan {
     int64_t N, R, S, Sp, M;
     FoldGeom geom;
     int target_blocks;
+    int sync_pairs;   // fold walk: workgroup barrier every sync_pairs pairs of groups (0: none)
+    bool target_from_env;  // PCAL_TARGET_BLOCKS set: keep it on every device
     int max_blocks;
 };
 
+constexpr int kSyncPairs = 1;  // fold walk: a workgroup barrier after every pair of groups (PCAL_SYNC_PAIRS)
 constexpr int64_t kMaxFoldPeriod = int64_t(1) << 26;  // S' samples
 constexpr int64_t kMaxTableRows = int64_t(1) << 20;   // u table entries
 constexpr int64_t kMaxLutPeriod = int64_t(1) << 24;   // rotator table entries (table method)
@@ -74,7 +77,8 @@ struct pcal_ctx {
     int64_t n_total = 0;
     int64_t n_integ = 0;
     hipStream_t last_stream = nullptr;
-    hipEvent_t ev = nullptr;
+    hipEvent_t ev = nullptr;       // recorded after the handle's own calls
+    hipEvent_t wait_ev = nullptr;  // event marking the handle's last work (ev, or a batch's event)
     bool have_ev = false;
     size_t device_bytes = 0;
 };
@@ -89,8 +93,9 @@ int create(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int meth
 // Order work on `s` after the handle's previous work; record it as the handle's last work.
 int order_on(pcal_ctx *h, hipStream_t s);
 int mark(pcal_ctx *h, hipStream_t s);
-// Kernel arguments of one extract call of a period-fold handle.
-FoldArgs fold_args(const pcal_ctx *h, const pcal_launch_t &L, const void *dev_ptr);
+// Kernel arguments of one extract call of a period-fold handle (advances the
+// handle's chunk-counter base past the launch).
+FoldArgs fold_args(pcal_ctx *h, const pcal_launch_t &L, const void *dev_ptr);
 // Finalize arguments writing to `out` (4N + 1 doubles).
 FinArgs fin_args(const pcal_ctx *h, double *out);
 

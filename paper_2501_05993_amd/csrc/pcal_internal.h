@@ -20,7 +20,7 @@ constexpr int kEpilogueScratch = 40;
 // kAccSlots), summed by the finalize: spreads same-address atomics.
 constexpr int kAccSlots = 16;
 // Largest workgroup of the fold kernel.
-constexpr int kMaxFoldThreads = 1024;
+constexpr int kMaxFoldThreads = 768;
 // Largest workgroup of the per-sample rotation kernels (they keep 16 complex lanes
 // and their totals in registers).
 constexpr int kMaxRotThreads = 512;
@@ -34,21 +34,29 @@ constexpr int kMaxTones = 4096;
 // the same column of successive rows always meets the same period positions and can
 // keep one integer counter per position in registers.  A row is split into
 // `col_tiles` tiles of `tile_vecs` columns, one thread per column.
+//
+// Thread t of a workgroup on column tile c reads column c*tile_vecs + t%tile_vecs
+// of period t/tile_vecs of every row: a row holds row_vecs/period_vecs periods
+// (sub-rows), so tiles narrower than the workgroup still use all its threads.
 struct FoldGeom {
-    int spv;         // samples per vector (64 at 2-bit, 16 at 8-bit)
-    int row_vecs;    // vectors per row (a multiple of S'/spv)
-    int tile_vecs;   // columns per workgroup
-    int col_tiles;   // workgroups across a row
-    int pos_cols;    // columns per distinct set of positions (S'/spv when one tile holds the period)
-    int npos;        // period positions held per workgroup = pos_cols * spv
-    int threads;     // workgroup size (multiple of 64, >= tile_vecs)
+    int spv;          // samples per vector (64 at 2-bit fold, 16 otherwise)
+    int period_vecs;  // vectors per fold period (S'/spv)
+    int row_vecs;     // vectors per row (a multiple of period_vecs)
+    int tile_vecs;    // columns of one period per workgroup
+    int col_tiles;    // workgroups across a period
+    int pos_cols;     // = tile_vecs: columns with distinct period positions
+    int npos;         // period positions held per workgroup = tile_vecs * spv
+    int threads;      // workgroup size (multiple of 64, >= tile_vecs)
 };
 
 // Dynamic LDS of the fold kernel: skewed position sums (one pad word per vector)
 // overlaid by the epilogue scratch, then the rotator rows when they fit.
+// LDS in front of the rotator table: the skewed position sums plus one spare
+// column of spv + 1 words (the sink of the lanes that walk no column), reused
+// by the epilogue as scratch of kEpilogueScratch bytes per thread.
 __host__ __device__ constexpr size_t fold_front_bytes(int npos, int spv, int threads) {
-    return ((static_cast<size_t>(npos + npos / spv) * 4 > static_cast<size_t>(threads) * kEpilogueScratch
-                 ? static_cast<size_t>(npos + npos / spv) * 4
+    return ((static_cast<size_t>(npos + npos / spv + spv + 1) * 4 > static_cast<size_t>(threads) * kEpilogueScratch
+                 ? static_cast<size_t>(npos + npos / spv + spv + 1) * 4
                  : static_cast<size_t>(threads) * kEpilogueScratch) +
             15) & ~static_cast<size_t>(15);
 }
@@ -61,8 +69,9 @@ struct FoldArgs {
     const uint4 *data;       // 16-byte aligned start of the full vectors
     int64_t nvec;            // number of full vectors at data
     int64_t rows_total;      // ceil(nvec / row_vecs)
-    int64_t rows_per_group;  // rows walked by one workgroup
+    int64_t rows_per_group;  // rows per workgroup (per-sample forms)
     int row_vecs, tile_vecs, col_tiles, pos_cols, npos;
+    int period_vecs;         // vectors per fold period
     int N;                   // tones = bins
     int nbits;               // 2 or 8
     int prec;                // enum pcal_precision
@@ -81,6 +90,13 @@ struct FoldArgs {
     const uint8_t *tail;
     int tail_bytes;
     int64_t tail_q;
+    // Row layout of the fold walk: the full rows form groups of 5 (2-bit) or 4
+    // (8-bit) rows; workgroup g of a column tile walks groups_per_wg groups from
+    // row R*(g*groups_per_wg + min(g, extra_groups)), one more if g <
+    // extra_groups.  Rows [odd_start, rows_total) go to the first workgroup of
+    // each tile.
+    int64_t groups_per_wg, extra_groups, odd_start;
+    int sync_pairs;          // a workgroup barrier every sync_pairs pairs of groups (power of 2; 0: none)
     // Integration accumulators of the handle (each workgroup adds its bins atomically).
     double2 *acc;            // [kAccSlots][N] rotated, folded bins P[b], FP64
     float2 *accf;            // [kAccSlots][N] the same in FP32 (PREC_F32 form)
@@ -92,6 +108,7 @@ struct RotArgs {
     const void *data;        // aligned start of the full thread-vectors (16 samples each)
     int64_t nvec, rows_total, rows_per_group;
     int row_vecs, tile_vecs, col_tiles;
+    int period_vecs;
     int N, nbits, prec, method;
     int64_t g0;              // global index of the first full-vector sample
     int64_t fs, fo, R;       // Hz, Hz, rotator period (Eq. 4)
@@ -124,9 +141,15 @@ struct FinArgs {
     double gain_re, gain_im; // C_k is multiplied by this (1 / (1 + gamma) in the mixed form, else 1)
     double *out;             // [4N + 1]: amp, phase, re, im, delay
     unsigned *counter;
+    int clear;               // zero the accumulators afterwards (next integration)
+    double2 *acc_clear;      // the accumulators to zero ([kAccSlots][N] each)
+    float2 *accf_clear;
+    long long *acc_int_clear;
 };
 
 void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds, hipStream_t s);
+// Fold workgroups of the given shape resident at once on one compute unit (0 on error).
+int fold_blocks_per_cu(int nbits, int prec, int threads, size_t lds);
 void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int prec, int grid, int threads,
                        size_t lds, hipStream_t s);
 void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStream_t s);

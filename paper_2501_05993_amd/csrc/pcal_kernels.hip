@@ -19,6 +19,8 @@
 // and sums the 2-bit codes (or biased 8-bit values) of its 64 (16) positions
 // in SWAR lanes of ordinary registers: the inner loop is a few integer
 // operations per 32-bit word, well under the HBM time of the data it reads.
+#include <type_traits>
+
 #include "pcal_internal.h"
 
 namespace pcal {
@@ -105,50 +107,79 @@ __device__ __forceinline__ void add_codes(uint4 x, uint32_t (&lo)[4], uint32_t (
     hi[3] += (x.w >> 2) & kM33;
 }
 
-// Walk rows [r0, r1) of column colr, 2-bit samples.  Nibble lanes take five
-// rows of codes (max 15), byte lanes seventeen nibble flushes (max 255).
-__device__ void walk2(const FoldArgs &a, int colr, int64_t r0, int64_t r1, int *Fp) {
-    const uint4 *__restrict__ col = a.data + colr;
-    const int64_t stride = a.row_vecs;
-    const int64_t rfull = a.nvec / stride;
-    const bool last_ok = colr < a.nvec - rfull * stride;
-    const int64_t rend_fast = r1 < rfull ? r1 : rfull;  // rows with every column present
-    uint32_t bq[4][4] = {};
-    int cnt = 0, groups = 0;
-    int64_t r = r0;
-    for (; r + 5 <= rend_fast; r += 5) {
-        uint4 x[5];
+struct Walk2 {
+    const uint4 *col;
+    int64_t stride, rfull;
+    bool last_ok;
+    int *Fp;
+    uint32_t bq[4][4];
+    int cnt, spreads;
+
+    static constexpr int kRows = 5;  // rows of one group
+    struct Buf {
+        uint4 v[5];
+    };
+
+    __device__ __forceinline__ void init(const FoldArgs &a, int colr, int *fp) {
+        col = a.data + colr;
+        stride = a.row_vecs;
+        rfull = a.nvec / stride;
+        last_ok = colr < a.nvec - rfull * stride;
+        Fp = fp;
 #pragma unroll
-        for (int u = 0; u < 5; ++u) x[u] = load_stream(col + (r + u) * stride);
-        uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
+        for (int w = 0; w < 4; ++w)
 #pragma unroll
-        for (int u = 0; u < 5; ++u) add_codes(x[u], lo, hi);
-#pragma unroll
-        for (int w = 0; w < 4; ++w) nibbles_to_bytes(lo[w], hi[w], bq[w]);
-        cnt += 5;
-        if (++groups == 17) {
+            for (int q = 0; q < 4; ++q) bq[w][q] = 0u;
+        cnt = spreads = 0;
+    }
+    __device__ __forceinline__ void spread(const uint32_t (&lo)[4], const uint32_t (&hi)[4]) {
+        if (spreads == 17) {
             flush2(bq, cnt, Fp);
             cnt = 0;
-            groups = 0;
+            spreads = 0;
         }
-    }
-    // remaining rows, one at a time (at most 4 full rows plus a partial one)
-    uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
-    int nib = 0;
-    for (; r < r1; ++r) {
-        const bool ok = r < rfull || (r == rfull && last_ok);
-        if (ok) {
-            add_codes(load_stream(col + r * stride), lo, hi);
-            ++cnt;
-            ++nib;
-        }
-    }
-    if (nib) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) nibbles_to_bytes(lo[w], hi[w], bq[w]);
+        ++spreads;
     }
-    if (cnt) flush2(bq, cnt, Fp);
-}
+    // loads of the five full rows [r, r + 5)
+    __device__ __forceinline__ void load_group(Buf &b, int64_t r) const {
+#pragma unroll
+        for (int u = 0; u < 5; ++u) b.v[u] = load_stream(col + (r + u) * stride);
+    }
+    __device__ __forceinline__ void take(const Buf &b) {
+        uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int u = 0; u < 5; ++u) add_codes(b.v[u], lo, hi);
+        spread(lo, hi);
+        cnt += 5;
+    }
+    // rows [r0, r1) of this column, one at a time (the last row of the stream
+    // may be partial): the odd rows around the grouped walk
+    __device__ void rows(int64_t r0, int64_t r1) {
+        uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
+        int nib = 0;
+        for (int64_t r = r0; r < r1; ++r) {
+            if (r < rfull || (r == rfull && last_ok)) {
+                add_codes(load_stream(col + r * stride), lo, hi);
+                if (++nib == 5) {
+                    spread(lo, hi);
+                    cnt += 5;
+                    nib = 0;
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) lo[w] = hi[w] = 0u;
+                }
+            }
+        }
+        if (nib) {
+            spread(lo, hi);
+            cnt += nib;
+        }
+    }
+    __device__ __forceinline__ void finish() {
+        if (cnt) flush2(bq, cnt, Fp);
+    }
+};
 
 // ---------------------------------------------------------------- 8-bit rows
 
@@ -179,39 +210,57 @@ __device__ __forceinline__ void flush8(uint32_t (&e)[4], uint32_t (&o)[4], int c
     }
 }
 
-__device__ void walk8(const FoldArgs &a, int colr, int64_t r0, int64_t r1, int *Fp) {
-    const uint4 *__restrict__ col = a.data + colr;
-    const int64_t stride = a.row_vecs;
-    const int64_t rfull = a.nvec / stride;
-    const bool last_ok = colr < a.nvec - rfull * stride;
-    const int64_t rend_fast = r1 < rfull ? r1 : rfull;
-    uint32_t e[4] = {0u, 0u, 0u, 0u}, o[4] = {0u, 0u, 0u, 0u};
-    int cnt = 0;
-    int64_t r = r0;
-    for (; r + 8 <= rend_fast; r += 8) {
-        uint4 x[8];
+// One thread's column walk over 8-bit rows: biased sums of its 16 positions in
+// 16-bit lanes, 256 rows per flush to LDS.
+constexpr int kGroup8 = 4;  // rows loaded together
+
+struct Walk8 {
+    const uint4 *col;
+    int64_t stride, rfull;
+    bool last_ok;
+    int *Fp;
+    uint32_t e[4], o[4];
+    int cnt;
+
+    static constexpr int kRows = kGroup8;
+    struct Buf {
+        uint4 v[kGroup8];
+    };
+
+    __device__ __forceinline__ void init(const FoldArgs &a, int colr, int *fp) {
+        col = a.data + colr;
+        stride = a.row_vecs;
+        rfull = a.nvec / stride;
+        last_ok = colr < a.nvec - rfull * stride;
+        Fp = fp;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = load_stream(col + (r + u) * stride);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) add_bytes(x[u], e, o);
-        cnt += 8;
+        for (int w = 0; w < 4; ++w) e[w] = o[w] = 0u;
+        cnt = 0;
+    }
+    __device__ __forceinline__ void add(const uint4 &x) {
         if (cnt == 256) {
             flush8(e, o, cnt, Fp);
             cnt = 0;
         }
+        add_bytes(x, e, o);
+        ++cnt;
     }
-    for (; r < r1; ++r) {
-        const bool ok = r < rfull || (r == rfull && last_ok);
-        if (ok) {
-            add_bytes(load_stream(col + r * stride), e, o);
-            if (++cnt == 256) {
-                flush8(e, o, cnt, Fp);
-                cnt = 0;
-            }
-        }
+    __device__ __forceinline__ void load_group(Buf &b, int64_t r) const {
+#pragma unroll
+        for (int u = 0; u < kGroup8; ++u) b.v[u] = load_stream(col + (r + u) * stride);
     }
-    if (cnt) flush8(e, o, cnt, Fp);
-}
+    __device__ __forceinline__ void take(const Buf &b) {
+#pragma unroll
+        for (int u = 0; u < kGroup8; ++u) add(b.v[u]);
+    }
+    __device__ void rows(int64_t r0, int64_t r1) {
+        for (int64_t r = r0; r < r1; ++r)
+            if (r < rfull || (r == rfull && last_ok)) add(load_stream(col + r * stride));
+    }
+    __device__ __forceinline__ void finish() {
+        if (cnt) flush8(e, o, cnt, Fp);
+    }
+};
 
 // ---------------------------------------------------------------- per-workgroup bins
 
@@ -361,21 +410,48 @@ __device__ __forceinline__ void fold_body(const FoldArgs &a, const int wg, unsig
 #pragma unroll
     for (int j = 0; j < kPre; ++j)
         if (u_lds && t + j * nt < M) upre[j] = table_row<PREC>(a, t + j * nt);
-    for (int i = t; i < npos_sk; i += nt) F[i] = 0;
-    __syncthreads();
 
     const int c = wg % a.col_tiles;
     const int64_t g = wg / a.col_tiles;
-    const int colr = c * a.tile_vecs + t;
-    const int64_t r0 = g * a.rows_per_group;
-    const int64_t r1 = (r0 + a.rows_per_group) < a.rows_total ? (r0 + a.rows_per_group) : a.rows_total;
-    if (t < a.tile_vecs && colr < a.row_vecs && r0 < r1) {
-        int *Fp = F + (t % a.pos_cols) * (SPV + 1);
-        if constexpr (NBITS == 2)
-            walk2(a, colr, r0, r1, Fp);
-        else
-            walk8(a, colr, r0, r1, Fp);
+    const int tc = t % a.tile_vecs, sub = t / a.tile_vecs;
+    const int colp = c * a.tile_vecs + tc;                 // column within the period
+    const int colr = colp + sub * a.period_vecs;           // column within the row
+    const bool active = colp < a.period_vecs && colr < a.row_vecs;
+    // Workgroup g of the tile walks its block of whole groups of rows; the rows
+    // after the last whole group (with the partial last row) go to the first
+    // workgroup of each tile.  Each wave keeps two groups of rows in flight
+    // throughout (buffers A and B in turn): the loads of the next group are
+    // issued before the current one is added.
+    using W = typename std::conditional<NBITS == 2, Walk2, Walk8>::type;
+    constexpr int R = W::kRows;
+    const int64_t r0 = R * (g * a.groups_per_wg + (g < a.extra_groups ? g : a.extra_groups));
+    const int64_t r1 = r0 + R * (a.groups_per_wg + (g < a.extra_groups ? 1 : 0));
+    // Lanes that walk no column load column 0 and add into a spare LDS column,
+    // so that the walk has no divergent branch: the compiler's wait counting
+    // then keeps both groups in flight.
+    W walk;
+    walk.init(a, active ? colr : 0, active ? F + tc * (SPV + 1) : F + npos_sk);
+    typename W::Buf A, B;
+    const int64_t ngr = (r1 - r0) / R;  // groups of this workgroup
+    if (ngr > 0) walk.load_group(A, r0);
+    for (int j = t; j < npos_sk; j += nt) F[j] = 0;
+    __syncthreads();
+    if (g == 0 && active) walk.rows(a.odd_start, a.rows_total);
+    // group i in A, i + 1 in B; past the last group the loads repeat one (never
+    // added).  A barrier every few pairs keeps the waves in step: waves that
+    // ran ahead would otherwise leave the last stretch to a few waves with few
+    // loads in flight.  (A bare s_barrier: no fence, so no wait on the loads.)
+    const int sync_mask = a.sync_pairs > 0 ? a.sync_pairs - 1 : -1;
+    for (int64_t i = 0; i + 1 < ngr; i += 2) {
+        const int64_t q = r0 + i * R;
+        walk.load_group(B, q + R);
+        walk.take(A);
+        walk.load_group(A, i + 2 < ngr ? q + 2 * R : q + R);
+        walk.take(B);
+        if (sync_mask >= 0 && ((i >> 1) & sync_mask) == sync_mask) __builtin_amdgcn_s_barrier();
     }
+    if (ngr & 1) walk.take(A);
+    if (active) walk.finish();
     if (u_lds) {
 #pragma unroll
         for (int j = 0; j < kPre; ++j)
@@ -489,6 +565,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
         // add the accumulator slots in slot order
         double re = 0.0, im = 0.0;
         float fr = 0.f, fi = 0.f;
+#pragma unroll
         for (int k = 0; k < kAccSlots; ++k) {
             if (f32) {
                 fr += a.accf[k * N + i].x;
@@ -581,19 +658,21 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
         const double d = ph[i] - ph[i - 1];
         dsum += d - two_pi * rint(d / two_pi);
     }
-    sh[t] = dsum;
-    __syncthreads();
-    if (t == 0) {  // exclusive prefix of segment sums, in order
-        double run = 0.0;
-        for (int i = 0; i < 256; ++i) {
-            const double v = sh[i];
-            sh[i] = run;
-            run += v;
-        }
+    // exclusive prefix of the segment sums: scan inside each wave, then add the
+    // totals of the waves before (fixed order: deterministic)
+    double incl = dsum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
     }
+    if (lane == 63) sh[wave] = incl;
     __syncthreads();
+    double before = 0.0;
+    for (int w = 0; w < wave; ++w) before += sh[w];
+    const double excl = before + incl - dsum;
     const double kbar = 0.5 * static_cast<double>(n - 1);
-    double unw = (n > 0 ? ph[0] : 0.0) + sh[t];
+    double unw = (n > 0 ? ph[0] : 0.0) + excl;
     double sxu = 0.0;
     for (int i = s0; i < s1; ++i) {
         if (i > 0) {
@@ -617,6 +696,14 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
             delay = sh[0] / sxx / a.f_comb / two_pi;
         }
         a.out[4 * N] = delay;
+    }
+    if (a.clear) {
+        // start the next integration: every workgroup has read the bins
+        for (int i = t; i < kAccSlots * N; i += 256) {
+            a.acc_clear[i] = make_double2(0.0, 0.0);
+            a.accf_clear[i] = make_float2(0.f, 0.f);
+            a.acc_int_clear[i] = 0;
+        }
     }
 }
 
@@ -663,6 +750,21 @@ void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds
         else if (a.prec == 1) hipLaunchKernelGGL((fold_kernel<8, 1>), gd, bd, lds, s, a);
         else hipLaunchKernelGGL((fold_kernel<8, 2>), gd, bd, lds, s, a);
     }
+}
+
+int fold_blocks_per_cu(int nbits, int prec, int threads, size_t lds) {
+    const void *f = nullptr;
+    if (nbits == 2)
+        f = prec == 0 ? reinterpret_cast<const void *>(&fold_kernel<2, 0>)
+            : prec == 1 ? reinterpret_cast<const void *>(&fold_kernel<2, 1>)
+                        : reinterpret_cast<const void *>(&fold_kernel<2, 2>);
+    else
+        f = prec == 0 ? reinterpret_cast<const void *>(&fold_kernel<8, 0>)
+            : prec == 1 ? reinterpret_cast<const void *>(&fold_kernel<8, 1>)
+                        : reinterpret_cast<const void *>(&fold_kernel<8, 2>);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, threads, lds) != hipSuccess) return 0;
+    return n;
 }
 
 void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int prec, int grid, int threads,

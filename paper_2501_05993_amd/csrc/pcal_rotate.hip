@@ -179,10 +179,12 @@ __global__ void __launch_bounds__(kMaxRotThreads) rot_kernel(RotArgs a) {
 
     const int c = static_cast<int>(blockIdx.x % a.col_tiles);
     const int64_t g = blockIdx.x / a.col_tiles;
-    const int colr = c * a.tile_vecs + t;
+    const int tc = t % a.tile_vecs, sub = t / a.tile_vecs;
+    const int colp = c * a.tile_vecs + tc;
+    const int colr = colp + sub * a.period_vecs;
     const int64_t r0 = g * a.rows_per_group;
     const int64_t r1 = (r0 + a.rows_per_group) < a.rows_total ? (r0 + a.rows_per_group) : a.rows_total;
-    if (t < a.tile_vecs && colr < a.row_vecs && r0 < r1) {
+    if (colp < a.period_vecs && colr < a.row_vecs && r0 < r1) {
         const int64_t stride = a.row_vecs;
         const int64_t rfull = a.nvec / stride;
         const bool last_ok = colr < a.nvec - rfull * stride;

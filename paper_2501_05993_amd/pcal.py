@@ -31,7 +31,7 @@ class Info(ctypes.Structure):
     _fields_ = [(n, _i64) for n in (
         "ntones", "rotator_period", "joint_period", "fold_period", "method", "precision",
         "samples_total", "samples_integ", "block_threads", "row_vectors", "col_tiles",
-        "lds_positions", "device_bytes")]
+        "lds_positions", "device_bytes", "period_vectors", "tile_vectors", "target_blocks")]
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -40,7 +40,7 @@ class Info(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [(n, _i64) for n in (
         "grid", "threads", "lds_bytes", "head_bytes", "nvec", "tail_bytes", "rows_total",
-        "rows_per_group", "q0", "head_q", "tail_q")]
+        "rows_per_group", "q0", "head_q", "tail_q", "groups_per_wg", "extra_groups", "odd_start")]
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -62,6 +62,8 @@ _SIGS = {
     "pcal_extract": ([ctypes.c_void_p, ctypes.c_void_p, _i64, ctypes.c_void_p], ctypes.c_int),
     "pcal_results": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_spectrum": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "pcal_results_async": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
+    "pcal_sync": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_bins": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_reset": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_destroy": ([ctypes.c_void_p], ctypes.c_int),
@@ -181,6 +183,14 @@ class PCal:
         _check(lib().pcal_results(self._h, amp.ctypes.data, phase.ctypes.data, delay.ctypes.data),
                "pcal_results")
         return amp, phase, float(delay[0])
+
+    def results_async(self, host_out, reset: bool = False) -> None:
+        """Enqueue finalize + copy into host_out (4N+1 doubles, ideally pinned); see pcal_results_async."""
+        ptr = host_out.data_ptr() if isinstance(host_out, torch.Tensor) else host_out.ctypes.data
+        _check(lib().pcal_results_async(self._h, ctypes.c_void_p(ptr), 1 if reset else 0), "pcal_results_async")
+
+    def sync(self) -> None:
+        _check(lib().pcal_sync(self._h), "pcal_sync")
 
     def spectrum(self) -> np.ndarray:
         re = np.zeros(self.ntones)

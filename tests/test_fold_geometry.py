@@ -30,24 +30,47 @@ def _levels(packed, nbits):
 
 
 def _walk(info, L):
-    """(block, thread, vector index) of every load the fold kernel issues, in the kernel's formulas."""
-    row_vecs, tile_vecs, col_tiles = info["row_vectors"], L["tile_vecs"], info["col_tiles"]
+    """(block, thread, vector index) of every load the fold kernel issues, in the kernel's formulas.
+
+    Period fold: workgroup g of a tile walks groups_per_wg groups of R rows
+    (one more if g < extra_groups) from group g*groups_per_wg + min(g,
+    extra_groups); rows [odd_start, rows_total) go to the first workgroup of
+    each tile.  Per-sample forms: rows [g*rows_per_group, +rows_per_group).
+    """
+    row_vecs, tile, col_tiles, W = info["row_vectors"], info["tile_vectors"], info["col_tiles"], info["period_vectors"]
     out_b, out_t, out_v = [], [], []
     rfull = L["nvec"] // row_vecs
-    for blk in range(L["grid"]):
+    t = np.arange(L["threads"])
+    tc, sub = t % tile, t // tile
+
+    def emit(blk, r, tmask):
         c = blk % col_tiles
+        colp = c * tile + tc
+        colr = colp + sub * W
+        ok = tmask & (colp < W) & (colr < row_vecs) & ((r < rfull) | ((r == rfull) & (colr < L["nvec"] - rfull * row_vecs)))
+        tt = t[ok]
+        out_b.append(np.full(tt.size, blk))
+        out_t.append(tt)
+        out_v.append(r * row_vecs + colr[ok])
+
+    every = np.ones(t.size, bool)
+    fold = info["method"] == pcal.METHOD_PERIOD_FOLD
+    for blk in range(L["grid"]):
         g = blk // col_tiles
-        t = np.arange(L["threads"])
-        colr = c * tile_vecs + t
-        act = (t < tile_vecs) & (colr < row_vecs)
-        r0 = g * L["rows_per_group"]
-        r1 = min(r0 + L["rows_per_group"], L["rows_total"])
+        if fold:
+            R = L["R"]
+            r0 = R * (g * L["groups_per_wg"] + min(g, L["extra_groups"]))
+            r1 = r0 + R * (L["groups_per_wg"] + (1 if g < L["extra_groups"] else 0))
+            assert r1 <= rfull
+        else:
+            r0 = g * L["rows_per_group"]
+            r1 = min(r0 + L["rows_per_group"], L["rows_total"])
         for r in range(r0, r1):
-            ok = act & ((r < rfull) | ((r == rfull) & (colr < L["nvec"] - rfull * row_vecs)))
-            tt = t[ok]
-            out_b.append(np.full(tt.size, blk))
-            out_t.append(tt)
-            out_v.append(r * row_vecs + colr[ok])
+            emit(blk, r, every)
+    if fold:
+        for c in range(col_tiles):  # rows after the last whole group: first workgroup of the tile
+            for r in range(L["odd_start"], L["rows_total"]):
+                emit(c, r, every)
     if not out_v:
         return np.zeros(0, int), np.zeros(0, int), np.zeros(0, int)
     return np.concatenate(out_b), np.concatenate(out_t), np.concatenate(out_v)
@@ -57,8 +80,9 @@ def _geometry(fs, fc, fo, nbits, nsamples, addr_low=0, before=0, method=0):
     info = pcal.plan(fs, fc, fo, nbits, method=method)
     L = pcal.plan_launch(fs, fc, fo, nbits, nsamples, addr_low=addr_low, samples_before=before, method=method)
     spv = (64 if nbits == 2 else 16) if info["method"] == pcal.METHOD_PERIOD_FOLD else 16
-    L["tile_vecs"] = (info["lds_positions"] // spv) if info["col_tiles"] > 1 else info["row_vectors"]
-    L["pos_cols"] = info["lds_positions"] // spv
+    L["tile_vecs"] = info["tile_vectors"]
+    L["pos_cols"] = info["tile_vectors"]
+    L["R"] = 5 if nbits == 2 else 4  # rows per walker group of the period fold
     return info, L, spv
 
 
@@ -120,8 +144,14 @@ def test_walk_bounds_coverage_and_period(fs, fc, fo, nbits, ns, addr, before):
 ])
 def test_full_size_launch_limits(fs, fc, fo, nbits, ns):
     info, L, spv = _geometry(fs, fc, fo, nbits, ns)
-    assert L["grid"] >= 1 and L["rows_per_group"] * (L["grid"] // info["col_tiles"]) >= L["rows_total"]
-    assert (L["grid"] // info["col_tiles"] - 1) * L["rows_per_group"] < L["rows_total"]
+    ngroups = L["grid"] // info["col_tiles"]
+    unit = 5 if nbits == 2 else 4
+    rfull = L["nvec"] // info["row_vectors"]
+    wgroups = rfull // unit
+    assert L["grid"] >= 1 and ngroups * L["groups_per_wg"] + L["extra_groups"] == wgroups
+    assert 0 <= L["extra_groups"] < ngroups and L["odd_start"] == wgroups * unit
+    assert L["rows_total"] - L["odd_start"] <= unit  # at most unit - 1 full rows and a partial one
+    assert ngroups == 1 or L["groups_per_wg"] >= 1
     assert L["threads"] <= 1024 and L["lds_bytes"] <= 65536
     assert L["nvec"] * 16 + L["head_bytes"] + L["tail_bytes"] == ns * nbits // 8
 
@@ -196,13 +226,14 @@ def test_per_sample_walk(method, fs, fc, fo, nbits, ns, addr, before):
     assert L["threads"] <= 512 and L["threads"] % 64 == 0 and L["threads"] >= L["tile_vecs"]
     assert L["lds_bytes"] == 16 * N
     assert (info["row_vectors"] * 16) % N == 0       # every lane keeps its bin
+    assert info["row_vectors"] % info["period_vectors"] == 0
     blk, thr, vec = _walk(info, L)
     assert vec.size == L["nvec"]
     if vec.size:
         assert vec.min() >= 0 and vec.max() < L["nvec"] and np.unique(vec).size == vec.size
         g0 = before + L["head_bytes"] * spb
         c = blk % info["col_tiles"]
-        colr = c * L["tile_vecs"] + thr
+        colr = c * L["tile_vecs"] + thr % L["tile_vecs"] + (thr // L["tile_vecs"]) * info["period_vectors"]
         # bin the kernel assigns to lane 0 == true bin of the sample
         np.testing.assert_array_equal((g0 + colr * 16) % N, (g0 + vec * 16) % N)
     assert L["q0"] == before + L["head_bytes"] * spb

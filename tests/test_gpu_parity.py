@@ -261,3 +261,28 @@ def test_invalid_calls(pc):
     with pytest.raises(pc.PcalError):
         h.bins(integer=True)              # integer bins only exist for f_offset = 0
     h.close()
+
+
+def test_results_async_pipelined(pc):
+    """Pipelined integrations: results_async(reset) equals synchronous results, and resets."""
+    spec = synth.WORKLOADS["fold2_64M_10k"]["spec"]
+    L = 1 << 21
+    packed = synth.make_stream(spec, 3 * L)
+    dev = _dev(packed)
+    N = spec.ntones
+    ring = torch.zeros((3, 4 * N + 1), dtype=torch.float64, pin_memory=True)
+    with pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2) as h:
+        for i in range(3):
+            h.extract(dev[i * L // 4:], L)
+            h.results_async(ring[i], reset=True)
+        h.sync()
+        assert h.info()["samples_integ"] == 0 and h.info()["samples_total"] == 3 * L
+    for i in range(3):
+        r = ring[i].numpy()
+        C = r[2 * N:3 * N] + 1j * r[3 * N:4 * N]
+        Co = oracle.correlate(packed[i * L // 4:(i + 1) * L // 4], 2, L, spec.fs, spec.f_comb, spec.f_offset,
+                              n0=i * L)
+        assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="async %d" % i)
+        ao, po, do = oracle.results(Co, L, spec.fs, spec.f_comb, spec.f_offset)
+        np.testing.assert_allclose(r[:N], ao, rtol=1e-9)
+        assert abs(r[4 * N] - do) < 1e-13
