@@ -76,6 +76,133 @@ def cpu_baseline(host_bytes, spec, target_s=12.0):
                       "correlation, %.1f s" % (n2, np.log2(n2), spec.ntones, dt2)}
 
 
+SERVED_POOL = 1 << 24  # samples of the pre-staged device pool per stream configuration
+
+
+def _served_setup(torch, synth, seconds):
+    """Stream mix, arrival trace and device-resident chunk pools of the serving study."""
+    specs = synth.served_specs(256)
+    t, sid, ns = synth.served_trace(len(specs), seconds)
+    pools = {}
+    for sp in specs:
+        key = (sp.fs, sp.f_offset, sp.nbits)
+        if key not in pools:
+            pools[key] = synth.make_stream_device(sp, SERVED_POOL)
+    torch.cuda.synchronize()
+    return specs, (t, sid, ns), pools
+
+
+def _pieces(sp, pool, pos, n):
+    """Device (address, samples) pieces of the stream samples [pos, pos + n), taken cyclically from the pool."""
+    spb = 8 // sp.nbits
+    out = []
+    while n > 0:
+        off = pos % SERVED_POOL
+        take = min(n, SERVED_POOL - off)
+        out.append((pool.data_ptr() + off // spb, take))
+        pos += take
+        n -= take
+    return out
+
+
+def served_run(pcal, torch, setup, mode, drain_s=5.0):
+    """Replay the arrival trace through the served form or through plain per-chunk extraction.
+
+    Latency of an integration = host time its results are seen - arrival time of its last chunk.
+    """
+    from collections import deque
+
+    specs, (t, sid, ns), pools = setup
+    S = len(specs)
+    pos = [0] * S
+    last_arrival = {}
+    lat = []
+    done_samples = 0
+    if mode == "served":
+        srv = pcal.PCalServer(mem_budget_bytes=16 << 30, max_streams=S)
+        ids = [srv.open(sp.fs, sp.f_comb, sp.f_offset, sp.nbits, sp.fs) for sp in specs]
+        rev = {v: k for k, v in enumerate(ids)}
+    else:
+        K = 4
+        hs = [pcal.PCal(sp.fs, sp.f_comb, sp.f_offset, sp.nbits, method=pcal.METHOD_PERIOD_FOLD) for sp in specs]
+        streams = [torch.cuda.Stream() for _ in range(K)]
+        slots = [torch.zeros((8, 4 * sp.ntones + 1), dtype=torch.float64, pin_memory=True) for sp in specs]
+        in_integ = [0] * S
+        integ_no = [0] * S
+        pending = deque()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    i = 0
+    n_arr = len(t)
+    while True:
+        now = time.perf_counter() - t0
+        j = int(np.searchsorted(t, now, side="right"))
+        if j > i:
+            sub_s, sub_p, sub_n = [], [], []
+            for a in range(i, j):
+                s_, n_ = int(sid[a]), int(ns[a])
+                sp = specs[s_]
+                p0 = pos[s_]
+                for k in range(p0 // sp.fs, (p0 + n_) // sp.fs):
+                    last_arrival[(s_, k)] = t[a]
+                for ptr, m in _pieces(sp, pools[(sp.fs, sp.f_offset, sp.nbits)], p0, n_):
+                    if mode == "served":
+                        sub_s.append(ids[s_])
+                        sub_p.append(ptr)
+                        sub_n.append(m)
+                    else:
+                        h, st = hs[s_], streams[s_ % K]
+                        spb = 8 // sp.nbits
+                        while m > 0:
+                            take = min(m, sp.fs - in_integ[s_])
+                            h.extract(ptr, take, stream=st)
+                            ptr += take // spb
+                            m -= take
+                            in_integ[s_] += take
+                            if in_integ[s_] == sp.fs:
+                                k = integ_no[s_]
+                                h.results_async(slots[s_][k % 8], reset=True)
+                                ev = torch.cuda.Event()
+                                ev.record(st)
+                                pending.append((ev, s_, k))
+                                integ_no[s_] += 1
+                                in_integ[s_] = 0
+                pos[s_] += n_
+            if mode == "served":
+                srv.submit(sub_s, np.asarray(sub_p, dtype=np.uint64), sub_n)
+            i = j
+        if mode == "served":
+            srv.step()
+            for sv, k in srv.poll():
+                s_ = rev[sv]
+                lat.append(time.perf_counter() - t0 - last_arrival[(s_, k)])
+                done_samples += specs[s_].fs
+            st_ = srv.stats()
+            idle = st_["queued_samples"] == 0 and st_["inflight_finalizes"] == 0
+        else:
+            while pending and pending[0][0].query():
+                _, s_, k = pending.popleft()
+                lat.append(time.perf_counter() - t0 - last_arrival[(s_, k)])
+                done_samples += specs[s_].fs
+            idle = not pending
+        if i >= n_arr and (idle or now > t[-1] + drain_s):
+            break
+    wall = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    if mode == "served":
+        srv.close()
+    else:
+        for h in hs:
+            h.close()
+    offered = float(ns.sum())
+    return {"integrations": len(lat),
+            "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3) if lat else None,
+            "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3) if lat else None,
+            "sustained_gsps": round(offered / wall / 1e9, 2),
+            "completed_integration_gsps": round(done_samples / wall / 1e9, 2),
+            "wall_s": round(wall, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +210,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--served-seconds", type=float, default=8.0,
+                    help="length of the serving-study arrival trace (0: skip the serving study)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (10 times): the known-size reference that "
                          "scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
@@ -128,12 +257,10 @@ def main():
     # then the FP64 finalize (DFT, amplitude, phase, delay) which also clears the
     # bins for the next integration, and the copy of the results to pinned host
     # memory.  Steps are enqueued back to back (no host round trip per step).
+    # The kernel's own duration comes from events that hipExtLaunchKernel stamps
+    # at the fold kernel's start and end (pcal_extract_timed): no launch gaps.
     def step(i, ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        h.extract(bufs[i % 4], L)
-        if ev is not None:
-            ev[1].record(stream)
+        h.extract(bufs[i % 4], L, events=ev)
         h.results_async(ring[i % 8], reset=True)
 
     h.reset()
@@ -141,6 +268,9 @@ def main():
         step(i)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in evs:  # torch creates an event at its first record
+        a.record(stream)
+        b.record(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -199,6 +329,18 @@ def main():
         host = bufs[0].cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(host, spec)
     h.close()
+    if args.served_seconds > 0:
+        bufs.clear()
+        torch.cuda.empty_cache()
+        print("[bench] serving study: %.0f s trace, 256 streams" % args.served_seconds, file=sys.stderr, flush=True)
+        setup = _served_setup(torch, synth, args.served_seconds)
+        served = served_run(pcal, torch, setup, "served")
+        print("[bench] served form done", file=sys.stderr, flush=True)
+        plain = served_run(pcal, torch, setup, "plain")
+        out["served"] = {"workload": "256 streams (2-/8-bit, fs 32-512 MHz, f_offset 0-510 kHz), Poisson "
+                                     "chunks of 2^20-2^24 samples at 200 Gsamples/s offered, 1 s integrations, "
+                                     "%.0f s trace" % args.served_seconds,
+                         "served": served, "plain_per_chunk": plain}
     print(json.dumps(out), flush=True)
 
 

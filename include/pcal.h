@@ -100,6 +100,15 @@ int pcal_create_ex(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nb
  * is ordered after it.  nsamples == 0 is a no-op. */
 int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t stream);
 
+/* pcal_extract, with the extraction kernel launched between two events the
+ * caller created (hipEvent_t, passed as void*; either may be NULL).  The
+ * events take the kernel's own start and end time stamps (hipExtLaunchKernel),
+ * so hipEventElapsedTime(start, stop) is the kernel's duration, free of launch
+ * gaps: the figure a throughput-versus-bandwidth comparison needs.  Every other
+ * behaviour, argument and error is that of pcal_extract. */
+int pcal_extract_timed(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t stream,
+                       void *start_event, void *stop_event);
+
 /* Finish the current integration: FP64 N-point DFT of the bins, then for
  * every tone k (k = 0..N-1, tone frequency f_offset + k*f_comb)
  *   amp[k]   = |C_k| / L  (L = samples since the last reset),
@@ -252,6 +261,57 @@ int pcal_batch_size(pcal_batch_t b, int *n);
 
 /* Release the batch and its member handles (synchronises). */
 int pcal_batch_destroy(pcal_batch_t b);
+
+/* ---- Served form: many live streams under one memory budget -------------
+ *
+ * The spec serving configuration (continuous batching of many
+ * independent streams; the paper extracts one stream at a time).  A server
+ * holds up to max_streams live streams of any (fs, f_comb, f_offset, nbits,
+ * sideband), all in one precision form (enum pcal_precision).
+ *
+ * pcal_server_open admits a stream only if the device memory of its tables
+ * and accumulators fits what is left of mem_budget_bytes, else it returns
+ * PCAL_EAGAIN and keeps nothing.  integration_samples (a multiple of the
+ * samples per byte) is the length of one integration: its results are one
+ * Eq. 1 extraction over exactly those samples, and the global sample index
+ * (rotator phase) continues across integrations.
+ *
+ * pcal_server_submit queues chunks on the host, in order per stream (same
+ * rules as pcal_extract: nsamples a multiple of the samples per byte; device
+ * memory the caller keeps valid until a pcal_server_step that dispatched the
+ * chunk's last samples has completed on its stream).  It never blocks.
+ *
+ * pcal_server_step dispatches, with one launch of the batched fused kernel,
+ * the oldest queued piece of every stream that has one (a chunk crossing an
+ * integration boundary is split there), then one batched finalize for the
+ * streams whose integration it completed: it reads and clears their bins and
+ * copies their results (amplitude, phase, C_k, delay) to pinned host memory.
+ * All of it is asynchronous on `stream`; *samples_dispatched (may be NULL)
+ * gets the samples dispatched.  Call it repeatedly while samples are queued.
+ *
+ * pcal_server_poll reports, without blocking, up to `max` integrations whose
+ * results have reached the host (stream id and integration index, in order of
+ * completion); pcal_server_result / pcal_server_spectrum copy one out (the
+ * last 8 integrations of each stream are kept; an older or unfinished one
+ * gives PCAL_ESTATE).  Output arrays hold N doubles.
+ *
+ * pcal_server_close waits for work in flight and frees the stream's memory
+ * (its budget returns); pcal_server_stats reports queued samples, finalizes
+ * in flight and the device bytes of open streams.  A server is not
+ * thread-safe. */
+typedef struct pcal_server_ctx *pcal_server_t;
+int pcal_server_create(int64_t mem_budget_bytes, int max_streams, int precision, pcal_server_t *out);
+int pcal_server_open(pcal_server_t s, int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits,
+                     int sideband, int64_t integration_samples, int *sid);
+int pcal_server_close(pcal_server_t s, int sid);
+int pcal_server_submit(pcal_server_t s, int count, const int *sids, const void *const *dev_ptrs,
+                       const int64_t *nsamples);
+int pcal_server_step(pcal_server_t s, pcal_stream_t stream, int64_t *samples_dispatched);
+int pcal_server_poll(pcal_server_t s, int max, int *sids, int64_t *integrations, int *n);
+int pcal_server_result(pcal_server_t s, int sid, int64_t integration, double *amp, double *phase, double *delay);
+int pcal_server_spectrum(pcal_server_t s, int sid, int64_t integration, double *re, double *im);
+int pcal_server_stats(pcal_server_t s, int64_t *queued_samples, int *inflight_finalizes, int64_t *device_bytes);
+int pcal_server_destroy(pcal_server_t s);
 
 /* Text of a status code. */
 const char *pcal_strerror(int code);

@@ -538,7 +538,13 @@ int pcal_create(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits
 }
 
 int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t stream) {
+    return pcal_extract_timed(h, dev_ptr, nsamples, stream, nullptr, nullptr);
+}
+
+int pcal_extract_timed(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t stream, void *start_event,
+                       void *stop_event) {
     if (!h || nsamples < 0) return PCAL_EINVAL;
+    hipEvent_t t0 = static_cast<hipEvent_t>(start_event), t1 = static_cast<hipEvent_t>(stop_event);
     const Plan &p = h->plan;
     const int spb = 8 / p.nbits;
     if (nsamples % spb) return PCAL_EINVAL;
@@ -555,7 +561,7 @@ int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t 
 
     if (p.method == PCAL_METHOD_PERIOD_FOLD) {
         const FoldArgs a = fold_args(h, L, dev_ptr);
-        launch_fold(a, p.nbits, static_cast<int>(L.grid), g.threads, static_cast<size_t>(L.lds_bytes), s);
+        launch_fold(a, p.nbits, static_cast<int>(L.grid), g.threads, static_cast<size_t>(L.lds_bytes), s, t0, t1);
     } else {
         const int64_t vb = static_cast<int64_t>(g.spv) * p.nbits / 8;  // bytes per thread-vector
         RotArgs a{};
@@ -588,7 +594,7 @@ int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t 
         a.tail_n = L.tail_q;
         a.acc = h->acc;
         a.accf = h->accf;
-        launch_rotate(a, static_cast<int>(L.grid), g.threads, static_cast<size_t>(L.lds_bytes), s);
+        launch_rotate(a, static_cast<int>(L.grid), g.threads, static_cast<size_t>(L.lds_bytes), s, t0, t1);
     }
     PCAL_HIP(hipGetLastError());
     h->n_total += nsamples;

@@ -90,7 +90,7 @@ int take_stage(pcal_batch_ctx *b, Stage **out) {
 int check_ids(const pcal_batch_ctx *b, int count, const int *ids) {
     if (count < 0 || (count > 0 && !ids) || count > b->max_streams) return PCAL_EINVAL;
     for (int i = 0; i < count; ++i)
-        if (ids[i] < 0 || ids[i] >= static_cast<int>(b->members.size())) return PCAL_EINVAL;
+        if (ids[i] < 0 || ids[i] >= static_cast<int>(b->members.size()) || !b->members[ids[i]]) return PCAL_EINVAL;
     return PCAL_OK;
 }
 
@@ -117,6 +117,51 @@ int mark_members(pcal_batch_ctx *b, int count, const int *ids, hipStream_t s) {
 }
 
 }  // namespace
+
+namespace pcal {
+namespace host {
+
+// Batched finalize of members ids[0..count) that reads and clears their bins
+// (the next integration starts at zero); each member's results land in its
+// own device buffer h->out.  Asynchronous on s.
+int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, hipStream_t s) {
+    int rc = check_ids(b, count, ids);
+    if (rc || count == 0) return rc;
+    DeviceGuard guard(b->members[ids[0]]->device);
+    if ((rc = order_members(b, count, ids, s))) return rc;
+    Stage *st = nullptr;
+    if ((rc = take_stage(b, &st))) return rc;
+    int grid = 0;
+    size_t lds = 0;
+    for (int i = 0; i < count; ++i) {
+        pcal_ctx *h = b->members[ids[i]];
+        st->h_fin[i] = fin_args(h, h->out);
+        st->h_fin[i].clear = 1;
+        st->h_first[i] = grid;
+        grid += static_cast<int>((h->plan.N + 63) / 64);
+        lds = std::max(lds, finalize_lds_bytes(static_cast<int>(h->plan.N)));
+        h->n_integ = 0;
+    }
+    st->h_first[count] = grid;
+    PCAL_HIP(hipMemcpyAsync(st->d_fin, st->h_fin, sizeof(FinArgs) * count, hipMemcpyHostToDevice, s));
+    PCAL_HIP(hipMemcpyAsync(st->d_first, st->h_first, sizeof(int) * (count + 1), hipMemcpyHostToDevice, s));
+    launch_finalize_batch(st->d_fin, st->d_first, count, grid, lds, s);
+    PCAL_HIP(hipGetLastError());
+    PCAL_HIP(hipEventRecord(st->done, s));
+    st->pending = true;
+    return mark_members(b, count, ids, s);
+}
+
+// Destroy member id (after its work) and free its slot for reuse.
+int batch_release(pcal_batch_ctx *b, int id) {
+    if (!b || id < 0 || id >= static_cast<int>(b->members.size()) || !b->members[id]) return PCAL_EINVAL;
+    const int rc = pcal_destroy(b->members[id]);
+    b->members[id] = nullptr;
+    return rc;
+}
+
+}  // namespace host
+}  // namespace pcal
 
 extern "C" {
 
@@ -149,18 +194,30 @@ int pcal_batch_create(int max_streams, int precision, pcal_batch_t *out) {
 int pcal_batch_add(pcal_batch_t b, int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband,
                    int *id) {
     if (!b || !id) return PCAL_EINVAL;
-    if (static_cast<int>(b->members.size()) >= b->max_streams) return PCAL_EAGAIN;
+    // a released slot is reused first
+    int slot = -1;
+    for (int i = 0; i < static_cast<int>(b->members.size()); ++i)
+        if (!b->members[i]) {
+            slot = i;
+            break;
+        }
+    if (slot < 0 && static_cast<int>(b->members.size()) >= b->max_streams) return PCAL_EAGAIN;
     pcal_ctx *h = nullptr;
     const int rc = create(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_PERIOD_FOLD, b->prec,
                           kBatchThreads, &h);
     if (rc) return rc;
-    b->members.push_back(h);
-    *id = static_cast<int>(b->members.size()) - 1;
+    if (slot < 0) {
+        b->members.push_back(h);
+        slot = static_cast<int>(b->members.size()) - 1;
+    } else {
+        b->members[slot] = h;
+    }
+    *id = slot;
     return PCAL_OK;
 }
 
 int pcal_batch_handle(pcal_batch_t b, int id, pcal_t *h) {
-    if (!b || !h || id < 0 || id >= static_cast<int>(b->members.size())) return PCAL_EINVAL;
+    if (!b || !h || id < 0 || id >= static_cast<int>(b->members.size()) || !b->members[id]) return PCAL_EINVAL;
     *h = b->members[id];
     return PCAL_OK;
 }
@@ -326,7 +383,8 @@ int pcal_batch_size(pcal_batch_t b, int *n) {
 int pcal_batch_destroy(pcal_batch_t b) {
     if (!b) return PCAL_EINVAL;
     if (b->ev) (void)hipEventSynchronize(b->ev);
-    for (pcal_ctx *h : b->members) pcal_destroy(h);
+    for (pcal_ctx *h : b->members)
+        if (h) pcal_destroy(h);
     for (int i = 0; i < kStages; ++i) {
         if (b->stage[i].pending) (void)hipEventSynchronize(b->stage[i].done);
         stage_free(b->stage[i]);

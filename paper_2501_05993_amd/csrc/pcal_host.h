@@ -110,5 +110,10 @@ struct DeviceGuard {
     }
 };
 
+// Batched read-and-clear finalize and member release (pcal_batch.hip), for the
+// served form.
+int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, hipStream_t s);
+int batch_release(pcal_batch_ctx *b, int id);
+
 }  // namespace host
 }  // namespace pcal

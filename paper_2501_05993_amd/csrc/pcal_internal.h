@@ -3,6 +3,7 @@
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace pcal {
@@ -147,12 +148,15 @@ struct FinArgs {
     long long *acc_int_clear;
 };
 
-void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds, hipStream_t s);
+// t0 / t1: optional events stamped with the kernel's start and end (null: a plain launch)
+void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds, hipStream_t s,
+                 hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // Fold workgroups of the given shape resident at once on one compute unit (0 on error).
 int fold_blocks_per_cu(int nbits, int prec, int threads, size_t lds);
 void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int prec, int grid, int threads,
                        size_t lds, hipStream_t s);
-void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStream_t s);
+void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStream_t s,
+                   hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_finalize(const FinArgs &a, hipStream_t s);
 size_t finalize_lds_bytes(int N);
 void launch_finalize_batch(const FinArgs *items, const int *first, int nitems, int grid, size_t lds, hipStream_t s);

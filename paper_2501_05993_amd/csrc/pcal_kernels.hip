@@ -739,17 +739,27 @@ __global__ void zero_kernel(uint32_t *p, size_t n) {
 
 }  // namespace
 
-void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds, hipStream_t s) {
+void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds, hipStream_t s, hipEvent_t t0,
+                 hipEvent_t t1) {
     const dim3 gd(grid), bd(threads);
+    // with events: hipExtLaunchKernel stamps them with the kernel's own start and end
+#define PCAL_FOLD(NB, PR)                                                                   \
+    do {                                                                                    \
+        if (t0 || t1)                                                                       \
+            hipExtLaunchKernelGGL((fold_kernel<NB, PR>), gd, bd, lds, s, t0, t1, 0, a);     \
+        else                                                                                \
+            hipLaunchKernelGGL((fold_kernel<NB, PR>), gd, bd, lds, s, a);                   \
+    } while (0)
     if (nbits == 2) {
-        if (a.prec == 0) hipLaunchKernelGGL((fold_kernel<2, 0>), gd, bd, lds, s, a);
-        else if (a.prec == 1) hipLaunchKernelGGL((fold_kernel<2, 1>), gd, bd, lds, s, a);
-        else hipLaunchKernelGGL((fold_kernel<2, 2>), gd, bd, lds, s, a);
+        if (a.prec == 0) PCAL_FOLD(2, 0);
+        else if (a.prec == 1) PCAL_FOLD(2, 1);
+        else PCAL_FOLD(2, 2);
     } else {
-        if (a.prec == 0) hipLaunchKernelGGL((fold_kernel<8, 0>), gd, bd, lds, s, a);
-        else if (a.prec == 1) hipLaunchKernelGGL((fold_kernel<8, 1>), gd, bd, lds, s, a);
-        else hipLaunchKernelGGL((fold_kernel<8, 2>), gd, bd, lds, s, a);
+        if (a.prec == 0) PCAL_FOLD(8, 0);
+        else if (a.prec == 1) PCAL_FOLD(8, 1);
+        else PCAL_FOLD(8, 2);
     }
+#undef PCAL_FOLD
 }
 
 int fold_blocks_per_cu(int nbits, int prec, int threads, size_t lds) {

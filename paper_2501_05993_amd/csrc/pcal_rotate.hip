@@ -294,9 +294,15 @@ __global__ void __launch_bounds__(kMaxRotThreads) rot_kernel(RotArgs a) {
 
 }  // namespace
 
-void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStream_t s) {
+void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     const dim3 gd(grid), bd(threads);
-#define PCAL_ROT(NB, ME, PR) hipLaunchKernelGGL((rot_kernel<NB, ME, PR>), gd, bd, lds, s, a)
+#define PCAL_ROT(NB, ME, PR)                                                                 \
+    do {                                                                                     \
+        if (t0 || t1)                                                                        \
+            hipExtLaunchKernelGGL((rot_kernel<NB, ME, PR>), gd, bd, lds, s, t0, t1, 0, a);   \
+        else                                                                                 \
+            hipLaunchKernelGGL((rot_kernel<NB, ME, PR>), gd, bd, lds, s, a);                 \
+    } while (0)
     if (a.nbits == 2) {
         if (a.method == 2) {
             if (a.prec == 0) PCAL_ROT(2, 2, 0); else if (a.prec == 1) PCAL_ROT(2, 2, 1); else PCAL_ROT(2, 2, 2);

@@ -60,6 +60,8 @@ _SIGS = {
     "pcal_create_ex": ([_i64, _i64, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                         ctypes.c_void_p], ctypes.c_int),
     "pcal_extract": ([ctypes.c_void_p, ctypes.c_void_p, _i64, ctypes.c_void_p], ctypes.c_int),
+    "pcal_extract_timed": ([ctypes.c_void_p, ctypes.c_void_p, _i64, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_void_p], ctypes.c_int),
     "pcal_results": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_spectrum": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_results_async": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
@@ -85,6 +87,21 @@ _SIGS = {
     "pcal_batch_reset": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "pcal_batch_size": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_batch_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "pcal_server_create": ([_i64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "pcal_server_open": ([ctypes.c_void_p, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int, _i64, ctypes.c_void_p],
+                         ctypes.c_int),
+    "pcal_server_close": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
+    "pcal_server_submit": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                           ctypes.c_int),
+    "pcal_server_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "pcal_server_poll": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                         ctypes.c_int),
+    "pcal_server_result": ([ctypes.c_void_p, ctypes.c_int, _i64, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_void_p], ctypes.c_int),
+    "pcal_server_spectrum": ([ctypes.c_void_p, ctypes.c_int, _i64, ctypes.c_void_p, ctypes.c_void_p],
+                             ctypes.c_int),
+    "pcal_server_stats": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "pcal_server_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "pcal_last_error": ([], ctypes.c_char_p),
 }
@@ -156,8 +173,13 @@ class PCal:
     def handle(self) -> int:
         return self._h.value
 
-    def extract(self, data, nsamples: Optional[int] = None, stream=None, byte_offset: int = 0) -> None:
-        """Enqueue packed samples held in a device tensor (or at a raw device address)."""
+    def extract(self, data, nsamples: Optional[int] = None, stream=None, byte_offset: int = 0,
+                events=None) -> None:
+        """Enqueue packed samples held in a device tensor (or at a raw device address).
+
+        events: optional (start, stop) torch.cuda.Event pair, already recorded once
+        (so that they exist), which pcal_extract_timed stamps with the kernel's
+        own start and end."""
         if isinstance(data, torch.Tensor):
             if not data.is_cuda:
                 raise ValueError("extract needs device memory")
@@ -173,8 +195,14 @@ class PCal:
             ptr = int(data) + byte_offset
             if nsamples is None:
                 raise ValueError("nsamples is required with a raw pointer")
-        _check(lib().pcal_extract(self._h, ctypes.c_void_p(ptr), nsamples,
-                                  ctypes.c_void_p(_stream_handle(stream))), "pcal_extract")
+        if events is None:
+            _check(lib().pcal_extract(self._h, ctypes.c_void_p(ptr), nsamples,
+                                      ctypes.c_void_p(_stream_handle(stream))), "pcal_extract")
+        else:
+            e0, e1 = (ctypes.c_void_p(int(e.cuda_event)) if e is not None else None for e in events)
+            _check(lib().pcal_extract_timed(self._h, ctypes.c_void_p(ptr), nsamples,
+                                            ctypes.c_void_p(_stream_handle(stream)), e0, e1),
+                   "pcal_extract_timed")
 
     def results(self) -> Tuple[np.ndarray, np.ndarray, float]:
         amp = np.zeros(self.ntones)
@@ -302,6 +330,97 @@ class PCalBatch:
         if self._b and self._b.value:
             _check(lib().pcal_batch_destroy(self._b), "pcal_batch_destroy")
             self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class PCalServer:
+    """Served form (pcal_server_t): many live streams under one device-memory budget,
+    continuously batched."""
+
+    def __init__(self, mem_budget_bytes: int, max_streams: int, precision: int = PREC_F64):
+        self._s = ctypes.c_void_p()
+        _check(lib().pcal_server_create(mem_budget_bytes, max_streams, precision, ctypes.byref(self._s)),
+               "pcal_server_create")
+        self.ntones = {}
+        self._poll_sid = np.zeros(4096, dtype=np.int32)
+        self._poll_int = np.zeros(4096, dtype=np.int64)
+
+    def open(self, fs: int, f_comb: int, f_offset: int, nbits: int, integration_samples: int,
+             sideband: int = 1) -> int:
+        """Stream id; raises PcalError(EAGAIN) when the memory budget cannot admit it."""
+        sid = ctypes.c_int()
+        _check(lib().pcal_server_open(self._s, fs, f_comb, f_offset, nbits, sideband, integration_samples,
+                                      ctypes.byref(sid)), "pcal_server_open")
+        self.ntones[sid.value] = fs // f_comb
+        return sid.value
+
+    def close_stream(self, sid: int) -> None:
+        _check(lib().pcal_server_close(self._s, sid), "pcal_server_close")
+        self.ntones.pop(sid, None)
+
+    def submit(self, sids, ptrs, nsamples) -> None:
+        """Queue chunks: sids, raw device addresses (or tensors) and sample counts, one per chunk."""
+        sv = np.ascontiguousarray(np.asarray(sids, dtype=np.int32))
+        pv = np.ascontiguousarray(np.asarray([p.data_ptr() if isinstance(p, torch.Tensor) else int(p)
+                                              for p in ptrs] if not isinstance(ptrs, np.ndarray) else ptrs,
+                                             dtype=np.uint64))
+        nv = np.ascontiguousarray(np.asarray(nsamples, dtype=np.int64))
+        _check(lib().pcal_server_submit(self._s, sv.size, sv.ctypes.data, pv.ctypes.data, nv.ctypes.data),
+               "pcal_server_submit")
+
+    def step(self, stream=None) -> int:
+        n = ctypes.c_int64()
+        _check(lib().pcal_server_step(self._s, ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(n)),
+               "pcal_server_step")
+        return n.value
+
+    def poll(self):
+        """[(sid, integration), ...] whose results have reached the host."""
+        n = ctypes.c_int()
+        _check(lib().pcal_server_poll(self._s, self._poll_sid.size, self._poll_sid.ctypes.data,
+                                      self._poll_int.ctypes.data, ctypes.byref(n)), "pcal_server_poll")
+        return list(zip(self._poll_sid[:n.value].tolist(), self._poll_int[:n.value].tolist()))
+
+    def result(self, sid: int, integration: int):
+        N = self.ntones[sid]
+        amp = np.zeros(N)
+        ph = np.zeros(N)
+        d = np.zeros(1)
+        _check(lib().pcal_server_result(self._s, sid, integration, amp.ctypes.data, ph.ctypes.data,
+                                        d.ctypes.data), "pcal_server_result")
+        return amp, ph, float(d[0])
+
+    def spectrum(self, sid: int, integration: int) -> np.ndarray:
+        N = self.ntones[sid]
+        re = np.zeros(N)
+        im = np.zeros(N)
+        _check(lib().pcal_server_spectrum(self._s, sid, integration, re.ctypes.data, im.ctypes.data),
+               "pcal_server_spectrum")
+        return re + 1j * im
+
+    def stats(self) -> dict:
+        q = ctypes.c_int64()
+        f = ctypes.c_int()
+        b = ctypes.c_int64()
+        _check(lib().pcal_server_stats(self._s, ctypes.byref(q), ctypes.byref(f), ctypes.byref(b)),
+               "pcal_server_stats")
+        return {"queued_samples": q.value, "inflight_finalizes": f.value, "device_bytes": b.value}
+
+    def close(self) -> None:
+        if self._s and self._s.value:
+            _check(lib().pcal_server_destroy(self._s), "pcal_server_destroy")
+            self._s = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -236,3 +236,38 @@ def batch_specs(nstreams: int = 64, seed: int = 4, nbits: Optional[int] = 2) -> 
         else:
             out.append(CombSpec(fs, 1_000_000, fo, 8, amp=1.0, t_d=td, sigma=20.0, seed=(seed, s, 0)))
     return out
+
+
+def served_specs(nstreams: int = 256, seed: int = 5) -> list:
+    """Stream mix of the serving study: 16 stations x 16 channels, each with
+    fs ~ U{32..512} MHz, f_offset ~ U{0,10,250,510} kHz, 2- or 8-bit with p = 1/2."""
+    rng = np.random.Generator(np.random.Philox(np.random.SeedSequence([seed, 0x5E7E])))
+    fss = [32, 64, 128, 256, 512]
+    fos = [0, 10_000, 250_000, 510_000]
+    out = []
+    for s in range(nstreams):
+        fs = int(fss[rng.integers(len(fss))]) * 1_000_000
+        fo = int(fos[rng.integers(len(fos))])
+        td = float(rng.uniform(0.0, 20e-9))
+        if rng.integers(2) == 0:
+            out.append(CombSpec(fs, 1_000_000, fo, 2, amp=0.02, t_d=td, seed=(seed, s, 0)))
+        else:
+            out.append(CombSpec(fs, 1_000_000, fo, 8, amp=1.0, t_d=td, sigma=20.0, seed=(seed, s, 0)))
+    return out
+
+
+def served_trace(nstreams: int, seconds: float, offered_sps: float = 200e9, seed: int = 5):
+    """Chunk arrivals of the serving study: Poisson in time at rate offered_sps / E[chunk],
+    chunk sizes 2^U{20..24} samples, each to a stream drawn uniformly.
+
+    Returns (arrival times in s, stream index, samples) as numpy arrays."""
+    rng = np.random.Generator(np.random.Philox(np.random.SeedSequence([seed, 0x7A3C])))
+    sizes = 2 ** np.arange(20, 25)
+    rate = offered_sps / sizes.mean()
+    n = int(rate * seconds * 1.2) + 16
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    keep = t < seconds
+    t = t[keep]
+    sid = rng.integers(0, nstreams, size=n)[keep]
+    ns = sizes[rng.integers(0, sizes.size, size=n)][keep].astype(np.int64)
+    return t, sid.astype(np.int64), ns

@@ -286,3 +286,30 @@ def test_results_async_pipelined(pc):
         ao, po, do = oracle.results(Co, L, spec.fs, spec.f_comb, spec.f_offset)
         np.testing.assert_allclose(r[:N], ao, rtol=1e-9)
         assert abs(r[4 * N] - do) < 1e-13
+
+
+@pytest.mark.gpu
+def test_extract_timed_matches_extract():
+    """pcal_extract_timed: the same bins as pcal_extract, and events that bracket the kernel."""
+    import torch
+    from paper_2501_05993_amd import pcal
+
+    spec = synth.CombSpec(64_000_000, 1_000_000, 10_000, 2, amp=0.3, t_d=5e-9, sigma=1.0, seed=(31, 1))
+    ns = 4 * 300_001
+    buf = synth.make_stream_device(spec, ns)
+    say("extract_timed: 64 MHz / 10 kHz, %d samples" % ns)
+    a = pcal.PCal(spec.fs, spec.f_comb, spec.f_offset, 2)
+    b = pcal.PCal(spec.fs, spec.f_comb, spec.f_offset, 2)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    e1.record(stream)
+    a.extract(buf, ns)
+    b.extract(buf, ns, events=(e0, e1))
+    torch.cuda.synchronize()
+    ra, rb = a.spectrum(), b.spectrum()
+    np.testing.assert_array_equal(np.abs(ra - rb) <= 1e-12 * np.abs(ra).max(), True)
+    ms = e0.elapsed_time(e1)
+    assert 0.0 < ms < 50.0
+    a.close()
+    b.close()

@@ -1,0 +1,150 @@
+"""Served form (pcal_server_*): continuous batching of many live streams.
+
+Each integration a server reports must equal the plain one-stream extraction
+of the same samples (same handle semantics: the global sample index runs on
+across integrations), whatever mix of other streams shared its launches and
+however its chunks straddled integration boundaries; one stream is also
+checked against the oracle.  Admission by memory budget: a stream that does
+not fit is refused with PCAL_EAGAIN and admitted once budget is released.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import F64_RTOL, assert_spectra, say
+
+pytestmark = pytest.mark.gpu
+
+STREAMS = [
+    # fs, f_comb, f_offset, nbits, integration samples
+    (64_000_000, 1_000_000, 10_000, 2, 600_000),
+    (32_000_000, 1_000_000, 0, 2, 400_000),
+    (16_000_000, 1_000_000, 250_000, 2, 333_332),
+    (128_000_000, 1_000_000, 510_000, 8, 500_001),
+    (256_000_000, 2_000_000, 10_000, 2, 1_000_000),
+]
+TOTAL = 2_000_000  # samples per stream (several integrations, the last one partial)
+
+
+def _chunks(rng, total, spb):
+    """Random chunk sizes (multiples of the samples per byte) covering total."""
+    out, n = [], 0
+    while n < total:
+        c = int(rng.integers(1, 300_000)) * spb
+        c = min(c, total - n)
+        out.append(c)
+        n += c
+    return out
+
+
+def _streams_on_device():
+    import torch
+
+    data = []
+    for i, (fs, fc, fo, nbits, integ) in enumerate(STREAMS):
+        spec = synth.CombSpec(fs, fc, fo, nbits, amp=0.3 if nbits == 2 else 4.0, t_d=5e-9,
+                              sigma=1.0 if nbits == 2 else 20.0, seed=(61, i))
+        data.append(synth.make_stream_device(spec, TOTAL))
+    torch.cuda.synchronize()
+    return data
+
+
+def _plain_integrations(buf, fs, fc, fo, nbits, integ):
+    """Spectra of the complete integrations with one plain handle, extract + reset per integration."""
+    from paper_2501_05993_amd import pcal
+
+    spb = 8 // nbits
+    out = []
+    with pcal.PCal(fs, fc, fo, nbits, method=pcal.METHOD_PERIOD_FOLD) as h:
+        for k in range(TOTAL // integ):
+            h.extract(buf, integ, byte_offset=k * integ // spb)
+            out.append(h.spectrum())
+            h.reset()
+    return out
+
+
+def test_served_matches_plain_per_integration():
+    from paper_2501_05993_amd import pcal
+
+    bufs = _streams_on_device()
+    rng = np.random.default_rng(5)
+    srv = pcal.PCalServer(mem_budget_bytes=1 << 30, max_streams=len(STREAMS))
+    sids = []
+    for fs, fc, fo, nbits, integ in STREAMS:
+        sids.append(srv.open(fs, fc, fo, nbits, integ))
+    # interleave the streams' chunks in a random order of arrival
+    queue = []
+    for i, (fs, fc, fo, nbits, integ) in enumerate(STREAMS):
+        spb = 8 // nbits
+        off = 0
+        for c in _chunks(rng, TOTAL, spb):
+            queue.append((i, off, c))
+            off += c
+    order = np.argsort(rng.random(len(queue)), kind="stable")
+    # keep per-stream order: sort by (arrival rank) but within a stream by offset
+    per = {i: [q for q in queue if q[0] == i] for i in range(len(STREAMS))}
+    arrivals, pos = [], {i: 0 for i in per}
+    for j in order:
+        i = queue[j][0]
+        arrivals.append(per[i][pos[i]])
+        pos[i] += 1
+    say("served: %d streams, %d chunks" % (len(STREAMS), len(arrivals)))
+    got = {}
+    k = 0
+    while k < len(arrivals) or srv.stats()["queued_samples"] > 0:
+        burst = arrivals[k:k + int(rng.integers(1, 8))]
+        k += len(burst)
+        if burst:
+            srv.submit([sids[i] for i, _, _ in burst],
+                       [bufs[i].data_ptr() + off // (8 // STREAMS[i][3]) for i, off, _ in burst],
+                       [c for _, _, c in burst])
+        srv.step()
+        for sid, integ in srv.poll():
+            got[(sid, integ)] = srv.spectrum(sid, integ)
+    import torch
+
+    torch.cuda.synchronize()
+    for _ in range(100):
+        for sid, integ in srv.poll():
+            got[(sid, integ)] = srv.spectrum(sid, integ)
+        if srv.stats()["inflight_finalizes"] == 0:
+            break
+    for i, (fs, fc, fo, nbits, integ) in enumerate(STREAMS):
+        want = _plain_integrations(bufs[i], fs, fc, fo, nbits, integ)
+        assert len(want) == TOTAL // integ
+        for k2, w in enumerate(want):
+            assert (sids[i], k2) in got, "integration %d of stream %d not reported" % (k2, i)
+            assert_spectra(got[(sids[i], k2)], w, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="stream %d integration %d" % (i, k2))
+    # one stream against the oracle: its second integration (global index continues)
+    fs, fc, fo, nbits, integ = STREAMS[0]
+    host = bufs[0].cpu().numpy()
+    sub = host[integ // 4:2 * integ // 4]
+    want = oracle.correlate(sub, nbits, integ, fs, fc, fo, n0=integ)
+    assert_spectra(got[(sids[0], 1)], want, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="served vs oracle")
+    srv.close()
+
+
+def test_served_admission_by_memory_budget():
+    from paper_2501_05993_amd import pcal
+
+    probe = pcal.PCalServer(mem_budget_bytes=1 << 30, max_streams=1)
+    a = probe.open(64_000_000, 1_000_000, 10_000, 2, 1 << 20)
+    need = probe.stats()["device_bytes"]
+    probe.close()
+    assert need > 0
+    say("served admission: %d device bytes per stream" % need)
+    srv = pcal.PCalServer(mem_budget_bytes=need + need // 2, max_streams=4)
+    a = srv.open(64_000_000, 1_000_000, 10_000, 2, 1 << 20)
+    with pytest.raises(pcal.PcalError) as e:
+        srv.open(64_000_000, 1_000_000, 10_000, 2, 1 << 20)
+    assert e.value.code == pcal.EAGAIN
+    assert srv.stats()["device_bytes"] == need
+    srv.close_stream(a)
+    assert srv.stats()["device_bytes"] == 0
+    b = srv.open(64_000_000, 1_000_000, 10_000, 2, 1 << 20)
+    assert b >= 0
+    with pytest.raises(pcal.PcalError) as e:
+        srv.submit([b], [0], [3])  # not a multiple of the samples per byte
+    assert e.value.code == pcal.EINVAL
+    srv.close()
