@@ -203,6 +203,50 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0):
             "wall_s": round(wall, 2)}
 
 
+def precision_report(pcal, torch, synth):
+    """Config-4 precision study: 64 streams (fs 16-512 MHz, f_offset 0-510 kHz, 2-bit, 2^26 samples each)
+    through the batched form in the mixed (FP16 table, Kahan FP32) and all-FP32 forms, against the FP64 form."""
+    specs = synth.batch_specs()
+    L = 1 << 26
+    devs = [synth.make_stream_device(sp, L) for sp in specs]
+    torch.cuda.synchronize()
+    res = {}
+    for prec in (pcal.PREC_F64, pcal.PREC_MIXED, pcal.PREC_F32):
+        b = pcal.PCalBatch(len(specs), precision=prec)
+        ids = [b.add(sp.fs, sp.f_comb, sp.f_offset, 2) for sp in specs]
+        b.extract(ids, devs, [L] * len(ids))
+        C = b.spectra(ids)
+        b.reset(ids)
+        b.extract(ids, devs, [L] * len(ids))
+        amp, ph, d = b.results(ids)
+        K = 5
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            b.reset(ids)
+            b.extract(ids, devs, [L] * len(ids))
+            b.results(ids)
+        dt = (time.perf_counter() - t0) / K
+        res[prec] = (C, d, dt)
+        b.close()
+    C64, d64, t64 = res[pcal.PREC_F64]
+    out = {"workload": "64 streams, fs 16-512 MHz, f_offset {0,10,250,510} kHz, 2-bit, 2^26 samples each",
+           "batched_step_ms": {"f64": round(t64 * 1e3, 3)}}
+    for name, prec in (("mixed", pcal.PREC_MIXED), ("f32", pcal.PREC_F32)):
+        C, d, dt = res[prec]
+        amp_e, ph_e, del_e = [], [], []
+        for c, c64 in zip(C, C64):
+            strong = np.abs(c64) >= 1e-5 * np.abs(c64).max()
+            amp_e.append(float(np.max(np.abs(np.abs(c[strong]) - np.abs(c64[strong])) / np.abs(c64[strong]))))
+            ph_e.append(float(np.max(np.abs(np.angle(c[strong] * np.conj(c64[strong]))))))
+        del_e = np.abs(np.asarray(d) - np.asarray(d64))
+        out[name] = {"amp_rel_err_max": max(amp_e), "amp_rel_err_median": float(np.median(amp_e)),
+                     "phase_err_rad_max": max(ph_e), "phase_err_rad_median": float(np.median(ph_e)),
+                     "delay_err_s_max": float(del_e.max()), "delay_err_s_median": float(np.median(del_e))}
+        out["batched_step_ms"][name] = round(dt * 1e3, 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +254,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="only run the 64-stream precision study (mixed and FP32 forms against FP64)")
     ap.add_argument("--served-seconds", type=float, default=8.0,
                     help="length of the serving-study arrival trace (0: skip the serving study)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -236,6 +282,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": 256 << 20, "copies": 10}), flush=True)
+        return
+    if args.precision_report:
+        print(json.dumps({"precision_report": precision_report(pcal, torch, synth)}), flush=True)
         return
     w = synth.WORKLOADS[WORKLOAD]
     spec, L = w["spec"], w["nsamples"]

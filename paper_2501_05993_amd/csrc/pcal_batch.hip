@@ -15,8 +15,8 @@ using namespace pcal::host;
 
 namespace {
 
-constexpr int kBatchThreads = 512;        // workgroup size members are planned for
-constexpr int kBatchTargetBlocks = 1024;  // workgroups per batched launch, split by bytes
+constexpr int kBatchThreads = 512;        // workgroup size members are planned for (PCAL_BATCH_THREADS)
+constexpr int kBatchTargetBlocks = 2048;  // workgroups per batched launch, split by bytes (PCAL_BATCH_BLOCKS)
 constexpr int kStages = 4;                // pinned staging buffers in flight
 
 // Host staging of one launch's work-list (pinned) and its device copy.
@@ -38,6 +38,8 @@ struct Stage {
 struct pcal_batch_ctx {
     int prec = PCAL_PREC_F64;
     int max_streams = 0;
+    int threads = kBatchThreads;        // workgroup size members are planned for
+    int target_blocks = kBatchTargetBlocks;
     std::vector<pcal_ctx *> members;
     Stage stage[kStages];
     int next = 0;
@@ -172,6 +174,10 @@ int pcal_batch_create(int max_streams, int precision, pcal_batch_t *out) {
     if (!b) return PCAL_ENOMEM;
     b->prec = precision;
     b->max_streams = max_streams;
+    b->threads = env_int("PCAL_BATCH_THREADS", kBatchThreads);
+    if (b->threads < 64 || b->threads > kMaxFoldThreads || b->threads % 64) b->threads = kBatchThreads;
+    b->target_blocks = env_int("PCAL_BATCH_BLOCKS", kBatchTargetBlocks);
+    if (b->target_blocks < 1) b->target_blocks = kBatchTargetBlocks;
     {
         hipError_t e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
         if (e != hipSuccess) {
@@ -204,7 +210,7 @@ int pcal_batch_add(pcal_batch_t b, int64_t fs_hz, int64_t f_comb_hz, int64_t f_o
     if (slot < 0 && static_cast<int>(b->members.size()) >= b->max_streams) return PCAL_EAGAIN;
     pcal_ctx *h = nullptr;
     const int rc = create(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_PERIOD_FOLD, b->prec,
-                          kBatchThreads, &h);
+                          b->threads, &h);
     if (rc) return rc;
     if (slot < 0) {
         b->members.push_back(h);
@@ -250,7 +256,7 @@ int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *co
         const Plan &p = h->plan;
         const int64_t bytes = nsamples[i] * p.nbits / 8;
         const int target = static_cast<int>(std::max<int64_t>(
-            p.geom.col_tiles, (kBatchTargetBlocks * bytes + total_bytes - 1) / total_bytes));
+            p.geom.col_tiles, (b->target_blocks * bytes + total_bytes - 1) / total_bytes));
         const pcal_launch_t L =
             plan_launch(p, reinterpret_cast<uintptr_t>(dev_ptrs[i]), h->n_total, nsamples[i], target);
         st->h_items[n] = fold_args(h, L, dev_ptrs[i]);

@@ -110,6 +110,9 @@ struct DeviceGuard {
     }
 };
 
+// Integer from the environment (tuning knobs), dflt when unset.
+int env_int(const char *name, int dflt);
+
 // Batched read-and-clear finalize and member release (pcal_batch.hip), for the
 // served form.
 int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, hipStream_t s);
