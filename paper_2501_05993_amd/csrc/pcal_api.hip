@@ -245,13 +245,17 @@ void release(pcal_ctx *h) {
 // Mean rounding gain gamma = mean over k of conj(t[k]) * (t_rounded[k] - t[k]) of a
 // rotator table: every tone's response is scaled by 1 + gamma when the table is
 // used rounded, so 1 / (1 + gamma) restores it (returned as re, im).
-void table_gain(const std::vector<double2> &t, const std::vector<__half2> &th, double *re, double *im) {
+double2 from_half2(__half2 h) {
+    _Float16 hx, hy;
+    memcpy(&hx, reinterpret_cast<const char *>(&h), 2);
+    memcpy(&hy, reinterpret_cast<const char *>(&h) + 2, 2);
+    return make_double2(static_cast<double>(hx), static_cast<double>(hy));
+}
+
+void table_gain(const std::vector<double2> &t, const std::vector<double2> &tr, double *re, double *im) {
     double gr = 0.0, gi = 0.0;
     for (size_t m = 0; m < t.size(); ++m) {
-        _Float16 hx, hy;
-        memcpy(&hx, reinterpret_cast<const char *>(&th[m]), 2);
-        memcpy(&hy, reinterpret_cast<const char *>(&th[m]) + 2, 2);
-        const double dr = static_cast<double>(hx) - t[m].x, di = static_cast<double>(hy) - t[m].y;
+        const double dr = tr[m].x - t[m].x, di = tr[m].y - t[m].y;
         gr += t[m].x * dr + t[m].y * di;
         gi += t[m].x * di - t[m].y * dr;
     }
@@ -301,13 +305,17 @@ int build(pcal_ctx *h) {
                 idx += p.fo;
                 if (idx >= p.fs) idx -= p.fs;
             }
-            if (p.prec == PCAL_PREC_MIXED) table_gain(t, th, &h->gain_re, &h->gain_im);
+            if (p.prec == PCAL_PREC_MIXED) {
+                std::vector<double2> tr(R);
+                for (int64_t n = 0; n < R; ++n) tr[n] = from_half2(th[n]);
+                table_gain(t, tr, &h->gain_re, &h->gain_im);
+            }
             if ((rc = dalloc(h, &h->rot32, R)) || (rc = dalloc(h, &h->rot16, R))) return rc;
             PCAL_HIP(hipMemcpy(h->rot32, tf.data(), sizeof(float2) * R, hipMemcpyHostToDevice));
             PCAL_HIP(hipMemcpy(h->rot16, th.data(), sizeof(__half2) * R, hipMemcpyHostToDevice));
         }
     }
-    if ((rc = dalloc(h, &h->u64, M)) || (rc = dalloc(h, &h->u32, M)) || (rc = dalloc(h, &h->u16, M)) ||
+    if ((rc = dalloc(h, &h->u64, M)) || (rc = dalloc(h, &h->u32, M)) || (rc = dalloc(h, &h->u16, 2 * M)) ||
         (rc = dalloc(h, &h->v, N)) || (rc = dalloc(h, &h->tw, N)) || (rc = dalloc(h, &h->acc, kAccSlots * N)) ||
         (rc = dalloc(h, &h->acc_int, kAccSlots * N)) || (rc = dalloc(h, &h->accf, kAccSlots * N)) || (rc = dalloc(h, &h->counters, 1)) ||
         (rc = dalloc(h, &h->out, 4 * N + 1)))
@@ -325,13 +333,18 @@ int build(pcal_ctx *h) {
     //   tw[j] = exp(-j 2 pi j / N)  (DFT twiddles).
     std::vector<double2> u(M), v(N), tw(N);
     std::vector<float2> uf(M);
-    std::vector<__half2> uh(M);
+    std::vector<__half2> uh(2 * M);  // two-term FP16 rows: u ~ hi + lo
+    std::vector<double2> ur(M);        // hi + lo, exactly
     const int64_t step_u = static_cast<int64_t>((static_cast<unsigned __int128>(p.fo) * N) % p.fs);
     int64_t idx = 0;
     for (int64_t m = 0; m < M; ++m) {
         phasor(idx, p.fs, &u[m].x, &u[m].y);
         uf[m] = make_float2(static_cast<float>(u[m].x), static_cast<float>(u[m].y));
-        uh[m] = to_half2(u[m]);
+        uh[2 * m] = to_half2(u[m]);
+        const double2 hi = from_half2(uh[2 * m]);
+        uh[2 * m + 1] = to_half2(make_double2(u[m].x - hi.x, u[m].y - hi.y));
+        const double2 lo = from_half2(uh[2 * m + 1]);
+        ur[m] = make_double2(hi.x + lo.x, hi.y + lo.y);
         idx += step_u;
         if (idx >= p.fs) idx -= p.fs;
     }
@@ -342,13 +355,15 @@ int build(pcal_ctx *h) {
         if (idx >= p.fs) idx -= p.fs;
         phasor(b, N, &tw[b].x, &tw[b].y);
     }
-    // Mixed form: the FP16 rows change every tone's response by the same known
-    // complex gain 1 + gamma, gamma = mean over m of conj(u[m]) * (u16[m] - u[m])
-    // (the rows sum against conj(u[m]) for every tone); the FP64 finalize divides it out.
-    if (fold && p.prec == PCAL_PREC_MIXED) table_gain(u, uh, &h->gain_re, &h->gain_im);
+    // Mixed form: each row is stored as two FP16 terms hi + lo (hi = u rounded,
+    // lo = the rest rounded; their sum is exact in FP32, about 22 bits).  The
+    // rounded rows change every tone's response by the same known complex gain
+    // 1 + gamma, gamma = mean over m of conj(u[m]) * (u16[m] - u[m]) (the rows
+    // sum against conj(u[m]) for every tone); the FP64 finalize divides it out.
+    if (fold && p.prec == PCAL_PREC_MIXED) table_gain(u, ur, &h->gain_re, &h->gain_im);
     PCAL_HIP(hipMemcpy(h->u64, u.data(), sizeof(double2) * M, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemcpy(h->u32, uf.data(), sizeof(float2) * M, hipMemcpyHostToDevice));
-    PCAL_HIP(hipMemcpy(h->u16, uh.data(), sizeof(__half2) * M, hipMemcpyHostToDevice));
+    PCAL_HIP(hipMemcpy(h->u16, uh.data(), sizeof(__half2) * 2 * M, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemcpy(h->v, v.data(), sizeof(double2) * N, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemcpy(h->tw, tw.data(), sizeof(double2) * N, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemset(h->acc, 0, sizeof(double2) * kAccSlots * N));

@@ -82,7 +82,7 @@ struct FoldArgs {
     int64_t q0;              // period coordinate (global index mod S') of data[0], sample 0
     const double2 *u64;      // u[m] = exp(-j w_o N m), m < M  (FP64)
     const float2 *u32;       // same, rounded to FP32
-    const __half2 *u16;      // same, rounded to FP16
+    const __half2 *u16;      // [2M]: u[m] ~ u16[2m] + u16[2m+1] (FP16 rounded, then its residual)
     const double2 *v;        // v[b] = exp(-j w_o b), b < N  (FP64)
     // Samples outside the full vectors (misaligned head, short tail), <= 15 bytes each.
     const uint8_t *head;

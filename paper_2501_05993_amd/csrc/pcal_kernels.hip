@@ -266,7 +266,7 @@ struct Walk8 {
 
 // A partial bin sum in the arithmetic of one precision form (enum pcal_precision):
 //   0 (F64):   FP64 table, FP64 products and sums;
-//   1 (MIXED): FP16 table (held as FP32), FP32 products, Kahan-compensated FP32 sums;
+//   1 (MIXED): two-term FP16 table (hi + lo, held as FP32), FP32 products, Kahan-compensated FP32 sums;
 //   2 (F32):   FP32 table, plain FP32 products and sums.
 // si carries the exact integer sum (the Eq. 2 bin when f_offset = 0).
 template <int PREC>
@@ -339,8 +339,11 @@ template <int PREC>
 __device__ __forceinline__ typename BinAcc<PREC>::Tab table_row(const FoldArgs &a, int m) {
     if constexpr (PREC == 0)
         return a.u64[m];
-    else if constexpr (PREC == 1)
-        return __half22float2(a.u16[m]);
+    else if constexpr (PREC == 1) {
+        // two FP16 terms; their FP32 sum is exact
+        const float2 hi = __half22float2(a.u16[2 * m]), lo = __half22float2(a.u16[2 * m + 1]);
+        return make_float2(hi.x + lo.x, hi.y + lo.y);
+    }
     else
         return a.u32[m];
 }
