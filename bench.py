@@ -356,6 +356,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "fold_kernel<2,0>",
+                     "kernel_note": "each launch also runs the previous integration's finalize in 1 of its "
+                                    "256 workgroups (pcal_results_async with reset defers it into the next fold)",
                      "kernel_avg_us": round(kavg_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": nbytes},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),

@@ -233,13 +233,48 @@ int dalloc(pcal_ctx *h, T **p, size_t count) {
 }
 
 void release(pcal_ctx *h) {
-    void *ptrs[] = {h->u64, h->u32, h->u16, h->v, h->tw, h->acc, h->acc_int, h->accf, h->counters, h->out,
-                    h->rot32, h->rot16, h->w};
+    void *ptrs[] = {h->u64, h->u32, h->u16, h->v, h->tw, h->acc_mem, h->acc_int_mem, h->accf_mem, h->counters,
+                    h->out, h->rot32, h->rot16, h->w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->host_out) (void)hipHostFree(h->host_out);
     if (h->ev) (void)hipEventDestroy(h->ev);
     delete h;
+}
+
+void set_bank(pcal_ctx *h, int b) {
+    const size_t NS = static_cast<size_t>(kAccSlots) * static_cast<size_t>(h->plan.N);
+    h->bank = b;
+    h->acc = h->acc_mem + b * NS;
+    h->acc_int = h->acc_int_mem + b * NS;
+    h->accf = h->accf_mem + b * NS;
+}
+
+int flush_pending(pcal_ctx *h, hipStream_t s) {
+    if (!h->fin_pending) return PCAL_OK;
+    h->fin_pending = false;
+    launch_finalize(h->fin, s);
+    PCAL_HIP(hipGetLastError());
+    if (h->fin_dev)
+        PCAL_HIP(hipMemcpyAsync(h->fin_host, h->fin_dev, sizeof(double) * (4 * h->plan.N + 1),
+                                hipMemcpyDeviceToHost, s));
+    return PCAL_OK;
+}
+
+// Device address of a host result buffer the finalize may write directly
+// (pinned, mapped host memory of 4N + 1 doubles), or null.  Cached per handle.
+double *mapped_results(pcal_ctx *h, double *host) {
+    for (const auto &e : h->map_cache)
+        if (e.host == host) return e.dev;
+    void *dev = nullptr;
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, host) != hipSuccess || at.type != hipMemoryTypeHost ||
+        hipHostGetDevicePointer(&dev, host, 0) != hipSuccess)
+        dev = nullptr;
+    (void)hipGetLastError();  // a refused query leaves no error behind
+    h->map_cache[h->map_next] = {host, static_cast<double *>(dev)};
+    h->map_next = (h->map_next + 1) % 8;
+    return static_cast<double *>(dev);
 }
 
 // Mean rounding gain gamma = mean over k of conj(t[k]) * (t_rounded[k] - t[k]) of a
@@ -316,9 +351,9 @@ int build(pcal_ctx *h) {
         }
     }
     if ((rc = dalloc(h, &h->u64, M)) || (rc = dalloc(h, &h->u32, M)) || (rc = dalloc(h, &h->u16, 2 * M)) ||
-        (rc = dalloc(h, &h->v, N)) || (rc = dalloc(h, &h->tw, N)) || (rc = dalloc(h, &h->acc, kAccSlots * N)) ||
-        (rc = dalloc(h, &h->acc_int, kAccSlots * N)) || (rc = dalloc(h, &h->accf, kAccSlots * N)) || (rc = dalloc(h, &h->counters, 1)) ||
-        (rc = dalloc(h, &h->out, 4 * N + 1)))
+        (rc = dalloc(h, &h->v, N)) || (rc = dalloc(h, &h->tw, N)) || (rc = dalloc(h, &h->acc_mem, 2 * kAccSlots * N)) ||
+        (rc = dalloc(h, &h->acc_int_mem, 2 * kAccSlots * N)) || (rc = dalloc(h, &h->accf_mem, 2 * kAccSlots * N)) ||
+        (rc = dalloc(h, &h->counters, 2)) || (rc = dalloc(h, &h->out, 2 * (4 * N + 1))))
         return rc;
     {
         hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->host_out), sizeof(double) * (4 * N + 1),
@@ -366,18 +401,19 @@ int build(pcal_ctx *h) {
     PCAL_HIP(hipMemcpy(h->u16, uh.data(), sizeof(__half2) * 2 * M, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemcpy(h->v, v.data(), sizeof(double2) * N, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemcpy(h->tw, tw.data(), sizeof(double2) * N, hipMemcpyHostToDevice));
-    PCAL_HIP(hipMemset(h->acc, 0, sizeof(double2) * kAccSlots * N));
-    PCAL_HIP(hipMemset(h->acc_int, 0, sizeof(long long) * kAccSlots * N));
-    PCAL_HIP(hipMemset(h->accf, 0, sizeof(float2) * kAccSlots * N));
-    PCAL_HIP(hipMemset(h->counters, 0, sizeof(unsigned)));
+    PCAL_HIP(hipMemset(h->acc_mem, 0, sizeof(double2) * 2 * kAccSlots * N));
+    PCAL_HIP(hipMemset(h->acc_int_mem, 0, sizeof(long long) * 2 * kAccSlots * N));
+    PCAL_HIP(hipMemset(h->accf_mem, 0, sizeof(float2) * 2 * kAccSlots * N));
+    PCAL_HIP(hipMemset(h->counters, 0, 2 * sizeof(unsigned)));
+    set_bank(h, 0);
     PCAL_HIP(hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
     return PCAL_OK;
 }
 
 // Order work on `s` after the handle's previous work (possibly on another stream).
-int order_on(pcal_ctx *h, hipStream_t s) {
+int order_on(pcal_ctx *h, hipStream_t s, bool flush) {
     if (h->have_ev && s != h->last_stream) PCAL_HIP(hipStreamWaitEvent(s, h->wait_ev, 0));
-    return PCAL_OK;
+    return flush ? flush_pending(h, s) : PCAL_OK;
 }
 
 int mark(pcal_ctx *h, hipStream_t s) {
@@ -428,6 +464,8 @@ FinArgs fin_args(const pcal_ctx *h, double *out) {
 int run_finalize(pcal_ctx *h) {
     const Plan &p = h->plan;
     hipStream_t s = h->last_stream;
+    int rc = flush_pending(h, s);
+    if (rc) return rc;
     launch_finalize(fin_args(h, h->out), s);
     PCAL_HIP(hipGetLastError());
     PCAL_HIP(hipMemcpyAsync(h->host_out, h->out, sizeof(double) * (4 * p.N + 1), hipMemcpyDeviceToHost, s));
@@ -473,6 +511,8 @@ FoldArgs fold_args(pcal_ctx *h, const pcal_launch_t &L, const void *dev_ptr) {
     a.extra_groups = L.extra_groups;
     a.odd_start = L.odd_start;
     a.sync_pairs = p.sync_pairs;
+    a.fold_wgs = static_cast<int>(L.grid);
+    a.fin_wgs = 0;
     return a;
 }
 
@@ -567,16 +607,33 @@ int pcal_extract_timed(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_str
     if (!dev_ptr) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int rc = order_on(h, s);
+    const bool fold = p.method == PCAL_METHOD_PERIOD_FOLD;
+    int rc = order_on(h, s, !fold);
     if (rc) return rc;
 
     const FoldGeom &g = p.geom;
-    const pcal_launch_t L = plan_launch(p, reinterpret_cast<uintptr_t>(dev_ptr), h->n_total, nsamples);
+    // A pending finalize takes fin_wgs of the launch's resident workgroups, so
+    // that every workgroup starts at once: the fold gets the rest.
+    const int fin_wgs = (fold && h->fin_pending) ? static_cast<int>((p.N + 63) / 64) : 0;
+    const int target = fin_wgs ? std::max(g.col_tiles, p.target_blocks - fin_wgs) : 0;
+    const pcal_launch_t L = plan_launch(p, reinterpret_cast<uintptr_t>(dev_ptr), h->n_total, nsamples, target);
     if (L.grid > p.max_blocks) return PCAL_EINVAL;  // cannot happen by construction
 
-    if (p.method == PCAL_METHOD_PERIOD_FOLD) {
-        const FoldArgs a = fold_args(h, L, dev_ptr);
-        launch_fold(a, p.nbits, static_cast<int>(L.grid), g.threads, static_cast<size_t>(L.lds_bytes), s, t0, t1);
+    if (fold) {
+        FoldArgs a = fold_args(h, L, dev_ptr);
+        size_t lds = static_cast<size_t>(L.lds_bytes);
+        if (fin_wgs) {  // the previous integration's finalize rides along in extra workgroups
+            a.fin = h->fin;
+            a.fin_wgs = fin_wgs;
+            lds = std::max(lds, finalize_lds_bytes(static_cast<int>(p.N)));
+        }
+        launch_fold(a, p.nbits, static_cast<int>(L.grid) + a.fin_wgs, g.threads, lds, s, t0, t1);
+        if (h->fin_pending) {
+            h->fin_pending = false;
+            if (h->fin_dev)
+                PCAL_HIP(hipMemcpyAsync(h->fin_host, h->fin_dev, sizeof(double) * (4 * p.N + 1),
+                                        hipMemcpyDeviceToHost, s));
+        }
     } else {
         const int64_t vb = static_cast<int64_t>(g.spv) * p.nbits / 8;  // bytes per thread-vector
         RotArgs a{};
@@ -634,18 +691,41 @@ int pcal_results_async(pcal_t h, double *host_out, int reset) {
     DeviceGuard guard(h->device);
     const Plan &p = h->plan;
     hipStream_t s = h->last_stream;
-    FinArgs f = fin_args(h, h->out);
-    f.clear = reset ? 1 : 0;
-    launch_finalize(f, s);
-    PCAL_HIP(hipGetLastError());
-    PCAL_HIP(hipMemcpyAsync(host_out, h->out, sizeof(double) * (4 * p.N + 1), hipMemcpyDeviceToHost, s));
-    if (reset) h->n_integ = 0;
-    return mark(h, s);
+    int rc = flush_pending(h, s);
+    if (rc) return rc;
+    if (!reset) {
+        launch_finalize(fin_args(h, h->out), s);
+        PCAL_HIP(hipGetLastError());
+        PCAL_HIP(hipMemcpyAsync(host_out, h->out, sizeof(double) * (4 * p.N + 1), hipMemcpyDeviceToHost, s));
+        return mark(h, s);
+    }
+    // Finish the integration: its finalize (reading and clearing the current
+    // bank) is left pending for the next fold launch, and the handle moves on
+    // to the other bank.  One workgroup (N <= 64) writes the results straight
+    // into mapped pinned host memory; otherwise a device buffer is copied.
+    const int b = h->bank;
+    double *dev_host = p.N <= 64 ? mapped_results(h, host_out) : nullptr;
+    double *out = dev_host ? dev_host : h->out + static_cast<size_t>(b) * (4 * p.N + 1);
+    h->fin = fin_args(h, out);
+    h->fin.counter = h->counters + b;
+    h->fin.clear = 1;
+    h->fin_host = host_out;
+    h->fin_dev = dev_host ? nullptr : out;
+    h->fin_pending = true;
+    set_bank(h, b ^ 1);
+    h->n_integ = 0;
+    if (p.method != PCAL_METHOD_PERIOD_FOLD) return flush_pending(h, s);
+    return PCAL_OK;
 }
 
 int pcal_sync(pcal_t h) {
     if (!h) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
+    if (h->fin_pending) {
+        const int rc = flush_pending(h, h->last_stream);
+        if (rc) return rc;
+        PCAL_HIP(hipStreamSynchronize(h->last_stream));
+    }
     if (h->have_ev) PCAL_HIP(hipEventSynchronize(h->wait_ev));
     return PCAL_OK;
 }
@@ -719,6 +799,8 @@ int pcal_destroy(pcal_t h) {
     if (!h) return PCAL_EINVAL;
     {
         DeviceGuard guard(h->device);
+        if (h->fin_pending && flush_pending(h, h->last_stream) == PCAL_OK)
+            (void)hipStreamSynchronize(h->last_stream);
         if (h->have_ev) (void)hipEventSynchronize(h->wait_ev);
         release(h);
     }

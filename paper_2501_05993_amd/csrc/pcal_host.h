@@ -62,11 +62,29 @@ struct pcal_ctx {
     __half2 *u16 = nullptr;
     double2 *v = nullptr;
     double2 *tw = nullptr;
+    // Integration accumulators in two banks; acc / acc_int / accf point at the
+    // current one.  pcal_results_async with reset leaves the current bank's
+    // finalize pending and switches banks; the next fold launch runs that
+    // finalize in extra workgroups (flush_pending runs it alone otherwise).
+    double2 *acc_mem = nullptr;     // [2][kAccSlots][N]
+    long long *acc_int_mem = nullptr;
+    float2 *accf_mem = nullptr;
     double2 *acc = nullptr;
     long long *acc_int = nullptr;
     float2 *accf = nullptr;
-    unsigned *counters = nullptr;  // [0] finalize
-    double *out = nullptr;         // device results [4N + 1]
+    int bank = 0;
+    bool fin_pending = false;
+    pcal::FinArgs fin;              // the pending finalize (clearing the other bank)
+    double *fin_host = nullptr;     // where its results go
+    const double *fin_dev = nullptr;  // device results to copy to fin_host (null: written there directly)
+    // host result buffers the finalize may write directly (mapped pinned memory)
+    struct MapEntry {
+        const double *host;
+        double *dev;  // null: not device-accessible
+    } map_cache[8] = {};
+    int map_next = 0;
+    unsigned *counters = nullptr;  // [0] finalize of bank 0's pending form / plain, [1] bank 1
+    double *out = nullptr;         // device results [2][4N + 1]
     double *host_out = nullptr;    // pinned copy
     float2 *rot32 = nullptr;       // rotator table [R] (table method)
     __half2 *rot16 = nullptr;
@@ -87,11 +105,16 @@ namespace pcal {
 namespace host {
 
 int build(pcal_ctx *h);
+// Point acc / acc_int / accf at bank b.
+void set_bank(pcal_ctx *h, int b);
+// Run a pending finalize on its own (on s).
+int flush_pending(pcal_ctx *h, hipStream_t s);
 void release(pcal_ctx *h);
 int create(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int method, int prec, int force_threads,
            pcal_ctx **out);
 // Order work on `s` after the handle's previous work; record it as the handle's last work.
-int order_on(pcal_ctx *h, hipStream_t s);
+// Order s after the handle's last work (a pending finalize runs first unless flush is false).
+int order_on(pcal_ctx *h, hipStream_t s, bool flush = true);
 int mark(pcal_ctx *h, hipStream_t s);
 // Kernel arguments of one extract call of a period-fold handle (advances the
 // handle's chunk-counter base past the launch).

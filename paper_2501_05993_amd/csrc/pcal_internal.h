@@ -65,6 +65,26 @@ __host__ __device__ constexpr size_t fold_lds_bytes(int npos, int spv, int threa
     return fold_front_bytes(npos, spv, threads) + (M <= kLdsTableRows ? static_cast<size_t>(M) * 16 : 0);
 }
 
+// Arguments of the FP64 finalize (DFT, amplitude, phase, delay).
+struct FinArgs {
+    const double2 *acc;      // [kAccSlots][N] bins (FP64 forms)
+    const float2 *accf;      // [kAccSlots][N] bins (FP32 form)
+    const double2 *tw;       // [N] exp(-j 2 pi j / N)
+    int N;
+    int prec;
+    int sideband;
+    double inv_L;            // 1 / samples in the integration (0 if none)
+    int k_lo, k_hi;          // in-band tones [k_lo, k_hi): 0 < f_k < fs/2
+    double f_comb;           // Hz
+    double gain_re, gain_im; // C_k is multiplied by this (1 / (1 + gamma) in the mixed form, else 1)
+    double *out;             // [4N + 1]: amp, phase, re, im, delay
+    unsigned *counter;
+    int clear;               // zero the accumulators afterwards (next integration)
+    double2 *acc_clear;      // the accumulators to zero ([kAccSlots][N] each)
+    float2 *accf_clear;
+    long long *acc_int_clear;
+};
+
 // Arguments of the fused unpack-rotate-fold kernel (one launch per pcal_extract).
 struct FoldArgs {
     const uint4 *data;       // 16-byte aligned start of the full vectors
@@ -98,6 +118,11 @@ struct FoldArgs {
     // each tile.
     int64_t groups_per_wg, extra_groups, odd_start;
     int sync_pairs;          // a workgroup barrier every sync_pairs pairs of groups (power of 2; 0: none)
+    // Fused finalize of the previous integration: workgroups [fold_wgs,
+    // fold_wgs + fin_wgs) of the launch run the finalize of `fin` (another
+    // accumulator bank) instead of folding; fin_wgs = 0: none.
+    int fold_wgs, fin_wgs;
+    FinArgs fin;
     // Integration accumulators of the handle (each workgroup adds its bins atomically).
     double2 *acc;            // [kAccSlots][N] rotated, folded bins P[b], FP64
     float2 *accf;            // [kAccSlots][N] the same in FP32 (PREC_F32 form)
@@ -128,25 +153,6 @@ struct RotArgs {
     float2 *accf;            // [kAccSlots][N] (F32 form)
 };
 
-// Arguments of the FP64 finalize (DFT, amplitude, phase, delay).
-struct FinArgs {
-    const double2 *acc;      // [kAccSlots][N] bins (FP64 forms)
-    const float2 *accf;      // [kAccSlots][N] bins (FP32 form)
-    const double2 *tw;       // [N] exp(-j 2 pi j / N)
-    int N;
-    int prec;
-    int sideband;
-    double inv_L;            // 1 / samples in the integration (0 if none)
-    int k_lo, k_hi;          // in-band tones [k_lo, k_hi): 0 < f_k < fs/2
-    double f_comb;           // Hz
-    double gain_re, gain_im; // C_k is multiplied by this (1 / (1 + gamma) in the mixed form, else 1)
-    double *out;             // [4N + 1]: amp, phase, re, im, delay
-    unsigned *counter;
-    int clear;               // zero the accumulators afterwards (next integration)
-    double2 *acc_clear;      // the accumulators to zero ([kAccSlots][N] each)
-    float2 *accf_clear;
-    long long *acc_int_clear;
-};
 
 // t0 / t1: optional events stamped with the kernel's start and end (null: a plain launch)
 void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds, hipStream_t s,

@@ -517,11 +517,6 @@ __device__ __forceinline__ void fold_body(const FoldArgs &a, const int wg, unsig
     }
 }
 
-template <int NBITS, int PREC>
-__global__ void __launch_bounds__(kMaxFoldThreads) fold_kernel(FoldArgs a) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    fold_body<NBITS, PREC>(a, static_cast<int>(blockIdx.x), lds);
-}
 
 // Index of the work item that owns workgroup `wg`: the last i with first[i] <= wg.
 __device__ __forceinline__ int owner_of(const int *first, int nitems, int wg) {
@@ -553,18 +548,21 @@ __global__ void __launch_bounds__(kMaxFoldThreads) fold_batch_kernel(const FoldA
 
 // ---------------------------------------------------------------- finalize
 
-// One 256-thread workgroup per 64 tones: lane -> tone, the four waves split
-// the N-term DFT sum, twiddles indexed exactly by (k*b) mod N.  The last
-// workgroup unwraps the in-band phases (prefix sum of wrapped differences)
-// and fits the delay by least squares.
+// One workgroup per 64 tones, the first 256 threads working (more may be
+// present when it runs inside the fold kernel; they only meet the barriers):
+// lane -> tone, four waves split the N-term DFT sum, twiddles indexed exactly
+// by (k*b) mod N.  The last workgroup unwraps the in-band phases (prefix sum
+// of wrapped differences) and fits the delay by least squares.
 __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, const int nwg, unsigned char *lds) {
     const int N = a.N, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const bool me = t < 256;
+    __shared__ double s_ph[64];  // phases of a single-workgroup finalize
     double2 *P = reinterpret_cast<double2 *>(lds);
     const bool tw_lds = N <= kTwLdsMaxTones;
     double2 *TW = tw_lds ? P + N : nullptr;
     double2 *red = P + (tw_lds ? 2 * N : N);
     const bool f32 = a.prec == 2;
-    for (int i = t; i < N; i += 256) {
+    for (int i = t; me && i < N; i += 256) {
         // add the accumulator slots in slot order
         double re = 0.0, im = 0.0;
         float fr = 0.f, fi = 0.f;
@@ -587,7 +585,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
     const int bb = wave * qn;
     const int be = (bb + qn) < N ? (bb + qn) : N;
     double re = 0.0, im = 0.0;
-    if (k < N && bb < be) {
+    if (me && k < N && bb < be) {
         int idx = static_cast<int>((static_cast<int64_t>(k) * bb) % N);
         if (f32) {
             float fr = 0.f, fi = 0.f;
@@ -614,7 +612,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
             }
         }
     }
-    red[wave * 64 + lane] = make_double2(re, im);
+    if (me) red[wave * 64 + lane] = make_double2(re, im);
     __syncthreads();
     if (wave == 0 && k < N) {
         double cr = 0.0, ci = 0.0;
@@ -639,18 +637,25 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
             cr = gr;
         }
         if (a.sideband < 0) ci = -ci;
+        const double phase = atan2(ci, cr);
         a.out[k] = sqrt(cr * cr + ci * ci) * a.inv_L;
-        a.out[N + k] = atan2(ci, cr);
+        a.out[N + k] = phase;
         a.out[2 * N + k] = cr;
         a.out[3 * N + k] = ci;
+        if (nwg == 1) s_ph[k] = phase;
     }
 
-    if (!last_workgroup_done(a.counter, static_cast<unsigned>(nwg))) return;
+    // One workgroup (N <= 64) has every phase in LDS; several meet at a counter
+    // and the last one reads the phases back from global memory.
+    if (nwg == 1)
+        __syncthreads();
+    else if (!last_workgroup_done(a.counter, static_cast<unsigned>(nwg)))
+        return;
 
     // Delay: unwrap phases over tones [k_lo, k_hi) and fit phase = a + 2 pi t_d f.
     const int n = a.k_hi - a.k_lo;
     double *sh = reinterpret_cast<double *>(lds);  // reuse: [256] segment sums, [256] products
-    const double *ph = a.out + N + a.k_lo;
+    const double *ph = (nwg == 1 ? s_ph : a.out + N) + a.k_lo;
     const int seg = (n + 255) / 256;
     const int s0 = t * seg;
     const int s1 = (s0 + seg) < n ? (s0 + seg) : n;
@@ -669,7 +674,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
         const double o = __shfl_up(incl, d, 64);
         if (lane >= d) incl += o;
     }
-    if (lane == 63) sh[wave] = incl;
+    if (me && lane == 63) sh[wave] = incl;
     __syncthreads();
     double before = 0.0;
     for (int w = 0; w < wave; ++w) before += sh[w];
@@ -685,7 +690,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
         sxu += (static_cast<double>(i) - kbar) * unw;
     }
     __syncthreads();
-    sh[t] = sxu;
+    if (me) sh[t] = sxu;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) sh[t] += sh[t + w];
@@ -702,12 +707,23 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
     }
     if (a.clear) {
         // start the next integration: every workgroup has read the bins
-        for (int i = t; i < kAccSlots * N; i += 256) {
+        for (int i = t; me && i < kAccSlots * N; i += 256) {
             a.acc_clear[i] = make_double2(0.0, 0.0);
             a.accf_clear[i] = make_float2(0.f, 0.f);
             a.acc_int_clear[i] = 0;
         }
     }
+}
+
+template <int NBITS, int PREC>
+__global__ void __launch_bounds__(kMaxFoldThreads) fold_kernel(FoldArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int wg = static_cast<int>(blockIdx.x);
+    if (wg >= a.fold_wgs) {  // the previous integration's finalize, fused into this launch
+        finalize_body(a.fin, wg - a.fold_wgs, a.fin_wgs, lds);
+        return;
+    }
+    fold_body<NBITS, PREC>(a, wg, lds);
 }
 
 __global__ void __launch_bounds__(256) finalize_kernel(FinArgs a) {

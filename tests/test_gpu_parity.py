@@ -263,29 +263,52 @@ def test_invalid_calls(pc):
     h.close()
 
 
-def test_results_async_pipelined(pc):
-    """Pipelined integrations: results_async(reset) equals synchronous results, and resets."""
+@pytest.mark.parametrize("case", ["n64_pinned", "n64_pageable", "n256_pinned", "lut_pinned"])
+def test_results_async_pipelined(pc, case):
+    """Pipelined integrations: results_async(reset) equals synchronous results, and resets.
+
+    With reset the finalize is deferred into the next fold launch (extra
+    workgroups, the other accumulator bank); a single-workgroup finalize writes
+    mapped pinned host memory directly, otherwise results are copied."""
     spec = synth.WORKLOADS["fold2_64M_10k"]["spec"]
+    method = pc.METHOD_AUTO
+    if case == "n256_pinned":
+        spec = synth.CombSpec(256_000_000, 1_000_000, 10_000, 2, amp=0.05, t_d=4e-9, seed=(41, 2))
+    if case == "lut_pinned":
+        method = pc.METHOD_LUT
     L = 1 << 21
-    packed = synth.make_stream(spec, 3 * L)
+    K = 5  # integrations: the two accumulator banks are each reused
+    packed = synth.make_stream(spec, (K + 1) * L)
     dev = _dev(packed)
     N = spec.ntones
-    ring = torch.zeros((3, 4 * N + 1), dtype=torch.float64, pin_memory=True)
-    with pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2) as h:
-        for i in range(3):
-            h.extract(dev[i * L // 4:], L)
+    say("results_async pipelined: %s" % case)
+    if case == "n64_pageable":
+        ring = torch.from_numpy(np.zeros((K, 4 * N + 1)))
+    else:
+        ring = torch.zeros((K, 4 * N + 1), dtype=torch.float64, pin_memory=True)
+    with pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2, method=method) as h:
+        for i in range(K):
+            h.extract(dev[i * L // 4:], L // 2)
+            h.extract(dev[i * L // 4 + L // 8:], L // 2)
             h.results_async(ring[i], reset=True)
+        # a synchronous read of the next integration sees only its own samples
+        h.extract(dev[K * L // 4:], L)
+        Cn = h.spectrum()
         h.sync()
-        assert h.info()["samples_integ"] == 0 and h.info()["samples_total"] == 3 * L
-    for i in range(3):
+        assert h.info()["samples_integ"] == L and h.info()["samples_total"] == (K + 1) * L
+    # the per-sample table form adds FP32 products per sample: the contract tolerance
+    tol = (1e-5, 1e-4, 1e-5, 1e-10) if case == "lut_pinned" else (F64_RTOL, F64_RTOL, 1e-9, 1e-13)
+    Co = oracle.correlate(packed[K * L // 4:(K + 1) * L // 4], 2, L, spec.fs, spec.f_comb, spec.f_offset, n0=K * L)
+    assert_spectra(Cn, Co, amp_rtol=tol[0], phase_atol=tol[1], what="after async resets")
+    for i in range(K):
         r = ring[i].numpy()
         C = r[2 * N:3 * N] + 1j * r[3 * N:4 * N]
         Co = oracle.correlate(packed[i * L // 4:(i + 1) * L // 4], 2, L, spec.fs, spec.f_comb, spec.f_offset,
                               n0=i * L)
-        assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="async %d" % i)
+        assert_spectra(C, Co, amp_rtol=tol[0], phase_atol=tol[1], what="async %d" % i)
         ao, po, do = oracle.results(Co, L, spec.fs, spec.f_comb, spec.f_offset)
-        np.testing.assert_allclose(r[:N], ao, rtol=1e-9)
-        assert abs(r[4 * N] - do) < 1e-13
+        np.testing.assert_allclose(r[:N], ao, rtol=tol[2])
+        assert abs(r[4 * N] - do) < tol[3]
 
 
 @pytest.mark.gpu
