@@ -119,17 +119,24 @@ int pcal_extract_timed(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_str
  * the handle's last stream; does not reset the accumulators. */
 int pcal_results(pcal_t h, double *amp, double *phase, double *delay);
 
-/* Asynchronous form of pcal_results for pipelined integrations: enqueues the
- * FP64 finalize and a copy of its output to host_out on the handle's last
- * stream and returns.  host_out (4N + 1 doubles; pinned host memory for the
- * copy to be asynchronous) receives amp[0..N), phase[N..2N), Re C[2N..3N),
- * Im C[3N..4N), delay[4N] once the stream has passed the copy (pcal_sync).
- * reset != 0 also starts the next integration, in the same launch (the
- * finalize clears the accumulators after reading them).  host_out must stay
- * valid until then. */
+/* Asynchronous form of pcal_results for pipelined integrations.  host_out
+ * (4N + 1 doubles) receives amp[0..N), phase[N..2N), Re C[2N..3N),
+ * Im C[3N..4N), delay[4N]; it must stay valid until pcal_sync returns.
+ * reset == 0: enqueues the FP64 finalize and a copy to host_out on the
+ *   handle's last stream; the integration goes on.
+ * reset != 0: finishes the integration and starts the next one.  The handle
+ *   keeps its bins in two banks: the finalize of the current bank (which also
+ *   clears it) is left pending and the handle switches banks, so the next
+ *   pcal_extract runs that finalize inside its own launch, in one of its
+ *   workgroups (period fold; the per-sample forms run it at once).  Any other
+ *   call on the handle runs a pending finalize on its own first; pcal_sync
+ *   runs it and waits.  With N <= 64 and host_out in pinned (mapped) host
+ *   memory the finalize writes host_out directly; otherwise a device copy is
+ *   enqueued after it. */
 int pcal_results_async(pcal_t h, double *host_out, int reset);
 
-/* Wait until all work enqueued on the handle has finished. */
+/* Run any pending finalize and wait until all work enqueued on the handle has
+ * finished. */
 int pcal_sync(pcal_t h);
 
 /* The raw C_k (k = 0..N-1) of the current integration, FP64 real and imaginary
