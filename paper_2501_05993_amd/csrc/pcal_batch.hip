@@ -248,31 +248,36 @@ int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *co
     if ((rc = order_members(b, count, ids, s))) return rc;
     Stage *st = nullptr;
     if ((rc = take_stage(b, &st))) return rc;
-    int n = 0, grid = 0, threads = 64;
-    size_t lds = 0;
-    for (int i = 0; i < count; ++i) {
-        if (nsamples[i] == 0) continue;
-        pcal_ctx *h = b->members[ids[i]];
-        const Plan &p = h->plan;
-        const int64_t bytes = nsamples[i] * p.nbits / 8;
-        const int target = static_cast<int>(std::max<int64_t>(
-            p.geom.col_tiles, (b->target_blocks * bytes + total_bytes - 1) / total_bytes));
-        const pcal_launch_t L =
-            plan_launch(p, reinterpret_cast<uintptr_t>(dev_ptrs[i]), h->n_total, nsamples[i], target);
-        st->h_items[n] = fold_args(h, L, dev_ptrs[i]);
-        st->h_first[n] = grid;
-        grid += static_cast<int>(L.grid);
-        threads = std::max(threads, p.geom.threads);
-        ++n;
-    }
-    for (int i = 0; i < n; ++i) {
-        const FoldArgs &a = st->h_items[i];
-        lds = std::max(lds, fold_lds_bytes(a.npos, a.nbits == 2 ? 64 : 16, threads, a.M));
+    // The work-list holds the 2-bit items first, then the 8-bit ones (one fold
+    // launch per sample width).
+    int n = 0, grid = 0, grid2 = 0, threads = 64;
+    for (int i = 0; i < count; ++i)
+        if (nsamples[i] > 0) threads = std::max(threads, b->members[ids[i]]->plan.geom.threads);
+    size_t lds[2] = {0, 0};
+    for (int pass = 0; pass < 2; ++pass) {
+        const int width = pass == 0 ? 2 : 8;
+        for (int i = 0; i < count; ++i) {
+            if (nsamples[i] == 0 || b->members[ids[i]]->plan.nbits != width) continue;
+            pcal_ctx *h = b->members[ids[i]];
+            const Plan &p = h->plan;
+            const int64_t bytes = nsamples[i] * p.nbits / 8;
+            const int target = static_cast<int>(std::max<int64_t>(
+                p.geom.col_tiles, (b->target_blocks * bytes + total_bytes - 1) / total_bytes));
+            const pcal_launch_t L =
+                plan_launch(p, reinterpret_cast<uintptr_t>(dev_ptrs[i]), h->n_total, nsamples[i], target);
+            st->h_items[n] = fold_args(h, L, dev_ptrs[i]);
+            st->h_first[n] = grid;
+            grid += static_cast<int>(L.grid);
+            const FoldArgs &a = st->h_items[n];
+            lds[pass] = std::max(lds[pass], fold_lds_bytes(a.npos, p.geom.spv, threads, a.M));
+            ++n;
+        }
+        if (pass == 0) grid2 = grid;
     }
     st->h_first[n] = grid;
     PCAL_HIP(hipMemcpyAsync(st->d_items, st->h_items, sizeof(FoldArgs) * n, hipMemcpyHostToDevice, s));
     PCAL_HIP(hipMemcpyAsync(st->d_first, st->h_first, sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
-    launch_fold_batch(st->d_items, st->d_first, n, b->prec, grid, threads, lds, s);
+    launch_fold_batch(st->d_items, st->d_first, n, b->prec, grid2, grid - grid2, threads, lds[0], lds[1], s);
     PCAL_HIP(hipGetLastError());
     PCAL_HIP(hipEventRecord(st->done, s));
     st->pending = true;

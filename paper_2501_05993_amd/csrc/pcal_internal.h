@@ -159,8 +159,10 @@ void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds
                  hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // Fold workgroups of the given shape resident at once on one compute unit (0 on error).
 int fold_blocks_per_cu(int nbits, int prec, int threads, size_t lds);
-void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int prec, int grid, int threads,
-                       size_t lds, hipStream_t s);
+// Work-list items [0, n2) are 2-bit and own workgroups [0, grid2); the rest
+// are 8-bit and own the next grid8 workgroups.  One launch per width.
+void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int prec, int grid2, int grid8,
+                       int threads, size_t lds2, size_t lds8, hipStream_t s);
 void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStream_t s,
                    hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_finalize(const FinArgs &a, hipStream_t s);

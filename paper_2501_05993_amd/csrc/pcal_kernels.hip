@@ -35,15 +35,38 @@ constexpr int kTwLdsMaxTones = 1792;
 
 // The packed stream is read once: non-temporal 16-byte loads keep it from
 // displacing reusable lines in the caches.
+//
+// Every device read goes through a pointer in the global address space.  The
+// batched kernel takes its pointers from memory, where the compiler cannot
+// tell global memory from LDS and would emit flat loads; a flat load counts on
+// both wait counters, and with one pending the compiler's waits for the
+// stream's loads all become waits for every load.
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef const u32x4_t __attribute__((address_space(1))) *global_u32x4_ptr;
 __device__ __forceinline__ uint4 load_stream(const uint4 *p) {
-    const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(p));
+    const u32x4_t v = __builtin_nontemporal_load((global_u32x4_ptr)p);
     return make_uint4(v.x, v.y, v.z, v.w);
+}
+// (A struct is loaded as a raw vector of its size: its copy constructor would
+// take the address back to the generic space.)
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+template <int B> struct RawOf;
+template <> struct RawOf<1> { using T = uint8_t; };
+template <> struct RawOf<4> { using T = uint32_t; };
+template <> struct RawOf<8> { using T = u32x2_t; };
+template <> struct RawOf<16> { using T = u32x4_t; };
+template <class T>
+__device__ __forceinline__ T load_global(const T *p) {
+    using V = typename RawOf<sizeof(T)>::T;
+    const V v = *(const __attribute__((address_space(1))) V *)p;
+    T r;
+    __builtin_memcpy(&r, &v, sizeof(T));
+    return r;
 }
 
 __device__ __forceinline__ int level_of(const uint8_t *p, int nbits, int i) {
-    if (nbits == 2) return 2 * ((p[i >> 2] >> (2 * (i & 3))) & 3) - 3;
-    return static_cast<int>(static_cast<int8_t>(p[i]));
+    if (nbits == 2) return 2 * ((load_global(p + (i >> 2)) >> (2 * (i & 3))) & 3) - 3;
+    return static_cast<int>(static_cast<int8_t>(load_global(p + i)));
 }
 
 // True in every thread of the workgroup that finishes last (all workgroups
@@ -338,14 +361,15 @@ struct BinAcc<2> {
 template <int PREC>
 __device__ __forceinline__ typename BinAcc<PREC>::Tab table_row(const FoldArgs &a, int m) {
     if constexpr (PREC == 0)
-        return a.u64[m];
+        return load_global(a.u64 + m);
     else if constexpr (PREC == 1) {
         // two FP16 terms; their FP32 sum is exact
-        const float2 hi = __half22float2(a.u16[2 * m]), lo = __half22float2(a.u16[2 * m + 1]);
+        const float2 hi = __half22float2(load_global(a.u16 + 2 * m));
+        const float2 lo = __half22float2(load_global(a.u16 + 2 * m + 1));
         return make_float2(hi.x + lo.x, hi.y + lo.y);
     }
     else
-        return a.u32[m];
+        return load_global(a.u32 + m);
 }
 
 // Add one workgroup's bin b (before v) to the integration accumulators:
@@ -397,6 +421,12 @@ __device__ __forceinline__ void fold_body(const FoldArgs &a, const int wg, unsig
     using Acc = BinAcc<PREC>;
     using Tab = typename Acc::Tab;
     static_assert(sizeof(Acc) <= kEpilogueScratch, "epilogue scratch");
+    // Start the walk with no memory operation outstanding.  Code that may run
+    // before it in the same kernel (the fused finalize's stores, whose path
+    // the compiler joins to this one) would otherwise leave mixed kinds of
+    // operations pending in the compiler's wait accounting, which then waits
+    // for every load in the walk instead of keeping two groups in flight.
+    __builtin_amdgcn_s_waitcnt(0);
     constexpr int SPV = NBITS == 2 ? 64 : 16;
     constexpr int kPre = 4;  // rotator rows prefetched per thread
     const int t = threadIdx.x, nt = blockDim.x;
@@ -407,7 +437,7 @@ __device__ __forceinline__ void fold_body(const FoldArgs &a, const int wg, unsig
     const int M = static_cast<int>(a.M);
 
     // v[b] of the bin this thread commits (group form), loaded now.
-    const double2 vb = (a.N < nt && t < a.N) ? a.v[t] : make_double2(0.0, 0.0);
+    const double2 vb = (a.N < nt && t < a.N) ? load_global(a.v + t) : make_double2(0.0, 0.0);
     // Rotator rows: loads issued now, stored to LDS after the walk.
     Tab upre[kPre];
 #pragma unroll
@@ -483,7 +513,7 @@ __device__ __forceinline__ void fold_body(const FoldArgs &a, const int wg, unsig
                 if (++m == M) m = 0;
             }
             if (edges) add_edges<PREC>(a, b, acc, UL, u_lds);
-            commit_bin<PREC>(a, wg, b, acc, a.v[b]);
+            commit_bin<PREC>(a, wg, b, acc, load_global(a.v + b));
         }
     } else {
         // G groups of N threads split the positions of every bin; the group
@@ -531,19 +561,20 @@ __device__ __forceinline__ int owner_of(const int *first, int nitems, int wg) {
     return lo;
 }
 
-// One launch over the work items of many streams (each item: one stream's
-// launch geometry, tables and accumulators; first[i] = its first workgroup).
-template <int PREC>
+// One launch over the work items of many streams of one sample width (each
+// item: one stream's launch geometry, tables and accumulators; first[i] = its
+// first workgroup).  Workgroup blockIdx.x is workgroup wg0 + blockIdx.x of the
+// work-list, so that the 2-bit and 8-bit items of one work-list (2-bit first)
+// go to two launches: with both bodies in one kernel, the compiler's wait
+// accounting carries the pending operations of one body into the other.
+template <int NBITS, int PREC>
 __global__ void __launch_bounds__(kMaxFoldThreads) fold_batch_kernel(const FoldArgs *items, const int *first,
-                                                                      int nitems) {
+                                                                      int nitems, int wg0) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const int wg = static_cast<int>(blockIdx.x);
+    const int wg = wg0 + static_cast<int>(blockIdx.x);
     const int i = __builtin_amdgcn_readfirstlane(owner_of(first, nitems, wg));
     const FoldArgs a = items[i];
-    if (a.nbits == 2)
-        fold_body<2, PREC>(a, wg - first[i], lds);
-    else
-        fold_body<8, PREC>(a, wg - first[i], lds);
+    fold_body<NBITS, PREC>(a, wg - first[i], lds);
 }
 
 // ---------------------------------------------------------------- finalize
@@ -796,15 +827,28 @@ int fold_blocks_per_cu(int nbits, int prec, int threads, size_t lds) {
     return n;
 }
 
-void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int prec, int grid, int threads,
-                       size_t lds, hipStream_t s) {
-    const dim3 gd(grid), bd(threads);
-    if (prec == 0)
-        hipLaunchKernelGGL((fold_batch_kernel<0>), gd, bd, lds, s, items, first, nitems);
-    else if (prec == 1)
-        hipLaunchKernelGGL((fold_batch_kernel<1>), gd, bd, lds, s, items, first, nitems);
-    else
-        hipLaunchKernelGGL((fold_batch_kernel<2>), gd, bd, lds, s, items, first, nitems);
+void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int prec, int grid2, int grid8,
+                       int threads, size_t lds2, size_t lds8, hipStream_t s) {
+    const dim3 bd(threads);
+#define PCAL_BATCH_LAUNCH(NB, PR, G, L, W0) \
+    hipLaunchKernelGGL((fold_batch_kernel<NB, PR>), dim3(G), bd, L, s, items, first, nitems, W0)
+    if (grid2 > 0) {
+        if (prec == 0)
+            PCAL_BATCH_LAUNCH(2, 0, grid2, lds2, 0);
+        else if (prec == 1)
+            PCAL_BATCH_LAUNCH(2, 1, grid2, lds2, 0);
+        else
+            PCAL_BATCH_LAUNCH(2, 2, grid2, lds2, 0);
+    }
+    if (grid8 > 0) {
+        if (prec == 0)
+            PCAL_BATCH_LAUNCH(8, 0, grid8, lds8, grid2);
+        else if (prec == 1)
+            PCAL_BATCH_LAUNCH(8, 1, grid8, lds8, grid2);
+        else
+            PCAL_BATCH_LAUNCH(8, 2, grid8, lds8, grid2);
+    }
+#undef PCAL_BATCH_LAUNCH
 }
 
 void launch_finalize(const FinArgs &a, hipStream_t s) {
