@@ -122,6 +122,15 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
     p->R = fs / gcd64(fs, fo);  // Eq. 4 (gcd(fs, 0) = fs gives R = 1)
     p->S = lcm_capped(p->N, p->R, kMaxFoldPeriod);
     p->Sp = p->S > 0 ? lcm_capped(p->S, spv_of(nbits), kMaxFoldPeriod) : -1;
+    // A fold period of fewer than 64 vectors puts several lanes of a wave on
+    // the same period positions, and their flushes to LDS collide (64 lanes on
+    // one address at one vector per period).  Any multiple of the period folds
+    // the same (rotator and bins repeat with it), so a short period is widened
+    // to the first multiple of at least 64 vectors.
+    if (p->Sp > 0 && p->Sp < 64 * spv_of(nbits)) {
+        const int64_t W = p->Sp / spv_of(nbits);
+        p->Sp *= (64 + W - 1) / W;
+    }
     p->M = p->Sp > 0 ? p->Sp / p->N : -1;
     const bool fold_ok = p->Sp > 0 && p->M <= kMaxTableRows;
     const bool osc_ok = fs < (int64_t(1) << 32);
