@@ -76,11 +76,12 @@ FoldGeom plan_geom(int64_t Sp, int spv, int64_t max_positions, int max_threads, 
     const int pref = force_threads ? force_threads : env_int("PCAL_FOLD_THREADS", 0);
     // columns of one period per workgroup: the whole period when it fits the
     // LDS position budget and the workgroup, else equal tiles within both
+    // (split tiles are whole 128-byte lines wide: 8 vectors)
     int64_t tile = W;
     if (Sp > max_positions || W > max_threads) {
-        const int64_t tile_max = std::min<int64_t>(max_threads, max_positions / g.spv);
+        const int64_t tile_max = std::min<int64_t>(max_threads, max_positions / g.spv) / 8 * 8;
         const int64_t tiles = (W + tile_max - 1) / tile_max;
-        tile = (W + tiles - 1) / tiles;
+        tile = ((W + tiles - 1) / tiles + 7) / 8 * 8;
     }
     g.tile_vecs = static_cast<int>(tile);
     g.col_tiles = static_cast<int>((W + tile - 1) / tile);

@@ -11,8 +11,10 @@ namespace pcal {
 // Samples per 16-byte vector load for each sample format.
 constexpr int spv_of(int nbits) { return nbits == 2 ? 64 : 16; }
 
-// Largest number of period positions a fold workgroup keeps in LDS (int32 each).
-constexpr int kMaxLdsPositions = 12288;
+// Largest number of period positions a fold workgroup keeps in LDS (int32 each):
+// 200 vectors of 2-bit samples, with the skew, the spare column and a 512-row
+// FP64 table under 64 KiB.
+constexpr int kMaxLdsPositions = 12800;
 // Rotator rows (u table) kept in LDS by the fold kernel when the table is at most this long.
 constexpr int kLdsTableRows = 512;
 // Per-thread LDS scratch of the fold epilogue (a partial bin sum in every precision).

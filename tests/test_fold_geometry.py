@@ -112,7 +112,7 @@ def test_walk_bounds_coverage_and_period(fs, fc, fo, nbits, ns, addr, before):
     assert L["threads"] % 64 == 0 and L["threads"] <= 1024
     assert L["threads"] >= L["tile_vecs"]
     assert L["lds_bytes"] <= 65536
-    assert info["lds_positions"] <= 12288
+    assert info["lds_positions"] <= 12800
     npos_sk = info["lds_positions"] + info["lds_positions"] // spv     # skewed position sums
     assert L["lds_bytes"] >= 4 * npos_sk and L["lds_bytes"] >= 40 * L["threads"]
     assert info["row_vectors"] * spv % Sp == 0          # rows are whole fold periods
