@@ -247,6 +247,52 @@ def precision_report(pcal, torch, synth):
     return out
 
 
+def rotator_study(pcal, torch, synth):
+    """8-bit wide workload (fs = 1024 MHz, f_offset = 510 kHz, N = 1024, rotator period 102400): one
+    integration of 2^33 samples streamed in 2^28-sample chunks (the global sample index runs on across
+    chunks) through each rotator form -- the period fold, the per-sample rotator table and the recurrence
+    (Eq. 7) -- timed with events around the 32 launches, with each form's HBM roofline fraction (1 B per
+    sample read once) and its spectrum's spread against the period fold's (tones with signal)."""
+    w = synth.WORKLOADS["wide8_1024M_510k"]
+    spec, L, chunk = w["spec"], w["nsamples"], w["chunk"]
+    print("[bench] rotator study: generating %d GiB of 8-bit samples" % (L >> 30), file=sys.stderr, flush=True)
+    buf = synth.make_stream_device(spec, L)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    forms = (("period_fold", pcal.METHOD_PERIOD_FOLD), ("table", pcal.METHOD_LUT), ("recurrence", pcal.METHOD_OSC))
+    out, spectra = {}, {}
+    for name, method in forms:
+        h = pcal.PCal(spec.fs, spec.f_comb, spec.f_offset, spec.nbits, method=method)
+        h.extract(buf, chunk)  # warm-up chunk, then a fresh integration (global index continues)
+        torch.cuda.synchronize()
+        h.reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(L // chunk):
+            h.extract(buf, chunk, byte_offset=k * chunk)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3
+        spectra[name] = h.spectrum()
+        gbs = L / t / 1e9  # 1 B per sample
+        out[name] = {"ms_per_integration": round(t * 1e3, 3), "gsamples_per_s": round(L / t / 1e9, 1),
+                     "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+        h.close()
+    ref = spectra["period_fold"]
+    strong = np.abs(ref) >= 1e-3 * np.abs(ref).max()
+    for name, _ in forms[1:]:
+        c = spectra[name]
+        out[name]["vs_period_fold"] = {
+            "amp_rel_err_max": float(np.max(np.abs(np.abs(c[strong]) - np.abs(ref[strong])) / np.abs(ref[strong]))),
+            "phase_err_rad_max": float(np.max(np.abs(np.angle(c[strong] * np.conj(ref[strong]))))),
+        }
+    del buf
+    torch.cuda.empty_cache()
+    return {"workload": "8-bit, fs 1024 MHz, f_comb 1 MHz (N = 1024), f_offset 510 kHz, 2^33 samples in "
+                        "2^28-sample chunks, one integration per form", **out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +302,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--precision-report", action="store_true",
                     help="only run the 64-stream precision study (mixed and FP32 forms against FP64)")
+    ap.add_argument("--no-rotator-study", action="store_true",
+                    help="skip the 8-bit wide-workload comparison of the rotator forms")
     ap.add_argument("--served-seconds", type=float, default=8.0,
                     help="length of the serving-study arrival trace (0: skip the serving study)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -383,9 +431,11 @@ def main():
         host = bufs[0].cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(host, spec)
     h.close()
+    bufs.clear()
+    torch.cuda.empty_cache()
+    if not args.no_rotator_study:
+        out["rotator_study"] = rotator_study(pcal, torch, synth)
     if args.served_seconds > 0:
-        bufs.clear()
-        torch.cuda.empty_cache()
         print("[bench] serving study: %.0f s trace, 256 streams" % args.served_seconds, file=sys.stderr, flush=True)
         setup = _served_setup(torch, synth, args.served_seconds)
         served = served_run(pcal, torch, setup, "served")
