@@ -67,8 +67,11 @@ int check_params(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband) {
 // Fold geometry.  One tile holds the whole period when it fits the LDS
 // position budget: then a row is k periods long and the workgroup size is
 // picked to waste the fewest lanes.  Otherwise a row is one period, split
-// into equal column tiles of at most the budget.
-FoldGeom plan_geom(int64_t Sp, int spv, int64_t max_positions, int max_threads, int force_threads) {
+// into equal column tiles of at most the budget.  Among workgroup sizes that
+// waste equally few lanes, the one nearest aim_threads is taken (0: the
+// smallest); sizes below min_threads are not considered unless none fits.
+FoldGeom plan_geom(int64_t Sp, int spv, int64_t max_positions, int max_threads, int force_threads,
+                   int min_threads, int aim_threads) {
     FoldGeom g{};
     g.spv = spv;
     const int64_t W = Sp / g.spv;  // vectors per period
@@ -90,12 +93,13 @@ FoldGeom plan_geom(int64_t Sp, int spv, int64_t max_positions, int max_threads, 
     // workgroup size: k sub-rows of one tile each, wasting the fewest lanes
     int best_t = 0;
     double best = -1.0;
-    for (int t = 256; t <= max_threads; t += 64) {
+    for (int t = pref ? pref : std::min(min_threads, max_threads) / 64 * 64; t <= max_threads; t += 64) {
         if (pref && t != pref) continue;
         const int64_t k = t / tile;
         if (k < 1) continue;
         const double eff = static_cast<double>(k * tile) / t;
-        if (eff > best + 1e-9) {
+        const bool nearer = aim_threads > 0 && std::abs(t - aim_threads) < std::abs(best_t - aim_threads);
+        if (eff > best + 1e-9 || (eff > best - 1e-9 && nearer)) {
             best = eff;
             best_t = t;
         }
@@ -144,11 +148,12 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
     if (method == PCAL_METHOD_OSC && !osc_ok) return PCAL_ENOTSUP;
     p->method = method;
     if (method == PCAL_METHOD_PERIOD_FOLD) {
-        p->geom = plan_geom(p->Sp, spv_of(nbits), kMaxLdsPositions, kMaxFoldThreads, force_threads);
+        p->geom = plan_geom(p->Sp, spv_of(nbits), kMaxLdsPositions, kMaxFoldThreads, force_threads,
+                            kMinFoldThreads, kAimFoldThreads);
     } else {
         // rows of a multiple of lcm(N, 16) samples: every lane keeps its bin
         const int64_t per = p->N / gcd64(p->N, kRotLanes) * kRotLanes;
-        p->geom = plan_geom(per, kRotLanes, INT64_MAX, kMaxRotThreads, force_threads);
+        p->geom = plan_geom(per, kRotLanes, INT64_MAX, kMaxRotThreads, force_threads, 256, 0);
     }
     {
         const int sp = env_int("PCAL_SYNC_PAIRS", kSyncPairs);  // power of two or 0
