@@ -19,18 +19,28 @@ constexpr int kBatchThreads = 512;        // workgroup size members are planned 
 constexpr int kBatchTargetBlocks = 2048;  // workgroups per batched launch, split by bytes (PCAL_BATCH_BLOCKS)
 constexpr int kStages = 4;                // pinned staging buffers in flight
 
-// Host staging of one launch's work-list (pinned) and its device copy.
+// Host staging of one launch's work-list (pinned) and its device copy: one
+// block holding first[] (the first workgroup of each item, then the total),
+// then the items (FoldArgs, FinArgs or ZeroItem: one kind per use), so that a
+// work-list goes to the device in one copy.
 struct Stage {
-    FoldArgs *h_items = nullptr;
+    unsigned char *h_buf = nullptr;
+    unsigned char *d_buf = nullptr;
+    size_t off_items = 0;       // byte offset of the items in both blocks
     int *h_first = nullptr;
+    FoldArgs *h_items = nullptr;
     FinArgs *h_fin = nullptr;
     ZeroItem *h_zero = nullptr;
-    FoldArgs *d_items = nullptr;
-    int *d_first = nullptr;
-    FinArgs *d_fin = nullptr;
-    ZeroItem *d_zero = nullptr;
     hipEvent_t done = nullptr;  // the launch that read this stage has been enqueued past this event
     bool pending = false;
+    const int *d_first() const { return reinterpret_cast<const int *>(d_buf); }
+    template <class T>
+    const T *d_items() const { return reinterpret_cast<const T *>(d_buf + off_items); }
+    // copy first[0..nfirst) and items [0, item_bytes) to the device (one transfer)
+    hipError_t upload(int nfirst, size_t item_bytes, hipStream_t s) const {
+        const size_t bytes = item_bytes ? off_items + item_bytes : sizeof(int) * nfirst;
+        return hipMemcpyAsync(d_buf, h_buf, bytes, hipMemcpyHostToDevice, s);
+    }
 };
 
 }  // namespace
@@ -53,29 +63,22 @@ struct pcal_batch_ctx {
 namespace {
 
 int stage_alloc(Stage &st, int n) {
-    const size_t nf = sizeof(FoldArgs) * n, ni = sizeof(int) * (n + 1), nfin = sizeof(FinArgs) * n,
-                 nz = sizeof(ZeroItem) * 3 * n;
-    PCAL_HIP(hipHostMalloc(reinterpret_cast<void **>(&st.h_items), nf, hipHostMallocDefault));
-    PCAL_HIP(hipHostMalloc(reinterpret_cast<void **>(&st.h_first), ni, hipHostMallocDefault));
-    PCAL_HIP(hipHostMalloc(reinterpret_cast<void **>(&st.h_fin), nfin, hipHostMallocDefault));
-    PCAL_HIP(hipHostMalloc(reinterpret_cast<void **>(&st.h_zero), nz, hipHostMallocDefault));
-    PCAL_HIP(hipMalloc(reinterpret_cast<void **>(&st.d_items), nf));
-    PCAL_HIP(hipMalloc(reinterpret_cast<void **>(&st.d_first), ni));
-    PCAL_HIP(hipMalloc(reinterpret_cast<void **>(&st.d_fin), nfin));
-    PCAL_HIP(hipMalloc(reinterpret_cast<void **>(&st.d_zero), nz));
+    st.off_items = (sizeof(int) * (n + 1) + 255) & ~static_cast<size_t>(255);
+    const size_t item_cap = std::max(std::max(sizeof(FoldArgs), sizeof(FinArgs)), 3 * sizeof(ZeroItem)) * n;
+    const size_t bytes = st.off_items + item_cap;
+    PCAL_HIP(hipHostMalloc(reinterpret_cast<void **>(&st.h_buf), bytes, hipHostMallocDefault));
+    PCAL_HIP(hipMalloc(reinterpret_cast<void **>(&st.d_buf), bytes));
+    st.h_first = reinterpret_cast<int *>(st.h_buf);
+    st.h_items = reinterpret_cast<FoldArgs *>(st.h_buf + st.off_items);
+    st.h_fin = reinterpret_cast<FinArgs *>(st.h_buf + st.off_items);
+    st.h_zero = reinterpret_cast<ZeroItem *>(st.h_buf + st.off_items);
     PCAL_HIP(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
     return PCAL_OK;
 }
 
 void stage_free(Stage &st) {
-    if (st.h_items) (void)hipHostFree(st.h_items);
-    if (st.h_first) (void)hipHostFree(st.h_first);
-    if (st.h_fin) (void)hipHostFree(st.h_fin);
-    if (st.h_zero) (void)hipHostFree(st.h_zero);
-    if (st.d_items) (void)hipFree(st.d_items);
-    if (st.d_first) (void)hipFree(st.d_first);
-    if (st.d_fin) (void)hipFree(st.d_fin);
-    if (st.d_zero) (void)hipFree(st.d_zero);
+    if (st.h_buf) (void)hipHostFree(st.h_buf);
+    if (st.d_buf) (void)hipFree(st.d_buf);
     if (st.done) (void)hipEventDestroy(st.done);
 }
 
@@ -145,9 +148,8 @@ int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, hipStream
         h->n_integ = 0;
     }
     st->h_first[count] = grid;
-    PCAL_HIP(hipMemcpyAsync(st->d_fin, st->h_fin, sizeof(FinArgs) * count, hipMemcpyHostToDevice, s));
-    PCAL_HIP(hipMemcpyAsync(st->d_first, st->h_first, sizeof(int) * (count + 1), hipMemcpyHostToDevice, s));
-    launch_finalize_batch(st->d_fin, st->d_first, count, grid, lds, s);
+    PCAL_HIP(st->upload(count + 1, sizeof(FinArgs) * count, s));
+    launch_finalize_batch(st->d_items<FinArgs>(), st->d_first(), count, grid, lds, s);
     PCAL_HIP(hipGetLastError());
     PCAL_HIP(hipEventRecord(st->done, s));
     st->pending = true;
@@ -275,9 +277,9 @@ int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *co
         if (pass == 0) grid2 = grid;
     }
     st->h_first[n] = grid;
-    PCAL_HIP(hipMemcpyAsync(st->d_items, st->h_items, sizeof(FoldArgs) * n, hipMemcpyHostToDevice, s));
-    PCAL_HIP(hipMemcpyAsync(st->d_first, st->h_first, sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
-    launch_fold_batch(st->d_items, st->d_first, n, b->prec, grid2, grid - grid2, threads, lds[0], lds[1], s);
+    PCAL_HIP(st->upload(n + 1, sizeof(FoldArgs) * n, s));
+    launch_fold_batch(st->d_items<FoldArgs>(), st->d_first(), n, b->prec, grid2, grid - grid2, threads, lds[0],
+                      lds[1], s);
     PCAL_HIP(hipGetLastError());
     PCAL_HIP(hipEventRecord(st->done, s));
     st->pending = true;
@@ -321,9 +323,8 @@ int pcal_batch_results(pcal_batch_t b, int count, const int *ids, double *amp, d
         off += 4 * static_cast<size_t>(h->plan.N) + 1;
     }
     st->h_first[count] = grid;
-    PCAL_HIP(hipMemcpyAsync(st->d_fin, st->h_fin, sizeof(FinArgs) * count, hipMemcpyHostToDevice, s));
-    PCAL_HIP(hipMemcpyAsync(st->d_first, st->h_first, sizeof(int) * (count + 1), hipMemcpyHostToDevice, s));
-    launch_finalize_batch(st->d_fin, st->d_first, count, grid, lds, s);
+    PCAL_HIP(st->upload(count + 1, sizeof(FinArgs) * count, s));
+    launch_finalize_batch(st->d_items<FinArgs>(), st->d_first(), count, grid, lds, s);
     PCAL_HIP(hipGetLastError());
     PCAL_HIP(hipEventRecord(st->done, s));
     st->pending = true;
@@ -377,8 +378,8 @@ int pcal_batch_reset(pcal_batch_t b, int count, const int *ids) {
         st->h_zero[n++] = ZeroItem{h->acc_int, sizeof(long long) * N};
         h->n_integ = 0;
     }
-    PCAL_HIP(hipMemcpyAsync(st->d_zero, st->h_zero, sizeof(ZeroItem) * n, hipMemcpyHostToDevice, s));
-    launch_zero_list(st->d_zero, n, s);
+    PCAL_HIP(hipMemcpyAsync(st->d_buf + st->off_items, st->h_zero, sizeof(ZeroItem) * n, hipMemcpyHostToDevice, s));
+    launch_zero_list(st->d_items<ZeroItem>(), n, s);
     PCAL_HIP(hipGetLastError());
     PCAL_HIP(hipEventRecord(st->done, s));
     st->pending = true;

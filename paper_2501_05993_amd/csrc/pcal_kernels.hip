@@ -550,15 +550,17 @@ __device__ __forceinline__ void fold_body(const FoldArgs &a, const int wg, unsig
 
 // Index of the work item that owns workgroup `wg`: the last i with first[i] <= wg.
 __device__ __forceinline__ int owner_of(const int *first, int nitems, int wg) {
-    int lo = 0, hi = nitems - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (first[mid] <= wg)
-            lo = mid;
-        else
-            hi = mid - 1;
+    // first[] increases strictly (every item owns a workgroup): the owner is the
+    // number of items starting at or before wg, less one.  One wave-wide load
+    // per 64 items instead of a chain of dependent loads.
+    const int lane = static_cast<int>(threadIdx.x) & 63;
+    int count = 0;
+    for (int j0 = 0; j0 < nitems; j0 += 64) {
+        const int j = j0 + lane;
+        const bool at_or_before = j < nitems && load_global(first + j) <= wg;
+        count += __popcll(__ballot(at_or_before));
     }
-    return lo;
+    return count - 1;
 }
 
 // One launch over the work items of many streams of one sample width (each
