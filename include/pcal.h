@@ -130,8 +130,8 @@ int pcal_results(pcal_t h, double *amp, double *phase, double *delay);
  *   pcal_extract runs that finalize inside its own launch, in one of its
  *   workgroups (period fold; the per-sample forms run it at once).  Any other
  *   call on the handle runs a pending finalize on its own first; pcal_sync
- *   runs it and waits.  With N <= 64 and host_out in pinned (mapped) host
- *   memory the finalize writes host_out directly; otherwise a device copy is
+ *   runs it and waits.  With host_out in pinned host memory (hipHostMalloc)
+ *   the finalize writes host_out directly; otherwise a device copy is
  *   enqueued after it. */
 int pcal_results_async(pcal_t h, double *host_out, int reset);
 

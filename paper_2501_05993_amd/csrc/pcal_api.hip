@@ -249,7 +249,7 @@ int dalloc(pcal_ctx *h, T **p, size_t count) {
 
 void release(pcal_ctx *h) {
     void *ptrs[] = {h->u64, h->u32, h->u16, h->v, h->tw, h->acc_mem, h->acc_int_mem, h->accf_mem, h->counters,
-                    h->out, h->rot32, h->rot16, h->w};
+                    h->out, h->phases, h->rot32, h->rot16, h->w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->host_out) (void)hipHostFree(h->host_out);
@@ -368,7 +368,8 @@ int build(pcal_ctx *h) {
     if ((rc = dalloc(h, &h->u64, M)) || (rc = dalloc(h, &h->u32, M)) || (rc = dalloc(h, &h->u16, 2 * M)) ||
         (rc = dalloc(h, &h->v, N)) || (rc = dalloc(h, &h->tw, N)) || (rc = dalloc(h, &h->acc_mem, 2 * kAccSlots * N)) ||
         (rc = dalloc(h, &h->acc_int_mem, 2 * kAccSlots * N)) || (rc = dalloc(h, &h->accf_mem, 2 * kAccSlots * N)) ||
-        (rc = dalloc(h, &h->counters, 2)) || (rc = dalloc(h, &h->out, 2 * (4 * N + 1))))
+        (rc = dalloc(h, &h->counters, 2)) || (rc = dalloc(h, &h->out, 2 * (4 * N + 1))) ||
+        (rc = dalloc(h, &h->phases, N)))
         return rc;
     {
         hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->host_out), sizeof(double) * (4 * N + 1),
@@ -468,6 +469,7 @@ FinArgs fin_args(const pcal_ctx *h, double *out) {
     f.gain_re = h->gain_re;
     f.gain_im = h->gain_im;
     f.out = out;
+    f.phases = h->phases;
     f.counter = h->counters;
     f.clear = 0;
     f.acc_clear = h->acc;
@@ -716,10 +718,11 @@ int pcal_results_async(pcal_t h, double *host_out, int reset) {
     }
     // Finish the integration: its finalize (reading and clearing the current
     // bank) is left pending for the next fold launch, and the handle moves on
-    // to the other bank.  One workgroup (N <= 64) writes the results straight
-    // into mapped pinned host memory; otherwise a device buffer is copied.
+    // to the other bank.  The finalize writes the results straight into
+    // host_out when that is pinned host memory mapped for the device;
+    // otherwise into a device buffer that is then copied.
     const int b = h->bank;
-    double *dev_host = p.N <= 64 ? mapped_results(h, host_out) : nullptr;
+    double *dev_host = mapped_results(h, host_out);
     double *out = dev_host ? dev_host : h->out + static_cast<size_t>(b) * (4 * p.N + 1);
     h->fin = fin_args(h, out);
     h->fin.counter = h->counters + b;

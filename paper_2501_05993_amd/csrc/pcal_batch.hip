@@ -129,7 +129,7 @@ namespace host {
 // Batched finalize of members ids[0..count) that reads and clears their bins
 // (the next integration starts at zero); each member's results land in its
 // own device buffer h->out.  Asynchronous on s.
-int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, hipStream_t s) {
+int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, double *const *outs, hipStream_t s) {
     int rc = check_ids(b, count, ids);
     if (rc || count == 0) return rc;
     DeviceGuard guard(b->members[ids[0]]->device);
@@ -140,7 +140,7 @@ int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, hipStream
     size_t lds = 0;
     for (int i = 0; i < count; ++i) {
         pcal_ctx *h = b->members[ids[i]];
-        st->h_fin[i] = fin_args(h, h->out);
+        st->h_fin[i] = fin_args(h, outs && outs[i] ? outs[i] : h->out);
         st->h_fin[i].clear = 1;
         st->h_first[i] = grid;
         grid += static_cast<int>((h->plan.N + 63) / 64);

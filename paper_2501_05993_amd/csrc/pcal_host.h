@@ -89,6 +89,7 @@ struct pcal_ctx {
         double *dev;  // null: not device-accessible
     } map_cache[8] = {};
     int map_next = 0;
+    double *phases = nullptr;      // [N] phases the last finalize workgroup reads back
     unsigned *counters = nullptr;  // [0] finalize of bank 0's pending form / plain, [1] bank 1
     double *out = nullptr;         // device results [2][4N + 1]
     double *host_out = nullptr;    // pinned copy
@@ -144,7 +145,9 @@ int env_int(const char *name, int dflt);
 
 // Batched read-and-clear finalize and member release (pcal_batch.hip), for the
 // served form.
-int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, hipStream_t s);
+// outs: per member, the device address its results go to (mapped pinned host
+// memory allowed), or null for h->out; outs itself may be null.
+int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, double *const *outs, hipStream_t s);
 int batch_release(pcal_batch_ctx *b, int id);
 
 }  // namespace host

@@ -79,7 +79,8 @@ struct FinArgs {
     int k_lo, k_hi;          // in-band tones [k_lo, k_hi): 0 < f_k < fs/2
     double f_comb;           // Hz
     double gain_re, gain_im; // C_k is multiplied by this (1 / (1 + gamma) in the mixed form, else 1)
-    double *out;             // [4N + 1]: amp, phase, re, im, delay
+    double *out;             // [4N + 1]: amp, phase, re, im, delay (device or mapped host memory)
+    double *phases;          // [N] device copy of the phases, read back by the last of several workgroups
     unsigned *counter;
     int clear;               // zero the accumulators afterwards (next integration)
     double2 *acc_clear;      // the accumulators to zero ([kAccSlots][N] each)

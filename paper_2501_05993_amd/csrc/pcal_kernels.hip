@@ -675,11 +675,15 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
         a.out[N + k] = phase;
         a.out[2 * N + k] = cr;
         a.out[3 * N + k] = ci;
-        if (nwg == 1) s_ph[k] = phase;
+        if (nwg == 1)
+            s_ph[k] = phase;
+        else
+            a.phases[k] = phase;
     }
 
     // One workgroup (N <= 64) has every phase in LDS; several meet at a counter
-    // and the last one reads the phases back from global memory.
+    // and the last one reads the phases back from device memory (out may be
+    // mapped host memory).
     if (nwg == 1)
         __syncthreads();
     else if (!last_workgroup_done(a.counter, static_cast<unsigned>(nwg)))
@@ -688,7 +692,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
     // Delay: unwrap phases over tones [k_lo, k_hi) and fit phase = a + 2 pi t_d f.
     const int n = a.k_hi - a.k_lo;
     double *sh = reinterpret_cast<double *>(lds);  // reuse: [256] segment sums, [256] products
-    const double *ph = (nwg == 1 ? s_ph : a.out + N) + a.k_lo;
+    const double *ph = (nwg == 1 ? s_ph : a.phases) + a.k_lo;
     const int seg = (n + 255) / 256;
     const int s0 = t * seg;
     const int s1 = (s0 + seg) < n ? (s0 + seg) : n;

@@ -36,6 +36,7 @@ struct SrvStream {
     int64_t device_bytes = 0;
     std::deque<Piece> queue;
     double *slots = nullptr;         // pinned [kResultDepth][4N + 1]
+    double *slots_dev = nullptr;     // the same memory's device address (the finalize writes it)
     int64_t slot_integ[kResultDepth];  // integration held by each slot (-1: none)
     bool slot_ready[kResultDepth];
 };
@@ -63,6 +64,7 @@ struct pcal_server_ctx {
     std::vector<hipEvent_t> spare_events;
     // scratch of one step
     std::vector<int> ids, done_bids;
+    std::vector<double *> done_outs;
     std::vector<const void *> ptrs;
     std::vector<int64_t> ns;
     std::vector<Done> done;
@@ -141,6 +143,14 @@ int pcal_server_open(pcal_server_t s, int64_t fs_hz, int64_t f_comb_hz, int64_t 
             st.slots = nullptr;
             return e == hipErrorOutOfMemory ? PCAL_ENOMEM : PCAL_EHIP;
         }
+        e = hipHostGetDevicePointer(reinterpret_cast<void **>(&st.slots_dev), st.slots, 0);
+        if (e != hipSuccess) {
+            set_error("hipHostGetDevicePointer", e);
+            (void)batch_release(s->batch, bid);
+            (void)hipHostFree(st.slots);
+            st.slots = nullptr;
+            return PCAL_EHIP;
+        }
     }
     st.open = true;
     st.bid = bid;
@@ -168,6 +178,7 @@ int pcal_server_close(pcal_server_t s, int sid) {
     const int rc = batch_release(s->batch, st.bid);
     if (st.slots) (void)hipHostFree(st.slots);
     st.slots = nullptr;
+    st.slots_dev = nullptr;
     st.open = false;
     st.queue.clear();
     s->used -= st.device_bytes;
@@ -197,6 +208,7 @@ int pcal_server_step(pcal_server_t s, pcal_stream_t stream, int64_t *samples_dis
     s->ns.clear();
     s->done.clear();
     s->done_bids.clear();
+    s->done_outs.clear();
     int64_t total = 0;
     const int M = s->max_streams;
     for (int j = 0; j < M; ++j) {
@@ -216,6 +228,7 @@ int pcal_server_step(pcal_server_t s, pcal_stream_t stream, int64_t *samples_dis
         if (st.in_integ == st.integ_samples) {
             s->done.push_back(Done{sid, st.integ});
             s->done_bids.push_back(st.bid);
+            s->done_outs.push_back(st.slots_dev + static_cast<size_t>(st.integ % kResultDepth) * (4 * st.N + 1));
         }
     }
     s->rr = M > 0 ? (s->rr + 1) % M : 0;
@@ -225,20 +238,19 @@ int pcal_server_step(pcal_server_t s, pcal_stream_t stream, int64_t *samples_dis
     if (rc) return rc;
     if (samples_dispatched) *samples_dispatched = total;
     if (s->done.empty()) return PCAL_OK;
-    if ((rc = batch_finalize_async(s->batch, static_cast<int>(s->done_bids.size()), s->done_bids.data(), hs)))
-        return rc;
+    // The finalize writes each finished integration's results straight into
+    // its stream's pinned result slot (no copies).
     for (const Done &d : s->done) {
         SrvStream &st = s->streams[d.sid];
-        pcal_t h = nullptr;
-        if ((rc = pcal_batch_handle(s->batch, st.bid, &h))) return rc;
         const int k = static_cast<int>(d.integ % kResultDepth);
         st.slot_integ[k] = d.integ;
         st.slot_ready[k] = false;
-        PCAL_HIP(hipMemcpyAsync(st.slots + static_cast<size_t>(k) * (4 * st.N + 1), h->out,
-                                sizeof(double) * (4 * st.N + 1), hipMemcpyDeviceToHost, hs));
         st.integ += 1;
         st.in_integ = 0;
     }
+    if ((rc = batch_finalize_async(s->batch, static_cast<int>(s->done_bids.size()), s->done_bids.data(),
+                                   s->done_outs.data(), hs)))
+        return rc;
     Inflight f;
     if ((rc = take_event(s, &f.ev))) return rc;
     PCAL_HIP(hipEventRecord(f.ev, hs));
