@@ -162,6 +162,7 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0):
                             if in_integ[s_] == sp.fs:
                                 k = integ_no[s_]
                                 h.results_async(slots[s_][k % 8], reset=True)
+                                h.flush()  # finalize now, not with this stream's next chunk
                                 ev = torch.cuda.Event()
                                 ev.record(st)
                                 pending.append((ev, s_, k))

@@ -139,6 +139,14 @@ int pcal_results_async(pcal_t h, double *host_out, int reset);
  * finished. */
 int pcal_sync(pcal_t h);
 
+/* Enqueue a finalize left pending by pcal_results_async(reset != 0) now, on
+ * the handle's last stream, instead of inside the next pcal_extract; returns
+ * at once (host_out is complete when that stream reaches this point).  For
+ * callers that want each integration's results without waiting for the next
+ * chunk.  No-op when nothing is pending.  Errors: PCAL_EINVAL (null handle),
+ * PCAL_EHIP. */
+int pcal_flush(pcal_t h);
+
 /* The raw C_k (k = 0..N-1) of the current integration, FP64 real and imaginary
  * parts (after the sideband convention).  Synchronises. */
 int pcal_spectrum(pcal_t h, double *re, double *im);

@@ -736,6 +736,15 @@ int pcal_results_async(pcal_t h, double *host_out, int reset) {
     return PCAL_OK;
 }
 
+int pcal_flush(pcal_t h) {
+    if (!h) return PCAL_EINVAL;
+    if (!h->fin_pending) return PCAL_OK;
+    DeviceGuard guard(h->device);
+    const int rc = flush_pending(h, h->last_stream);
+    // later calls on other streams order after the finalize (it clears a bank)
+    return rc ? rc : mark(h, h->last_stream);
+}
+
 int pcal_sync(pcal_t h) {
     if (!h) return PCAL_EINVAL;
     DeviceGuard guard(h->device);

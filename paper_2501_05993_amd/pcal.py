@@ -66,6 +66,7 @@ _SIGS = {
     "pcal_spectrum": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_results_async": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "pcal_sync": ([ctypes.c_void_p], ctypes.c_int),
+    "pcal_flush": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_bins": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_reset": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_destroy": ([ctypes.c_void_p], ctypes.c_int),
@@ -219,6 +220,10 @@ class PCal:
 
     def sync(self) -> None:
         _check(lib().pcal_sync(self._h), "pcal_sync")
+
+    def flush(self) -> None:
+        """Enqueue a pending finalize now (non-blocking); see pcal_flush."""
+        _check(lib().pcal_flush(self._h), "pcal_flush")
 
     def spectrum(self) -> np.ndarray:
         re = np.zeros(self.ntones)

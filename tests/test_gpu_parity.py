@@ -311,6 +311,38 @@ def test_results_async_pipelined(pc, case):
         assert abs(r[4 * N] - do) < tol[3]
 
 
+@pytest.mark.parametrize("tones", [64, 256])
+def test_flush_delivers_results_without_another_extract(pc, tones):
+    """pcal_flush enqueues the finalize that results_async(reset) deferred: once the
+    handle's stream has reached it, host_out holds the integration's results, with
+    no further extract on the handle; the next integration starts from zero."""
+    spec = synth.CombSpec(tones * 1_000_000, 1_000_000, 10_000, 2, amp=0.05, t_d=4e-9, seed=(43, tones))
+    L = 1 << 21
+    packed = synth.make_stream(spec, 3 * L)
+    dev = _dev(packed)
+    N = spec.ntones
+    st = torch.cuda.Stream()
+    ring = torch.zeros((2, 4 * N + 1), dtype=torch.float64, pin_memory=True)
+    say("flush: N = %d" % N)
+    with pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2) as h:
+        for i in range(2):
+            h.extract(dev[i * L // 4:], L, stream=st)
+            h.results_async(ring[i], reset=True)
+            h.flush()
+            h.flush()  # nothing pending: no-op
+            st.synchronize()
+            r = ring[i].numpy()
+            C = r[2 * N:3 * N] + 1j * r[3 * N:4 * N]
+            Co = oracle.correlate(packed[i * L // 4:(i + 1) * L // 4], 2, L, spec.fs, spec.f_comb, spec.f_offset,
+                                  n0=i * L)
+            assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="flushed %d" % i)
+        # a later extract on another stream is ordered after the flushed finalize (it cleared a bank)
+        h.extract(dev[2 * L // 4:], L)
+        Cn = h.spectrum()
+    Co = oracle.correlate(packed[2 * L // 4:3 * L // 4], 2, L, spec.fs, spec.f_comb, spec.f_offset, n0=2 * L)
+    assert_spectra(Cn, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="after flushes")
+
+
 @pytest.mark.gpu
 def test_extract_timed_matches_extract():
     """pcal_extract_timed: the same bins as pcal_extract, and events that bracket the kernel."""
