@@ -134,25 +134,36 @@ int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, double *c
     if (rc || count == 0) return rc;
     DeviceGuard guard(b->members[ids[0]]->device);
     if ((rc = order_members(b, count, ids, s))) return rc;
+    // a short list travels in the kernel arguments; a longer one is staged
+    FinListInline il;
     Stage *st = nullptr;
-    if ((rc = take_stage(b, &st))) return rc;
+    const bool inl = count <= kInlineFinItems;
+    if (!inl && (rc = take_stage(b, &st))) return rc;
+    FinArgs *items = inl ? il.items : st->h_fin;
+    int *first = inl ? il.first : st->h_first;
     int grid = 0;
     size_t lds = 0;
     for (int i = 0; i < count; ++i) {
         pcal_ctx *h = b->members[ids[i]];
-        st->h_fin[i] = fin_args(h, outs && outs[i] ? outs[i] : h->out);
-        st->h_fin[i].clear = 1;
-        st->h_first[i] = grid;
+        items[i] = fin_args(h, outs && outs[i] ? outs[i] : h->out);
+        items[i].clear = 1;
+        first[i] = grid;
         grid += static_cast<int>((h->plan.N + 63) / 64);
         lds = std::max(lds, finalize_lds_bytes(static_cast<int>(h->plan.N)));
         h->n_integ = 0;
     }
-    st->h_first[count] = grid;
-    PCAL_HIP(st->upload(count + 1, sizeof(FinArgs) * count, s));
-    launch_finalize_batch(st->d_items<FinArgs>(), st->d_first(), count, grid, lds, s);
-    PCAL_HIP(hipGetLastError());
-    PCAL_HIP(hipEventRecord(st->done, s));
-    st->pending = true;
+    first[count] = grid;
+    if (inl) {
+        il.n = count;
+        launch_finalize_batch(il, grid, lds, s);
+        PCAL_HIP(hipGetLastError());
+    } else {
+        PCAL_HIP(st->upload(count + 1, sizeof(FinArgs) * count, s));
+        launch_finalize_batch(DeviceList<FinArgs>{st->d_items<FinArgs>(), st->d_first(), count}, grid, lds, s);
+        PCAL_HIP(hipGetLastError());
+        PCAL_HIP(hipEventRecord(st->done, s));
+        st->pending = true;
+    }
     return mark_members(b, count, ids, s);
 }
 
@@ -248,13 +259,21 @@ int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *co
     DeviceGuard guard(b->members[ids[0]]->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((rc = order_members(b, count, ids, s))) return rc;
-    Stage *st = nullptr;
-    if ((rc = take_stage(b, &st))) return rc;
     // The work-list holds the 2-bit items first, then the 8-bit ones (one fold
-    // launch per sample width).
-    int n = 0, grid = 0, grid2 = 0, threads = 64;
+    // launch per sample width).  A short list travels in the kernel
+    // arguments; a longer one is staged and copied.
+    int n = 0, grid = 0, grid2 = 0, threads = 64, used = 0;
     for (int i = 0; i < count; ++i)
-        if (nsamples[i] > 0) threads = std::max(threads, b->members[ids[i]]->plan.geom.threads);
+        if (nsamples[i] > 0) {
+            threads = std::max(threads, b->members[ids[i]]->plan.geom.threads);
+            ++used;
+        }
+    FoldListInline il;
+    Stage *st = nullptr;
+    const bool inl = used <= kInlineFoldItems;
+    if (!inl && (rc = take_stage(b, &st))) return rc;
+    FoldArgs *items = inl ? il.items : st->h_items;
+    int *first = inl ? il.first : st->h_first;
     size_t lds[2] = {0, 0};
     for (int pass = 0; pass < 2; ++pass) {
         const int width = pass == 0 ? 2 : 8;
@@ -267,22 +286,28 @@ int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *co
                 p.geom.col_tiles, (b->target_blocks * bytes + total_bytes - 1) / total_bytes));
             const pcal_launch_t L =
                 plan_launch(p, reinterpret_cast<uintptr_t>(dev_ptrs[i]), h->n_total, nsamples[i], target);
-            st->h_items[n] = fold_args(h, L, dev_ptrs[i]);
-            st->h_first[n] = grid;
+            items[n] = fold_args(h, L, dev_ptrs[i]);
+            first[n] = grid;
             grid += static_cast<int>(L.grid);
-            const FoldArgs &a = st->h_items[n];
+            const FoldArgs &a = items[n];
             lds[pass] = std::max(lds[pass], fold_lds_bytes(a.npos, p.geom.spv, threads, a.M));
             ++n;
         }
         if (pass == 0) grid2 = grid;
     }
-    st->h_first[n] = grid;
-    PCAL_HIP(st->upload(n + 1, sizeof(FoldArgs) * n, s));
-    launch_fold_batch(st->d_items<FoldArgs>(), st->d_first(), n, b->prec, grid2, grid - grid2, threads, lds[0],
-                      lds[1], s);
-    PCAL_HIP(hipGetLastError());
-    PCAL_HIP(hipEventRecord(st->done, s));
-    st->pending = true;
+    first[n] = grid;
+    if (inl) {
+        il.n = n;
+        launch_fold_batch(il, b->prec, grid2, grid - grid2, threads, lds[0], lds[1], s);
+        PCAL_HIP(hipGetLastError());
+    } else {
+        PCAL_HIP(st->upload(n + 1, sizeof(FoldArgs) * n, s));
+        launch_fold_batch(DeviceList<FoldArgs>{st->d_items<FoldArgs>(), st->d_first(), n}, b->prec, grid2,
+                          grid - grid2, threads, lds[0], lds[1], s);
+        PCAL_HIP(hipGetLastError());
+        PCAL_HIP(hipEventRecord(st->done, s));
+        st->pending = true;
+    }
     for (int i = 0; i < count; ++i) {
         b->members[ids[i]]->n_total += nsamples[i];
         b->members[ids[i]]->n_integ += nsamples[i];
@@ -324,7 +349,7 @@ int pcal_batch_results(pcal_batch_t b, int count, const int *ids, double *amp, d
     }
     st->h_first[count] = grid;
     PCAL_HIP(st->upload(count + 1, sizeof(FinArgs) * count, s));
-    launch_finalize_batch(st->d_items<FinArgs>(), st->d_first(), count, grid, lds, s);
+    launch_finalize_batch(DeviceList<FinArgs>{st->d_items<FinArgs>(), st->d_first(), count}, grid, lds, s);
     PCAL_HIP(hipGetLastError());
     PCAL_HIP(hipEventRecord(st->done, s));
     st->pending = true;

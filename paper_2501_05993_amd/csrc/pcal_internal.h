@@ -162,15 +162,39 @@ void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds
                  hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // Fold workgroups of the given shape resident at once on one compute unit (0 on error).
 int fold_blocks_per_cu(int nbits, int prec, int threads, size_t lds);
+// Work-lists of the batched kernels: item i owns workgroups [first[i],
+// first[i + 1]).  A list in device memory (copied there before the launch),
+// or a short one carried in the kernel arguments (no copy).
+template <class T>
+struct DeviceList {
+    const T *items;
+    const int *first;
+    int n;
+};
+template <class T, int CAP>
+struct InlineList {
+    static constexpr int kCap = CAP;
+    int n;
+    int first[CAP + 1];
+    T items[CAP];
+};
+constexpr int kInlineFoldItems = 8;   // 8 x 376 B of FoldArgs: within 4 KiB of kernel arguments
+constexpr int kInlineFinItems = 16;
+using FoldListInline = InlineList<FoldArgs, kInlineFoldItems>;
+using FinListInline = InlineList<FinArgs, kInlineFinItems>;
+
 // Work-list items [0, n2) are 2-bit and own workgroups [0, grid2); the rest
 // are 8-bit and own the next grid8 workgroups.  One launch per width.
-void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int prec, int grid2, int grid8,
-                       int threads, size_t lds2, size_t lds8, hipStream_t s);
+void launch_fold_batch(const DeviceList<FoldArgs> &list, int prec, int grid2, int grid8, int threads, size_t lds2,
+                       size_t lds8, hipStream_t s);
+void launch_fold_batch(const FoldListInline &list, int prec, int grid2, int grid8, int threads, size_t lds2,
+                       size_t lds8, hipStream_t s);
 void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStream_t s,
                    hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_finalize(const FinArgs &a, hipStream_t s);
 size_t finalize_lds_bytes(int N);
-void launch_finalize_batch(const FinArgs *items, const int *first, int nitems, int grid, size_t lds, hipStream_t s);
+void launch_finalize_batch(const DeviceList<FinArgs> &list, int grid, size_t lds, hipStream_t s);
+void launch_finalize_batch(const FinListInline &list, int grid, size_t lds, hipStream_t s);
 struct ZeroItem {
     void *ptr;
     size_t bytes;  // multiple of 4

@@ -563,20 +563,39 @@ __device__ __forceinline__ int owner_of(const int *first, int nitems, int wg) {
     return count - 1;
 }
 
+// Item i of a work-list and its first workgroup, for both list forms.
+template <class T>
+__device__ __forceinline__ int list_owner(const DeviceList<T> &l, int wg) {
+    return __builtin_amdgcn_readfirstlane(owner_of(l.first, l.n, wg));
+}
+template <class T, int CAP>
+__device__ __forceinline__ int list_owner(const InlineList<T, CAP> &l, int wg) {
+    int i = 0;  // a short list in the kernel arguments: a scalar scan
+    while (i + 1 < l.n && l.first[i + 1] <= wg) ++i;
+    return i;
+}
+template <class T>
+__device__ __forceinline__ int list_first(const DeviceList<T> &l, int i) { return load_global(l.first + i); }
+template <class T, int CAP>
+__device__ __forceinline__ int list_first(const InlineList<T, CAP> &l, int i) { return l.first[i]; }
+template <class T>
+__device__ __forceinline__ T list_item(const DeviceList<T> &l, int i) { return l.items[i]; }
+template <class T, int CAP>
+__device__ __forceinline__ T list_item(const InlineList<T, CAP> &l, int i) { return l.items[i]; }
+
 // One launch over the work items of many streams of one sample width (each
-// item: one stream's launch geometry, tables and accumulators; first[i] = its
-// first workgroup).  Workgroup blockIdx.x is workgroup wg0 + blockIdx.x of the
-// work-list, so that the 2-bit and 8-bit items of one work-list (2-bit first)
-// go to two launches: with both bodies in one kernel, the compiler's wait
-// accounting carries the pending operations of one body into the other.
-template <int NBITS, int PREC>
-__global__ void __launch_bounds__(kMaxFoldThreads) fold_batch_kernel(const FoldArgs *items, const int *first,
-                                                                      int nitems, int wg0) {
+// item: one stream's launch geometry, tables and accumulators).  Workgroup
+// blockIdx.x is workgroup wg0 + blockIdx.x of the work-list, so that the
+// 2-bit and 8-bit items of one work-list (2-bit first) go to two launches:
+// with both bodies in one kernel, the compiler's wait accounting carries the
+// pending operations of one body into the other.
+template <int NBITS, int PREC, class List>
+__global__ void __launch_bounds__(kMaxFoldThreads) fold_batch_kernel(const List list, int wg0) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int wg = wg0 + static_cast<int>(blockIdx.x);
-    const int i = __builtin_amdgcn_readfirstlane(owner_of(first, nitems, wg));
-    const FoldArgs a = items[i];
-    fold_body<NBITS, PREC>(a, wg - first[i], lds);
+    const int i = list_owner(list, wg);
+    const FoldArgs a = list_item(list, i);
+    fold_body<NBITS, PREC>(a, wg - list_first(list, i), lds);
 }
 
 // ---------------------------------------------------------------- finalize
@@ -770,12 +789,13 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs a) {
 
 // Finalize of many streams in one launch: item i owns workgroups
 // [first[i], first[i + 1]), ceil(N_i / 64) of them.
-__global__ void __launch_bounds__(256) finalize_batch_kernel(const FinArgs *items, const int *first, int nitems) {
+template <class List>
+__global__ void __launch_bounds__(256) finalize_batch_kernel(const List list) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int wg = static_cast<int>(blockIdx.x);
-    const int i = __builtin_amdgcn_readfirstlane(owner_of(first, nitems, wg));
-    const FinArgs a = items[i];
-    finalize_body(a, wg - first[i], (a.N + 63) / 64, lds);
+    const int i = list_owner(list, wg);
+    const FinArgs a = list_item(list, i);
+    finalize_body(a, wg - list_first(list, i), (a.N + 63) / 64, lds);
 }
 
 // Zero a list of buffers (one workgroup per buffer, grid-stride inside).
@@ -833,11 +853,12 @@ int fold_blocks_per_cu(int nbits, int prec, int threads, size_t lds) {
     return n;
 }
 
-void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int prec, int grid2, int grid8,
-                       int threads, size_t lds2, size_t lds8, hipStream_t s) {
+template <class List>
+void launch_fold_batch_list(const List &list, int prec, int grid2, int grid8, int threads, size_t lds2, size_t lds8,
+                            hipStream_t s) {
     const dim3 bd(threads);
 #define PCAL_BATCH_LAUNCH(NB, PR, G, L, W0) \
-    hipLaunchKernelGGL((fold_batch_kernel<NB, PR>), dim3(G), bd, L, s, items, first, nitems, W0)
+    hipLaunchKernelGGL((fold_batch_kernel<NB, PR, List>), dim3(G), bd, L, s, list, W0)
     if (grid2 > 0) {
         if (prec == 0)
             PCAL_BATCH_LAUNCH(2, 0, grid2, lds2, 0);
@@ -857,6 +878,16 @@ void launch_fold_batch(const FoldArgs *items, const int *first, int nitems, int 
 #undef PCAL_BATCH_LAUNCH
 }
 
+void launch_fold_batch(const DeviceList<FoldArgs> &list, int prec, int grid2, int grid8, int threads, size_t lds2,
+                       size_t lds8, hipStream_t s) {
+    launch_fold_batch_list(list, prec, grid2, grid8, threads, lds2, lds8, s);
+}
+
+void launch_fold_batch(const FoldListInline &list, int prec, int grid2, int grid8, int threads, size_t lds2,
+                       size_t lds8, hipStream_t s) {
+    launch_fold_batch_list(list, prec, grid2, grid8, threads, lds2, lds8, s);
+}
+
 void launch_finalize(const FinArgs &a, hipStream_t s) {
     const int grid = (a.N + 63) / 64;
     const size_t lds = finalize_lds_bytes(a.N);
@@ -865,8 +896,12 @@ void launch_finalize(const FinArgs &a, hipStream_t s) {
 
 size_t finalize_lds_bytes(int N) { return sizeof(double2) * ((N <= kTwLdsMaxTones ? 2 * N : N) + 256); }
 
-void launch_finalize_batch(const FinArgs *items, const int *first, int nitems, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(finalize_batch_kernel, dim3(grid), dim3(256), lds, s, items, first, nitems);
+void launch_finalize_batch(const DeviceList<FinArgs> &list, int grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((finalize_batch_kernel<DeviceList<FinArgs>>), dim3(grid), dim3(256), lds, s, list);
+}
+
+void launch_finalize_batch(const FinListInline &list, int grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((finalize_batch_kernel<FinListInline>), dim3(grid), dim3(256), lds, s, list);
 }
 
 void launch_zero_list(const ZeroItem *items, int n, hipStream_t s) {

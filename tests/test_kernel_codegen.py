@@ -63,7 +63,7 @@ def _walk_loop(lines):
 
 def _fold_kernels(funcs):
     names = [n for n in funcs if "fold_kernel" in n or "fold_batch_kernel" in n]
-    assert len(names) == 12, names  # {2,8}-bit x 3 precisions, plain and batched
+    assert len(names) == 18, names  # {2,8}-bit x 3 precisions: plain, batched (device or inline work-list)
     return names
 
 
