@@ -360,9 +360,23 @@ int build(pcal_ctx *h) {
                 for (int64_t n = 0; n < R; ++n) tr[n] = from_half2(th[n]);
                 table_gain(t, tr, &h->gain_re, &h->gain_im);
             }
+            // de-interleaved by D (the largest power of two <= 16 dividing R):
+            // entry n at (n mod D) * (R / D) + n / D, so that the lookups of
+            // lanes 16 entries apart fall on neighbouring addresses
+            int shift = 0;
+            while (shift < 4 && R % (int64_t(2) << shift) == 0) ++shift;
+            h->lut_shift = shift;
+            h->lut_rows = R >> shift;
+            std::vector<float2> tfd(R);
+            std::vector<__half2> thd(R);
+            for (int64_t n = 0; n < R; ++n) {
+                const int64_t k = (n & ((int64_t(1) << shift) - 1)) * h->lut_rows + (n >> shift);
+                tfd[k] = tf[n];
+                thd[k] = th[n];
+            }
             if ((rc = dalloc(h, &h->rot32, R)) || (rc = dalloc(h, &h->rot16, R))) return rc;
-            PCAL_HIP(hipMemcpy(h->rot32, tf.data(), sizeof(float2) * R, hipMemcpyHostToDevice));
-            PCAL_HIP(hipMemcpy(h->rot16, th.data(), sizeof(__half2) * R, hipMemcpyHostToDevice));
+            PCAL_HIP(hipMemcpy(h->rot32, tfd.data(), sizeof(float2) * R, hipMemcpyHostToDevice));
+            PCAL_HIP(hipMemcpy(h->rot16, thd.data(), sizeof(__half2) * R, hipMemcpyHostToDevice));
         }
     }
     if ((rc = dalloc(h, &h->u64, M)) || (rc = dalloc(h, &h->u32, M)) || (rc = dalloc(h, &h->u16, 2 * M)) ||
@@ -672,6 +686,8 @@ int pcal_extract_timed(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_str
         a.R = p.R;
         a.rot32 = h->rot32;
         a.rot16 = h->rot16;
+        a.lut_shift = h->lut_shift;
+        a.lut_rows = h->lut_rows;
         a.w = h->w;
         a.back = h->back;
         a.c2 = h->c2;

@@ -89,6 +89,8 @@ struct pcal_ctx {
         double *dev;  // null: not device-accessible
     } map_cache[8] = {};
     int map_next = 0;
+    int lut_shift = 0;            // rotator table layout (RotArgs::lut_shift)
+    int64_t lut_rows = 0;
     double *phases = nullptr;      // [N] phases the last finalize workgroup reads back
     unsigned *counters = nullptr;  // [0] finalize of bank 0's pending form / plain, [1] bank 1
     double *out = nullptr;         // device results [2][4N + 1]

@@ -141,8 +141,13 @@ struct RotArgs {
     int N, nbits, prec, method;
     int64_t g0;              // global index of the first full-vector sample
     int64_t fs, fo, R;       // Hz, Hz, rotator period (Eq. 4)
-    const float2 *rot32;     // rotator table [R] in FP32 (table method)
+    const float2 *rot32;     // rotator table [R] in FP32 (table method), de-interleaved (below)
     const __half2 *rot16;    // the same in FP16 (mixed form)
+    // Entry n of the table is stored at (n mod D) * (R / D) + n / D, D = 2^lut_shift
+    // the largest power of two <= 16 dividing R: the lanes of a wave look up
+    // entries 16 apart, which this places next to each other.
+    int lut_shift;
+    int64_t lut_rows;        // R / D
     const double2 *w;        // [16] lane factors exp(-j w_o i)
     double2 back;            // exp(+j w_o * samples per row): one row back, FP64
     float c2;                // 2 cos(w_o * samples per row), recurrence coefficient

@@ -131,7 +131,8 @@ struct RowRot {
     float zr = 0.f, zi = 0.f, pr = 0.f, pi = 0.f, c2 = 0.f;
     int64_t n = 0, dn = 0;  // global index of the row's first lane sample, row stride in samples
 
-    __device__ __forceinline__ float2 table(const RotArgs &a, int64_t k) const {
+    __device__ __forceinline__ float2 table(const RotArgs &a, int64_t n) const {
+        const int64_t k = (n & ((int64_t(1) << a.lut_shift) - 1)) * a.lut_rows + (n >> a.lut_shift);
         if constexpr (PREC == 1)
             return __half22float2(a.rot16[k]);
         else
