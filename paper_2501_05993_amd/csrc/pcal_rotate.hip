@@ -20,7 +20,7 @@ namespace {
 
 constexpr int kLanes = 16;   // samples per thread and row
 constexpr int kRun = 64;     // rows per run: run sums in FP32, then folded into totals
-constexpr int kUnroll = 4;   // rows loaded ahead
+constexpr int kUnroll = 8;   // rows loaded ahead
 
 __device__ __forceinline__ int edge_level(const uint8_t *p, int nbits, int i) {
     if (nbits == 2) return 2 * ((p[i >> 2] >> (2 * (i & 3))) & 3) - 3;
