@@ -243,3 +243,38 @@ def test_per_sample_walk(method, fs, fc, fo, nbits, ns, addr, before):
 def test_auto_prefers_recurrence_for_long_periods():
     assert pcal.plan(64_000_000, 1_000_000, 10_000, 2)["method"] == pcal.METHOD_PERIOD_FOLD
     assert pcal.plan(64_000_000, 2_000_000, 10_007, 8)["method"] == pcal.METHOD_OSC
+
+
+# fs, f_offset, nbits across the paper's and the serving mix's configurations
+_PLAN_CASES = [(fs * 1_000_000, fo, nb) for fs in (16, 32, 64, 128, 256, 512, 1024)
+               for fo in (0, 10_000, 250_000, 500_000, 510_000) for nb in (2, 8)]
+
+
+@pytest.mark.parametrize("fs,fo,nbits", _PLAN_CASES)
+def test_fold_plan_rules(fs, fo, nbits):
+    """The planner's fold geometry: the fold period is a multiple of the joint
+    period and of one vector, at least 64 vectors long (a wave's lanes own
+    distinct positions) and the first such multiple; split tiles are whole
+    128-byte lines wide and hold at most 12800 positions; workgroups are at
+    least 448 threads, waste the fewest lanes, and among equal sizes take the
+    one nearest 640."""
+    info = pcal.plan(fs, 1_000_000, fo, nbits, method=pcal.METHOD_PERIOD_FOLD)
+    spv = 64 if nbits == 2 else 16
+    S, Sp = info["joint_period"], info["fold_period"]
+    base = int(np.lcm(S, spv))
+    assert Sp % base == 0 and Sp % spv == 0
+    W = Sp // spv
+    assert W >= 64 and (Sp == base or (Sp - base) // spv < 64)
+    assert info["period_vectors"] == W
+    tile, tiles, thr = info["tile_vectors"], info["col_tiles"], info["block_threads"]
+    assert tile * tiles >= W and tile * (tiles - 1) < W
+    assert info["lds_positions"] == tile * spv <= 12800
+    if tiles > 1:
+        assert tile % 8 == 0
+    assert 448 <= thr <= 768 and thr % 64 == 0 and thr >= tile
+    eff = lambda t: (t // tile) * tile / t
+    best = max(eff(t) for t in range(448, 769, 64) if t >= tile)
+    assert abs(eff(thr) - best) < 1e-9
+    ties = [t for t in range(448, 769, 64) if t >= tile and abs(eff(t) - best) < 1e-9]
+    assert abs(thr - 640) == min(abs(t - 640) for t in ties)
+    assert info["row_vectors"] == (thr // tile) * W if tiles == 1 else info["row_vectors"] % W == 0
