@@ -55,8 +55,8 @@ enum pcal_status {
  *  PERIOD_FOLD: fold integer samples over the joint period S = lcm(N, R)
  *      (R from Eq. 4) and rotate each of the S positions once; by
  *      distributivity this is the precomputed-rotator method with the rotation
- *      moved after the accumulation (Section 4.1, the N_rotator-sample
- *      accumulator folded outside the sample loop).
+ *      moved after the accumulation (Section 4.1 proposes accumulating over a
+ *      rotator period and folding into the bins after the sample loop).
  *  LUT: multiply every sample by a precomputed rotator table value (Eq. 4
  *      table, Section 4.1), accumulate in FP32.
  *  OSC: multiply every sample by a recurrence sinewave generator (Eq. 6-7

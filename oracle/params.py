@@ -5,7 +5,7 @@ from math import gcd, pi
 
 
 def ntones(fs: int, f_comb: int) -> int:
-    """Number of comb tones (= fold bins) in the band and its mirror image: N = fs / f_comb (Section 2)."""
+    """Number of comb tones (= fold bins) over the band and its mirrored half: N = fs / f_comb (Section 2)."""
     if fs % f_comb:
         raise ValueError("fs must be a multiple of f_comb")
     return fs // f_comb

@@ -8,8 +8,9 @@
 // in one 16-byte load).  The sum over the stream of x[n] * rot[n] into bin
 // n mod N therefore equals, by distributivity, first summing the integer
 // samples that share a period position q = n mod S' and then rotating each of
-// the S' position sums once -- the "N_rotator-sample accumulator folded
-// outside the sample loop" of Section 4.1, carried to its end.  The rotator
+// the S' position sums once.  Section 4.1 suggests accumulating over one
+// rotator period and folding into the bins after the sample loop; here the
+// samples are summed before any rotation, which carries that idea to its end.  The rotator
 // is factorised as rot[q] = u[q / N] * v[q mod N] with u[m] = exp(-j w_o N m)
 // and v[b] = exp(-j w_o b); a workgroup applies u to its position sums and
 // folds them to N bins, and v is applied once per bin in the final reduction.
