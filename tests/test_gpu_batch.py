@@ -83,3 +83,25 @@ def test_batch_integer_bins_and_reset(pc, mix):
             n0 = L if j < 3 else 0
             want = oracle.fold_int(packed[i], 2, L, specs[i].ntones, n0=n0)
             np.testing.assert_array_equal(ib, want)
+
+
+@pytest.mark.parametrize("count", [8, 9])
+def test_batch_mixed_widths_inline_and_staged(pc, count):
+    """2-bit and 8-bit streams in one batched call: one launch per sample width
+    (the 8-bit launch starts at the 2-bit launch's last workgroup), the work-list
+    in the kernel arguments (8 items) or copied to the device (9 items).  Each
+    member equals the oracle; the order of the ids does not matter."""
+    specs = synth.batch_specs(count, seed=11, nbits=None)
+    assert {s.nbits for s in specs} == {2, 8}
+    L = 1 << 18
+    packed = [synth.make_stream(s, L) for s in specs]
+    devs = [torch.from_numpy(p).cuda() for p in packed]
+    say("batch of %d mixed-width streams" % count)
+    with pc.PCalBatch(count) as b:
+        ids = [b.add(s.fs, s.f_comb, s.f_offset, s.nbits) for s in specs]
+        order = list(range(count))[::-1]  # 8-bit and 2-bit ids interleaved, reversed
+        b.extract([ids[i] for i in order], [devs[i] for i in order], [L] * count)
+        C = b.spectra(ids)
+    for i, s in enumerate(specs):
+        Co = oracle.correlate(packed[i], s.nbits, L, s.fs, s.f_comb, s.f_offset)
+        assert_spectra(C[i], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6, what="mixed %d" % i)
