@@ -368,3 +368,35 @@ def test_extract_timed_matches_extract():
     assert 0.0 < ms < 50.0
     a.close()
     b.close()
+
+
+def test_repeatability(pc):
+    """The FP64 bins are summed with hardware atomics (16 slots, added in slot
+    order by the finalize), so the order of the additions within a slot varies
+    from run to run: repeated extractions agree to FP64 rounding (far below
+    the 1e-10 parity bar), and the exact integer bins (f_offset = 0) agree bit
+    for bit."""
+    spec = synth.WORKLOADS["fold2_64M_10k"]["spec"]
+    L = 1 << 26
+    packed = synth.make_stream(spec, L)
+    dev = _dev(packed)
+    runs = []
+    for _ in range(3):
+        with pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2) as h:
+            h.extract(dev, L)
+            runs.append(h.spectrum())
+    scale = np.abs(runs[0]).max()
+    for C in runs[1:]:
+        d = np.abs(C - runs[0]).max() / scale
+        say("repeatability: max |dC| / max |C| = %.3e" % d)
+        assert d < 1e-13
+    s0 = synth.WORKLOADS["small_2bit_fo0"]["spec"]
+    p0 = synth.make_stream(s0, 1 << 22)
+    d0 = _dev(p0)
+    bins = []
+    for _ in range(3):
+        with pc.PCal(s0.fs, s0.f_comb, 0, 2) as h:
+            h.extract(d0, 1 << 22)
+            bins.append(h.bins(integer=True)[1])
+    for b in bins[1:]:
+        np.testing.assert_array_equal(b, bins[0])
