@@ -563,14 +563,17 @@ int create(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int meth
         return PCAL_EHIP;
     }
     if (p.method == PCAL_METHOD_PERIOD_FOLD && !p.target_from_env) {
-        // persistent grid: as many fold workgroups as the device holds at once, so
-        // that the rows claimed at run time go to whichever finishes first
+        // persistent grid: every workgroup resident at once, and as few per
+        // compute unit as keep kMinResidentWaves waves there (each workgroup
+        // adds an epilogue and N atomics of its own)
         int cus = 0;
         const int per_cu = fold_blocks_per_cu(p.nbits, p.prec, p.geom.threads,
                                               fold_lds_bytes(p.geom.npos, p.geom.spv, p.geom.threads, p.M));
+        const int waves = (p.geom.threads + 63) / 64;
+        const int use = std::min(per_cu, std::max(1, (kMinResidentWaves + waves - 1) / waves));
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
             per_cu > 0 && cus > 0) {
-            h->plan.target_blocks = std::max(per_cu * cus, h->plan.geom.col_tiles);
+            h->plan.target_blocks = std::max(use * cus, h->plan.geom.col_tiles);
             h->plan.max_blocks = std::max(h->plan.geom.col_tiles, h->plan.target_blocks) + h->plan.geom.col_tiles;
         }
     }

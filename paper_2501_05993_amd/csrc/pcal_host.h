@@ -45,6 +45,11 @@ constexpr int64_t kMaxFoldPeriod = int64_t(1) << 26;  // S' samples
 // at 54 % of the HBM peak, 576-640 at 73 %).
 constexpr int kMinFoldThreads = 448;
 constexpr int kAimFoldThreads = 640;
+// Waves per compute unit the persistent fold grid aims for with the fewest
+// workgroups (2^28-sample 8-bit launches, N = 1024: one 768-thread workgroup
+// per compute unit ran at 73.5 % of the HBM peak, two at 70 %; the 8-bit
+// 6400-sample period: two 448-thread workgroups 76.8 %, three 75.4 %).
+constexpr int kMinResidentWaves = 10;
 constexpr int64_t kMaxTableRows = int64_t(1) << 20;   // u table entries
 constexpr int64_t kMaxLutPeriod = int64_t(1) << 24;   // rotator table entries (table method)
 constexpr int kRotLanes = 16;                          // samples per thread-row, per-sample forms
