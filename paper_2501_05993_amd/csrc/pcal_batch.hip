@@ -58,6 +58,8 @@ struct pcal_batch_ctx {
     size_t out_cap = 0;        // doubles
     hipStream_t last_stream = nullptr;
     hipEvent_t ev = nullptr;   // recorded after each batched call
+    std::vector<unsigned> seen;  // per member id: the call stamp that last listed it
+    unsigned stamp = 0;
 };
 
 namespace {
@@ -248,11 +250,17 @@ int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *co
     if (rc) return rc;
     if (count > 0 && (!dev_ptrs || !nsamples)) return PCAL_EINVAL;
     int64_t total_bytes = 0;
+    // one chunk per stream and call: each id at most once (stamped, linear time)
+    if (b->seen.size() < b->members.size()) b->seen.resize(b->members.size(), 0u);
+    if (++b->stamp == 0) {
+        std::fill(b->seen.begin(), b->seen.end(), 0u);
+        b->stamp = 1;
+    }
     for (int i = 0; i < count; ++i) {
         const Plan &p = b->members[ids[i]]->plan;
         if (nsamples[i] < 0 || nsamples[i] % (8 / p.nbits) || (nsamples[i] > 0 && !dev_ptrs[i])) return PCAL_EINVAL;
-        for (int j = 0; j < i; ++j)
-            if (ids[j] == ids[i]) return PCAL_EINVAL;  // one chunk per stream and launch
+        if (b->seen[ids[i]] == b->stamp) return PCAL_EINVAL;
+        b->seen[ids[i]] = b->stamp;
         total_bytes += nsamples[i] * p.nbits / 8;
     }
     if (total_bytes == 0) return PCAL_OK;

@@ -105,3 +105,22 @@ def test_batch_mixed_widths_inline_and_staged(pc, count):
     for i, s in enumerate(specs):
         Co = oracle.correlate(packed[i], s.nbits, L, s.fs, s.f_comb, s.f_offset)
         assert_spectra(C[i], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6, what="mixed %d" % i)
+
+
+def test_batch_rejects_a_stream_listed_twice(pc):
+    """One chunk per stream and call: an id listed twice is PCAL_EINVAL (nothing
+    is launched), and the next valid call on the same ids works."""
+    specs = synth.batch_specs(3, seed=13)
+    L = 1 << 16
+    packed = [synth.make_stream(s, L) for s in specs]
+    devs = [torch.from_numpy(p).cuda() for p in packed]
+    with pc.PCalBatch(3) as b:
+        ids = [b.add(s.fs, s.f_comb, s.f_offset, 2) for s in specs]
+        with pytest.raises(pc.PcalError) as e:
+            b.extract([ids[0], ids[1], ids[0]], [devs[0], devs[1], devs[0]], [L] * 3)
+        assert e.value.code == pc.EINVAL
+        b.extract(ids, devs, [L] * 3)
+        C = b.spectra(ids)
+    for i, s in enumerate(specs):
+        Co = oracle.correlate(packed[i], 2, L, s.fs, s.f_comb, s.f_offset)
+        assert_spectra(C[i], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6, what="after rejected %d" % i)
