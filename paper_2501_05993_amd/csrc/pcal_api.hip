@@ -277,18 +277,17 @@ int flush_pending(pcal_ctx *h, hipStream_t s) {
 }
 
 // Device address of a host result buffer the finalize may write directly
-// (pinned, mapped host memory of 4N + 1 doubles), or null.  Cached per handle.
+// (pinned, mapped host memory of 4N + 1 doubles), or null.  Queried on every
+// call (once per integration): a cached answer could outlive the buffer, and a
+// pageable buffer later at the same address must not be written by the GPU.
 double *mapped_results(pcal_ctx *h, double *host) {
-    for (const auto &e : h->map_cache)
-        if (e.host == host) return e.dev;
+    (void)h;
     void *dev = nullptr;
     hipPointerAttribute_t at{};
     if (hipPointerGetAttributes(&at, host) != hipSuccess || at.type != hipMemoryTypeHost ||
         hipHostGetDevicePointer(&dev, host, 0) != hipSuccess)
         dev = nullptr;
     (void)hipGetLastError();  // a refused query leaves no error behind
-    h->map_cache[h->map_next] = {host, static_cast<double *>(dev)};
-    h->map_next = (h->map_next + 1) % 8;
     return static_cast<double *>(dev);
 }
 

@@ -88,12 +88,6 @@ struct pcal_ctx {
     pcal::FinArgs fin;              // the pending finalize (clearing the other bank)
     double *fin_host = nullptr;     // where its results go
     const double *fin_dev = nullptr;  // device results to copy to fin_host (null: written there directly)
-    // host result buffers the finalize may write directly (mapped pinned memory)
-    struct MapEntry {
-        const double *host;
-        double *dev;  // null: not device-accessible
-    } map_cache[8] = {};
-    int map_next = 0;
     int lut_shift = 0;            // rotator table layout (RotArgs::lut_shift)
     int64_t lut_rows = 0;
     double *phases = nullptr;      // [N] phases the last finalize workgroup reads back
