@@ -395,6 +395,21 @@ __device__ __forceinline__ void commit_bin(const FoldArgs &a, int wg, int b, con
         atomicAdd(reinterpret_cast<unsigned long long *>(&a.acc_int[k]), static_cast<unsigned long long>(q.si));
 }
 
+// Sum F[p] * u[m] over the positions p = p, p + step_p, ... < npos of one bin
+// (skewed LDS position sums), the rotator row m advancing by step_m mod M;
+// tab(m) gives u[m].  The table's source (LDS or global) is chosen outside the
+// loop: a choice inside it made the compiler wait on every load in turn.
+template <int SPV, class Acc, class Tab>
+__device__ __forceinline__ void rotate_bin(Acc &acc, const int *F, int p, int m, int step_p, int step_m, int npos,
+                                           int M, const Tab &tab) {
+#pragma unroll 4
+    for (; p < npos; p += step_p) {
+        acc.add(F[p + p / SPV], tab(m));
+        m += step_m;
+        if (m >= M) m -= M;
+    }
+}
+
 // Samples of the misaligned head and short tail of bin b (workgroup 0 only).
 template <int PREC, typename Tab>
 __device__ void add_edges(const FoldArgs &a, int b, BinAcc<PREC> &q, const Tab *UL, bool u_lds) {
@@ -509,10 +524,10 @@ __device__ __forceinline__ void fold_body(const FoldArgs &a, const int wg, unsig
             if (q >= Sp) q -= Sp;
             int m = q / N;
             Acc acc;
-            for (; p < a.npos; p += N) {
-                acc.add(F[p + p / SPV], u_lds ? UL[m] : table_row<PREC>(a, m));
-                if (++m == M) m = 0;
-            }
+            if (u_lds)
+                rotate_bin<SPV>(acc, F, p, m, N, 1, a.npos, M, [&](int mm) { return UL[mm]; });
+            else
+                rotate_bin<SPV>(acc, F, p, m, N, 1, a.npos, M, [&](int mm) { return table_row<PREC>(a, mm); });
             if (edges) add_edges<PREC>(a, b, acc, UL, u_lds);
             commit_bin<PREC>(a, wg, b, acc, load_global(a.v + b));
         }
@@ -528,12 +543,11 @@ __device__ __forceinline__ void fold_body(const FoldArgs &a, const int wg, unsig
             if (q >= Sp) q -= Sp;
             int m = q / N;
             const int step_m = G % M, step_p = N * G;
-#pragma unroll 4
-            for (; p < a.npos; p += step_p) {
-                acc.add(F[p + p / SPV], u_lds ? UL[m] : table_row<PREC>(a, m));
-                m += step_m;
-                if (m >= M) m -= M;
-            }
+            if (u_lds)
+                rotate_bin<SPV>(acc, F, p, m, step_p, step_m, a.npos, M, [&](int mm) { return UL[mm]; });
+            else
+                rotate_bin<SPV>(acc, F, p, m, step_p, step_m, a.npos, M,
+                                [&](int mm) { return table_row<PREC>(a, mm); });
         }
         __syncthreads();  // every read of F is done: reuse its space
         Acc *scr = reinterpret_cast<Acc *>(lds);
