@@ -52,11 +52,11 @@ struct FoldGeom {
     int threads;      // workgroup size (multiple of 64, >= tile_vecs)
 };
 
-// Dynamic LDS of the fold kernel: skewed position sums (one pad word per vector)
-// overlaid by the epilogue scratch, then the rotator rows when they fit.
-// LDS in front of the rotator table: the skewed position sums plus one spare
-// column of spv + 1 words (the sink of the lanes that walk no column), reused
-// by the epilogue as scratch of kEpilogueScratch bytes per thread.
+// Dynamic LDS of the fold kernel.  In front (fold_front_bytes): the skewed
+// position sums (one pad word per vector) and one spare column of spv + 1
+// words (the sink of the lanes that walk no column), reused by the epilogue
+// as scratch of kEpilogueScratch bytes per thread.  Behind it
+// (fold_lds_bytes): the rotator rows, when there are at most kLdsTableRows.
 __host__ __device__ constexpr size_t fold_front_bytes(int npos, int spv, int threads) {
     return ((static_cast<size_t>(npos + npos / spv + spv + 1) * 4 > static_cast<size_t>(threads) * kEpilogueScratch
                  ? static_cast<size_t>(npos + npos / spv + spv + 1) * 4
