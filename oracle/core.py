@@ -33,8 +33,9 @@ def _bind(path: str):
     lib.orc_fold_int.argtypes = [p, i32, i64, i64, i64, p]
     lib.orc_decode.argtypes = [p, i32, i64, p]
     lib.orc_correlate_rotator.argtypes = [p, i32, i64, i64, i64, i64, p, p, p, p, i32, p, i32, p, p]
+    lib.orc_fold_rot.argtypes = [p, i32, i64, i64, i64, i64, i64, i32, p, p]
     for f in (lib.orc_correlate_packed, lib.orc_correlate_f64, lib.orc_fold_int, lib.orc_decode,
-              lib.orc_max_threads, lib.orc_correlate_rotator):
+              lib.orc_max_threads, lib.orc_correlate_rotator, lib.orc_fold_rot):
         f.restype = ctypes.c_int
     return lib
 
@@ -167,6 +168,18 @@ def fold_int(packed, nbits: int, nsamples: int, nbins: int, n0: int = 0) -> np.n
     if rc:
         raise ValueError("oracle rejected the arguments (code %d)" % rc)
     return out
+
+
+def fold_rot(packed, nbits: int, nsamples: int, fs: int, f_offset: int, nbins: int, n0: int = 0,
+             nthreads: int = 0) -> np.ndarray:
+    """Eqs. 2-3 rotated bins: P[b] = sum of x[n] exp(-j 2 pi f_offset n / fs), n = b (mod nbins), complex."""
+    b = _bytes(packed)
+    re = np.zeros(nbins)
+    im = np.zeros(nbins)
+    rc = _load().orc_fold_rot(_ptr(b), nbits, nsamples, n0, fs, f_offset, nbins, nthreads, _ptr(re), _ptr(im))
+    if rc:
+        raise ValueError("oracle rejected the arguments (code %d)" % rc)
+    return re + 1j * im
 
 
 def decode(packed, nbits: int, nsamples: int) -> np.ndarray:

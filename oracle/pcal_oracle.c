@@ -308,6 +308,62 @@ int orc_fold_int(const uint8_t *packed, int nbits, int64_t nsamples, int64_t n0,
     return ORC_OK;
 }
 
+/* Eqs. 2-3 (Section 2): the rotated, folded bins
+ *   P[b] = sum of x[n] exp(-j 2 pi f_o n / fs) over n = b (mod N),
+ * n = n0 .. n0+nsamples-1, N = nbins.  The phase index (f_o n) mod fs is kept
+ * exact in integers (reduced by g = gcd(fs, f_o)); each bin is one compensated
+ * sum over its samples in increasing n.  The plain definition of the pulse
+ * whose DFT is C_k (Section 2). */
+int orc_fold_rot(const uint8_t *packed, int nbits, int64_t nsamples, int64_t n0, int64_t fs, int64_t fo,
+                 int64_t nbins, int nthreads, double *re, double *im)
+{
+    if ((!packed && nsamples > 0) || (nbits != 2 && nbits != 8) || nsamples < 0 || n0 < 0 || fs <= 0 ||
+        fo < 0 || fo >= fs || nbins <= 0 || !re || !im)
+        return ORC_EINVAL;
+    const int64_t g = orc_gcd(fs, fo);
+    const int64_t P = fs / g;
+    const int64_t a = (fo / g) % P; /* phase index step per sample */
+    /* phase index step between consecutive samples of one bin: (a * N) mod P */
+    const int64_t da = (int64_t)(((unsigned __int128)(uint64_t)a * (uint64_t)(nbins % P)) % (uint64_t)P);
+    double *tab = NULL;
+    if (P <= ORC_TABLE_MAX) {
+        tab = (double *)malloc(sizeof(double) * 2 * (size_t)P);
+        if (!tab) return ORC_ENOMEM;
+        for (int64_t m = 0; m < P; m++) orc_phasor(m, P, &tab[2 * m], &tab[2 * m + 1]);
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < nbins; b++) {
+        /* first sample i >= 0 with (n0 + i) = b (mod N) */
+        const int64_t i0 = ((b - n0 % nbins) % nbins + nbins) % nbins;
+        int64_t m = (int64_t)(((unsigned __int128)(uint64_t)a * (uint64_t)((n0 + i0) % P)) % (uint64_t)P);
+        orc_acc sr = {0.0, 0.0}, si = {0.0, 0.0};
+        for (int64_t i = i0; i < nsamples; i += nbins) {
+            double c, s;
+            if (tab) {
+                c = tab[2 * m];
+                s = tab[2 * m + 1];
+            } else {
+                orc_phasor(m, P, &c, &s);
+            }
+            const double x = (double)orc_level(packed, nbits, i);
+            orc_add(&sr, x * c);
+            orc_add(&si, x * s);
+            m += da;
+            if (m >= P) m -= P;
+        }
+        re[b] = sr.s + sr.c;
+        im[b] = si.s + si.c;
+    }
+    free(tab);
+    return ORC_OK;
+}
+
 int orc_max_threads(void)
 {
 #ifdef _OPENMP

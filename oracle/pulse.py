@@ -1,0 +1,51 @@
+"""Delay at the power peak of the folded pulse (oracle side, numpy FP64).
+
+Test infrastructure only.  Section 2 notes that bin b of the fold P[b]
+stands for a time delay of b / fs and that the delay can be read off near the
+largest bin by a hyperbolic fit over its neighbours; Section 3 takes the
+group delay at the position of maximum power.  The paper gives no formula.
+Readings used here:
+
+* the peak bin b0 is the first bin of largest power |P[b]|^2;
+* the pulse of N tones of equal amplitude is a periodic sinc whose envelope
+  is c / |sin(pi (b - x0) / N)| -- near the peak the hyperbola c / |b - x0|,
+  made periodic.  Fitting it through the amplitudes of b0 and of its larger
+  cyclic neighbour b0 + s (s = +1 or -1) gives the offset d in [0, 1/2]:
+  tan(u d) = a_s sin(u) / (a_0 + a_s cos(u)), u = pi / N.  Equal neighbours
+  give d = 0.  The fit is exact for an equal-amplitude comb at any delay;
+* the pulse position pos = b0 + s d is taken in (-N/2, N/2] bins;
+* the delay is reported in the sign convention of the phase-slope delay (a
+  tone phase that grows as 2 pi f_k t_d): an upper-sideband comb delayed by
+  t_d folds into a pulse at bin -t_d fs (mod N), so delay = -pos / fs; a
+  lower-sideband stream (reported as the conjugate spectrum, whose pulse is
+  conj(P[-b])) gives +pos / fs.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def pulse_peak(P, fs: int, sideband: int = 1):
+    """(b0, signed offset s*d, delay_s, peak_power) of the pulse P[b] (power not normalised)."""
+    P = np.asarray(P, dtype=np.complex128)
+    n = P.size
+    power = P.real * P.real + P.imag * P.imag
+    b0 = int(np.argmax(power))
+    a_0 = math.sqrt(power[b0])
+    a_m = math.sqrt(power[(b0 - 1) % n])
+    a_p = math.sqrt(power[(b0 + 1) % n])
+    if a_p > a_m:
+        s, a_s = 1, a_p
+    elif a_m > a_p:
+        s, a_s = -1, a_m
+    else:
+        s, a_s = 0, 0.0
+    u = math.pi / n
+    d = math.atan2(a_s * math.sin(u), a_0 + a_s * math.cos(u)) / u if s else 0.0
+    pos = b0 + s * d
+    if pos > n / 2.0:
+        pos -= n
+    delay = (-pos if sideband > 0 else pos) / float(fs)
+    return b0, float(s * d), float(delay), float(power[b0])
