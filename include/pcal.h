@@ -153,8 +153,32 @@ int pcal_spectrum(pcal_t h, double *re, double *im);
 
 /* The rotated, folded bins P[b] (b = 0..N-1) of Eq. 2-3 in FP64.  When
  * f_offset == 0 and int_bins != NULL, also the exact integer bins of Eq. 2
- * (int64).  Synchronises. */
+ * (int64); PCAL_ESTATE when int_bins is requested for any other handle.
+ * Computed on the device (the accumulator slots added in slot order) on the
+ * handle's last stream; synchronises. */
 int pcal_bins(pcal_t h, double *re, double *im, int64_t *int_bins);
+
+/* The time-domain pulse of the current integration and the delay at its power
+ * peak (Section 2: bin b of the fold stands for a delay of b / fs, refined by
+ * a fit over the neighbours of the largest bin; Section 3: the group delay is
+ * taken at the position of maximum power).
+ *   re, im  [N] or NULL: the pulse P[b], as pcal_bins returns it.
+ *   delay   [1] or NULL: seconds, in the sign convention of pcal_results'
+ *           phase-slope delay (a comb delayed by t_d gives t_d), in
+ *           (-N/(2 fs), N/(2 fs)].  The peak bin b0 is the first bin of
+ *           largest |P[b]|^2; the offset d in [0, 1/2] towards the larger
+ *           neighbour b0 + s (s = +-1) fits the periodic-hyperbola envelope
+ *           c / |sin(pi (b - x0) / N)| of an N-tone pulse through the two
+ *           amplitudes: tan(pi d / N) = a_s sin(pi / N) / (a_0 + a_s cos(pi / N));
+ *           equal neighbours give d = 0.  Upper sideband: delay = -(b0 + s d) / fs;
+ *           lower sideband: +(b0 + s d) / fs.
+ *   peak    [3] or NULL: b0, the signed offset s d (bins), and the peak power
+ *           |P[b0]|^2 / L^2 (L = samples in the integration; the mixed form's
+ *           known table gain divided out).
+ * An integration with no samples gives b0 = 0 and delay 0.  Computed by one
+ * device workgroup on the handle's last stream; synchronises.  Errors:
+ * PCAL_EINVAL (null handle), PCAL_EHIP. */
+int pcal_pulse(pcal_t h, double *re, double *im, double *delay, double *peak);
 
 /* Start a new integration: zero the accumulators; the global sample index
  * keeps counting (rotator phase stays continuous).  Ordered on the handle's

@@ -249,7 +249,7 @@ int dalloc(pcal_ctx *h, T **p, size_t count) {
 
 void release(pcal_ctx *h) {
     void *ptrs[] = {h->u64, h->u32, h->u16, h->v, h->tw, h->acc_mem, h->acc_int_mem, h->accf_mem, h->counters,
-                    h->out, h->phases, h->rot32, h->rot16, h->w};
+                    h->out, h->phases, h->pulse, h->pulse_int, h->rot32, h->rot16, h->w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->host_out) (void)hipHostFree(h->host_out);
@@ -382,7 +382,8 @@ int build(pcal_ctx *h) {
         (rc = dalloc(h, &h->v, N)) || (rc = dalloc(h, &h->tw, N)) || (rc = dalloc(h, &h->acc_mem, 2 * kAccSlots * N)) ||
         (rc = dalloc(h, &h->acc_int_mem, 2 * kAccSlots * N)) || (rc = dalloc(h, &h->accf_mem, 2 * kAccSlots * N)) ||
         (rc = dalloc(h, &h->counters, 2)) || (rc = dalloc(h, &h->out, 2 * (4 * N + 1))) ||
-        (rc = dalloc(h, &h->phases, N)))
+        (rc = dalloc(h, &h->phases, N)) || (rc = dalloc(h, &h->pulse, 2 * N + 4)) ||
+        (rc = dalloc(h, &h->pulse_int, N)))
         return rc;
     {
         hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->host_out), sizeof(double) * (4 * N + 1),
@@ -786,45 +787,59 @@ int pcal_spectrum(pcal_t h, double *re, double *im) {
     return PCAL_OK;
 }
 
+// Run the pulse readout kernel on the handle's last stream and copy its
+// results (2N + 4 doubles, and the integer bins when host_int is set) to the host.
+static int read_pulse(pcal_ctx *h, double *host, long long *host_int) {
+    const Plan &p = h->plan;
+    const size_t N = static_cast<size_t>(p.N);
+    hipStream_t s = h->last_stream;
+    PulseArgs a{};
+    a.acc = h->acc;
+    a.accf = h->accf;
+    a.acc_int = host_int ? h->acc_int : nullptr;
+    a.N = static_cast<int>(p.N);
+    a.prec = p.prec;
+    a.sideband = p.sideband;
+    a.fs = static_cast<double>(p.fs);
+    a.inv_L = h->n_integ > 0 ? 1.0 / static_cast<double>(h->n_integ) : 0.0;
+    a.gain_re = h->gain_re;
+    a.gain_im = h->gain_im;
+    a.out = h->pulse;
+    a.out_int = host_int ? h->pulse_int : nullptr;
+    launch_pulse(a, s);
+    PCAL_HIP(hipGetLastError());
+    PCAL_HIP(hipMemcpyAsync(host, h->pulse, sizeof(double) * (2 * N + 4), hipMemcpyDeviceToHost, s));
+    if (host_int) PCAL_HIP(hipMemcpyAsync(host_int, h->pulse_int, sizeof(long long) * N, hipMemcpyDeviceToHost, s));
+    PCAL_HIP(hipStreamSynchronize(s));
+    return PCAL_OK;
+}
+
 int pcal_bins(pcal_t h, double *re, double *im, int64_t *int_bins) {
     if (!h) return PCAL_EINVAL;
     if (int_bins && (h->plan.fo != 0 || h->plan.method != PCAL_METHOD_PERIOD_FOLD)) return PCAL_ESTATE;
     DeviceGuard guard(h->device);
     const size_t N = static_cast<size_t>(h->plan.N);
-    hipStream_t s = h->last_stream;
-    const size_t NS = N * kAccSlots;
-    std::vector<double2> b(NS);
-    std::vector<float2> bf(NS);
-    std::vector<long long> ib(NS);
-    if (h->plan.prec == PCAL_PREC_F32)
-        PCAL_HIP(hipMemcpyAsync(bf.data(), h->accf, sizeof(float2) * NS, hipMemcpyDeviceToHost, s));
-    else
-        PCAL_HIP(hipMemcpyAsync(b.data(), h->acc, sizeof(double2) * NS, hipMemcpyDeviceToHost, s));
-    if (int_bins) PCAL_HIP(hipMemcpyAsync(ib.data(), h->acc_int, sizeof(long long) * NS, hipMemcpyDeviceToHost, s));
-    PCAL_HIP(hipStreamSynchronize(s));
-    // add the accumulator slots in slot order (as the finalize does)
-    for (size_t i = 0; i < N; ++i) {
-        double sr = 0.0, si = 0.0;
-        float fr = 0.f, fi = 0.f;
-        long long sn = 0;
-        for (size_t k = 0; k < static_cast<size_t>(kAccSlots); ++k) {
-            if (h->plan.prec == PCAL_PREC_F32) {
-                fr += bf[k * N + i].x;
-                fi += bf[k * N + i].y;
-            } else {
-                sr += b[k * N + i].x;
-                si += b[k * N + i].y;
-            }
-            sn += ib[k * N + i];
-        }
-        if (h->plan.prec == PCAL_PREC_F32) {
-            sr = fr;
-            si = fi;
-        }
-        if (re) re[i] = sr;
-        if (im) im[i] = si;
-        if (int_bins) int_bins[i] = sn;
-    }
+    std::vector<double> out(2 * N + 4);
+    std::vector<long long> ib(int_bins ? N : 0);
+    const int rc = read_pulse(h, out.data(), int_bins ? ib.data() : nullptr);
+    if (rc) return rc;
+    if (re) memcpy(re, out.data(), sizeof(double) * N);
+    if (im) memcpy(im, out.data() + N, sizeof(double) * N);
+    for (size_t i = 0; int_bins && i < N; ++i) int_bins[i] = ib[i];
+    return PCAL_OK;
+}
+
+int pcal_pulse(pcal_t h, double *re, double *im, double *delay, double *peak) {
+    if (!h) return PCAL_EINVAL;
+    DeviceGuard guard(h->device);
+    const size_t N = static_cast<size_t>(h->plan.N);
+    std::vector<double> out(2 * N + 4);
+    const int rc = read_pulse(h, out.data(), nullptr);
+    if (rc) return rc;
+    if (re) memcpy(re, out.data(), sizeof(double) * N);
+    if (im) memcpy(im, out.data() + N, sizeof(double) * N);
+    if (delay) *delay = out[2 * N];
+    if (peak) memcpy(peak, out.data() + 2 * N + 1, sizeof(double) * 3);
     return PCAL_OK;
 }
 

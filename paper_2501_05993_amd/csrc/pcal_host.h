@@ -91,6 +91,8 @@ struct pcal_ctx {
     int lut_shift = 0;            // rotator table layout (RotArgs::lut_shift)
     int64_t lut_rows = 0;
     double *phases = nullptr;      // [N] phases the last finalize workgroup reads back
+    double *pulse = nullptr;       // [2N + 4] pulse readout (PulseArgs::out)
+    long long *pulse_int = nullptr;  // [N] integer bins of the readout
     unsigned *counters = nullptr;  // [0] finalize of bank 0's pending form / plain, [1] bank 1
     double *out = nullptr;         // device results [2][4N + 1]
     double *host_out = nullptr;    // pinned copy

@@ -88,6 +88,22 @@ struct FinArgs {
     long long *acc_int_clear;
 };
 
+// Arguments of the pulse readout (one workgroup): the bins P[b] of the current
+// integration and the delay at the power peak of the pulse.
+struct PulseArgs {
+    const double2 *acc;        // [kAccSlots][N] bins (FP64 forms)
+    const float2 *accf;        // [kAccSlots][N] bins (FP32 form)
+    const long long *acc_int;  // [kAccSlots][N] exact integer bins (f_offset == 0), read when out_int is set
+    int N;
+    int prec;
+    int sideband;
+    double fs;                 // Hz
+    double inv_L;              // 1 / samples in the integration (0 if none)
+    double gain_re, gain_im;   // known gain of the rotator table (identity unless the mixed form)
+    double *out;               // [2N + 4]: re[N], im[N], delay (s), peak bin, offset (bins), peak power
+    long long *out_int;        // [N] integer bins, or null
+};
+
 // Arguments of the fused unpack-rotate-fold kernel (one launch per pcal_extract).
 struct FoldArgs {
     const uint4 *data;       // 16-byte aligned start of the full vectors
@@ -197,6 +213,7 @@ void launch_fold_batch(const FoldListInline &list, int prec, int grid2, int grid
 void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStream_t s,
                    hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_finalize(const FinArgs &a, hipStream_t s);
+void launch_pulse(const PulseArgs &a, hipStream_t s);
 size_t finalize_lds_bytes(int N);
 void launch_finalize_batch(const DeviceList<FinArgs> &list, int grid, size_t lds, hipStream_t s);
 void launch_finalize_batch(const FinListInline &list, int grid, size_t lds, hipStream_t s);

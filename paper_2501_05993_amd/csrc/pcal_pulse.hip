@@ -1,0 +1,113 @@
+// Time-domain pulse of an integration (Section 2): the rotated, folded bins
+// P[b] of Eqs. 2-3, read out of the accumulator slots, and the delay at the
+// power peak of that pulse (Section 2's interpolation near the largest bin,
+// Section 3's group delay at maximum power).  One workgroup, launched once per
+// readout; it reads N x kAccSlots bins and writes 2N + 4 doubles.
+//
+// Delay estimate.  The peak bin b0 is the first bin of largest power.  The
+// pulse of N equal tones is a periodic sinc whose amplitude envelope is
+// c / |sin(pi (b - x0) / N)| (a hyperbola near the peak, made periodic);
+// fitted through the amplitudes of b0 and of its larger neighbour b0 + s it
+// gives the offset d in [0, 1/2] from tan(u d) = a_s sin u / (a_0 + a_s cos u),
+// u = pi / N, exact for an equal-amplitude comb at any delay.  Equal
+// neighbours give d = 0.  The position b0 + s d, taken in (-N/2, N/2], is
+// turned into a delay in the convention of the phase-slope delay: -pos / fs
+// for an upper sideband, +pos / fs for a lower one.
+#include "pcal.h"
+#include "pcal_internal.h"
+
+namespace pcal {
+namespace {
+
+constexpr int kPulseThreads = 256;
+
+// Bin i with the accumulator slots added in slot order (as the finalize adds them).
+__device__ __forceinline__ double2 pulse_bin(const PulseArgs &a, int i) {
+    double re = 0.0, im = 0.0;
+    float fr = 0.f, fi = 0.f;
+#pragma unroll
+    for (int k = 0; k < kAccSlots; ++k) {
+        if (a.prec == PCAL_PREC_F32) {
+            fr += a.accf[k * a.N + i].x;
+            fi += a.accf[k * a.N + i].y;
+        } else {
+            re += a.acc[k * a.N + i].x;
+            im += a.acc[k * a.N + i].y;
+        }
+    }
+    return a.prec == PCAL_PREC_F32 ? make_double2(fr, fi) : make_double2(re, im);
+}
+
+// |p|^2 with both products rounded before the add (no fused multiply-add), so
+// the peak is chosen on the same values a plain FP64 evaluation gives.
+__device__ __forceinline__ double power_of(double2 p) {
+    return __dadd_rn(__dmul_rn(p.x, p.x), __dmul_rn(p.y, p.y));
+}
+
+__global__ void __launch_bounds__(kPulseThreads) pulse_kernel(PulseArgs a) {
+    __shared__ double s_pw[kPulseThreads];
+    __shared__ int s_ix[kPulseThreads];
+    const int N = a.N, t = static_cast<int>(threadIdx.x);
+    double best = -1.0;  // below any power: a thread without bins never wins
+    int bi = 0;
+    for (int i = t; i < N; i += kPulseThreads) {
+        const double2 p = pulse_bin(a, i);
+        a.out[i] = p.x;
+        a.out[N + i] = p.y;
+        if (a.out_int) {
+            long long s = 0;
+            for (int k = 0; k < kAccSlots; ++k) s += a.acc_int[k * N + i];
+            a.out_int[i] = s;
+        }
+        const double pw = power_of(p);
+        if (pw > best) {  // bins visited in increasing order: ties keep the first
+            best = pw;
+            bi = i;
+        }
+    }
+    s_pw[t] = best;
+    s_ix[t] = bi;
+    __syncthreads();
+    for (int w = kPulseThreads / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            const double o = s_pw[t + w];
+            const int oi = s_ix[t + w];
+            if (o > s_pw[t] || (o == s_pw[t] && oi < s_ix[t])) {
+                s_pw[t] = o;
+                s_ix[t] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    const int b0 = s_ix[0];
+    const double a0 = sqrt(s_pw[0]);
+    const double am = sqrt(power_of(pulse_bin(a, b0 == 0 ? N - 1 : b0 - 1)));
+    const double ap = sqrt(power_of(pulse_bin(a, b0 == N - 1 ? 0 : b0 + 1)));
+    int s = 0;
+    double as = 0.0;
+    if (ap > am) {
+        s = 1;
+        as = ap;
+    } else if (am > ap) {
+        s = -1;
+        as = am;
+    }
+    const double u = M_PI / N;
+    const double d = s ? atan2(as * sin(u), a0 + as * cos(u)) / u : 0.0;
+    double pos = b0 + s * d;
+    if (pos > 0.5 * N) pos -= N;
+    const double g2 = a.gain_re * a.gain_re + a.gain_im * a.gain_im;
+    a.out[2 * N] = (a.sideband > 0 ? -pos : pos) / a.fs;
+    a.out[2 * N + 1] = b0;
+    a.out[2 * N + 2] = s * d;
+    a.out[2 * N + 3] = s_pw[0] * g2 * a.inv_L * a.inv_L;
+}
+
+}  // namespace
+
+void launch_pulse(const PulseArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(pulse_kernel, dim3(1), dim3(kPulseThreads), 0, s, a);
+}
+
+}  // namespace pcal

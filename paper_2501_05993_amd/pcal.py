@@ -68,6 +68,8 @@ _SIGS = {
     "pcal_sync": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_flush": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_bins": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "pcal_pulse": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                   ctypes.c_int),
     "pcal_reset": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_num_tones": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -238,6 +240,16 @@ class PCal:
         _check(lib().pcal_bins(self._h, re.ctypes.data, im.ctypes.data, ib.ctypes.data if integer else None),
                "pcal_bins")
         return (re + 1j * im, ib) if integer else re + 1j * im
+
+    def pulse(self):
+        """(P[b] complex [N], delay_s, peak_bin, offset_bins, peak_power) of the current integration."""
+        re = np.zeros(self.ntones)
+        im = np.zeros(self.ntones)
+        delay = ctypes.c_double()
+        peak = np.zeros(3)
+        _check(lib().pcal_pulse(self._h, re.ctypes.data, im.ctypes.data, ctypes.byref(delay), peak.ctypes.data),
+               "pcal_pulse")
+        return re + 1j * im, delay.value, int(peak[0]), float(peak[1]), float(peak[2])
 
     def reset(self) -> None:
         _check(lib().pcal_reset(self._h), "pcal_reset")
