@@ -257,6 +257,70 @@ def precision_report(pcal, torch, synth):
     return out
 
 
+def batched_study(pcal, torch, synth):
+    """Batched form on the 64-stream mix (fs 16-512 MHz, f_offset {0,10,250,510} kHz, 2-bit, 2^26 samples
+    each: 1 GiB): one batched fold call (one launch per sample width over the work-list of all 64 streams,
+    the work-list copy included) timed back to back with events, with its HBM roofline fraction (0.25 B per
+    sample read once); and one synchronised integration of all 64 streams (reset, batched fold, batched
+    finalize, results) against one handle per stream doing the same one stream after another."""
+    specs = synth.batch_specs()
+    L = 1 << 26
+    print("[bench] batched study: 64 streams x 2^26 2-bit samples", file=sys.stderr, flush=True)
+    devs = [synth.make_stream_device(sp, L) for sp in specs]
+    torch.cuda.synchronize()
+    nbytes = len(specs) * L // 4
+    stream = torch.cuda.current_stream()
+    b = pcal.PCalBatch(len(specs))
+    ids = [b.add(sp.fs, sp.f_comb, sp.f_offset, 2) for sp in specs]
+    ns = [L] * len(ids)
+    for _ in range(3):
+        b.extract(ids, devs, ns)
+    torch.cuda.synchronize()
+    K = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(K):
+        b.extract(ids, devs, ns)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_fold = e0.elapsed_time(e1) * 1e-3 / K
+    integ = []
+    for _ in range(10):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        b.reset(ids)
+        b.extract(ids, devs, ns)
+        b.results(ids)
+        integ.append(time.perf_counter() - ts)
+    b.close()
+    hs = [pcal.PCal(sp.fs, sp.f_comb, sp.f_offset, 2) for sp in specs]
+    for h, d in zip(hs, devs):
+        h.extract(d, L)
+        h.results()
+    single = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for h, d in zip(hs, devs):
+            h.reset()
+            h.extract(d, L)
+            h.results()
+        single.append(time.perf_counter() - ts)
+    for h in hs:
+        h.close()
+    del devs
+    torch.cuda.empty_cache()
+    gbs = nbytes / t_fold / 1e9
+    return {"workload": "64 streams, fs 16-512 MHz, f_offset {0,10,250,510} kHz, 2-bit, 2^26 samples each",
+            "fold_call_us": round(t_fold * 1e6, 1),
+            "gsamples_per_s": round(len(specs) * L / t_fold / 1e9, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "kernel": "fold_batch_kernel<2,0>",
+                         "algorithmic_bytes_per_call": nbytes},
+            "integration_ms_p50": round(float(np.median(integ)) * 1e3, 3),
+            "one_handle_per_stream_integration_ms_p50": round(float(np.median(single)) * 1e3, 3)}
+
+
 def rotator_study(pcal, torch, synth):
     """8-bit wide workload (fs = 1024 MHz, f_offset = 510 kHz, N = 1024, rotator period 102400): one
     integration of 2^33 samples streamed in 2^28-sample chunks (the global sample index runs on across
@@ -312,6 +376,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--precision-report", action="store_true",
                     help="only run the 64-stream precision study (mixed and FP32 forms against FP64)")
+    ap.add_argument("--no-batched-study", action="store_true",
+                    help="skip the 64-stream batched-form measurement")
     ap.add_argument("--no-rotator-study", action="store_true",
                     help="skip the 8-bit wide-workload comparison of the rotator forms")
     ap.add_argument("--served-seconds", type=float, default=8.0,
@@ -445,6 +511,8 @@ def main():
     h.close()
     bufs.clear()
     torch.cuda.empty_cache()
+    if not args.no_batched_study:
+        out["batched"] = batched_study(pcal, torch, synth)
     if not args.no_rotator_study:
         out["rotator_study"] = rotator_study(pcal, torch, synth)
     if args.served_seconds > 0:
