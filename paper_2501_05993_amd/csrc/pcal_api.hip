@@ -440,17 +440,32 @@ int build(pcal_ctx *h) {
     return PCAL_OK;
 }
 
+// An event for the handle's last work: recorded now on its last stream when
+// work was enqueued there since the previous record.  Recorded only when
+// needed (a switch of stream, a synchronisation), because an event record
+// between two dependent launches costs the stream ~3-4 us.
+int settle(pcal_ctx *h) {
+    if (!h->dirty) return PCAL_OK;
+    PCAL_HIP(hipEventRecord(h->ev, h->last_stream));
+    h->wait_ev = h->ev;
+    h->have_ev = true;
+    h->dirty = false;
+    return PCAL_OK;
+}
+
 // Order work on `s` after the handle's previous work (possibly on another stream).
 int order_on(pcal_ctx *h, hipStream_t s, bool flush) {
-    if (h->have_ev && s != h->last_stream) PCAL_HIP(hipStreamWaitEvent(s, h->wait_ev, 0));
+    if (s != h->last_stream && (h->dirty || h->have_ev)) {
+        const int rc = settle(h);
+        if (rc) return rc;
+        PCAL_HIP(hipStreamWaitEvent(s, h->wait_ev, 0));
+    }
     return flush ? flush_pending(h, s) : PCAL_OK;
 }
 
 int mark(pcal_ctx *h, hipStream_t s) {
-    PCAL_HIP(hipEventRecord(h->ev, s));
-    h->wait_ev = h->ev;
-    h->have_ev = true;
     h->last_stream = s;
+    h->dirty = true;
     return PCAL_OK;
 }
 
@@ -772,6 +787,8 @@ int pcal_sync(pcal_t h) {
         if (rc) return rc;
         PCAL_HIP(hipStreamSynchronize(h->last_stream));
     }
+    const int rc = settle(h);
+    if (rc) return rc;
     if (h->have_ev) PCAL_HIP(hipEventSynchronize(h->wait_ev));
     return PCAL_OK;
 }
@@ -861,7 +878,7 @@ int pcal_destroy(pcal_t h) {
         DeviceGuard guard(h->device);
         if (h->fin_pending && flush_pending(h, h->last_stream) == PCAL_OK)
             (void)hipStreamSynchronize(h->last_stream);
-        if (h->have_ev) (void)hipEventSynchronize(h->wait_ev);
+        if (settle(h) == PCAL_OK && h->have_ev) (void)hipEventSynchronize(h->wait_ev);
         release(h);
     }
     return PCAL_OK;

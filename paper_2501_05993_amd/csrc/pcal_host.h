@@ -105,8 +105,9 @@ struct pcal_ctx {
     int64_t n_total = 0;
     int64_t n_integ = 0;
     hipStream_t last_stream = nullptr;
-    hipEvent_t ev = nullptr;       // recorded after the handle's own calls
-    hipEvent_t wait_ev = nullptr;  // event marking the handle's last work (ev, or a batch's event)
+    bool dirty = false;            // work enqueued on last_stream since ev was last recorded
+    hipEvent_t ev = nullptr;       // recorded on last_stream when another stream or a sync needs it (settle)
+    hipEvent_t wait_ev = nullptr;  // the recorded event marking the handle's last work
     bool have_ev = false;
     size_t device_bytes = 0;
 };
@@ -122,10 +123,12 @@ int flush_pending(pcal_ctx *h, hipStream_t s);
 void release(pcal_ctx *h);
 int create(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int method, int prec, int force_threads,
            pcal_ctx **out);
-// Order work on `s` after the handle's previous work; record it as the handle's last work.
 // Order s after the handle's last work (a pending finalize runs first unless flush is false).
 int order_on(pcal_ctx *h, hipStream_t s, bool flush = true);
+// Note work just enqueued on s as the handle's last work (no event is recorded here).
 int mark(pcal_ctx *h, hipStream_t s);
+// Record the handle's event on its last stream if work was enqueued there since the last record.
+int settle(pcal_ctx *h);
 // Kernel arguments of one extract call of a period-fold handle (advances the
 // handle's chunk-counter base past the launch).
 FoldArgs fold_args(pcal_ctx *h, const pcal_launch_t &L, const void *dev_ptr);
