@@ -352,6 +352,20 @@ int pcal_server_spectrum(pcal_server_t s, int sid, int64_t integration, double *
 int pcal_server_stats(pcal_server_t s, int64_t *queued_samples, int *inflight_finalizes, int64_t *device_bytes);
 int pcal_server_destroy(pcal_server_t s);
 
+/* Streaming-read reference (not part of the extraction): reads `bytes`
+ * bytes at dev_ptr once with 16-byte non-temporal loads, as the fold kernel
+ * reads its input, in `blocks` workgroups of `threads` threads, each
+ * workgroup owning a contiguous slice, and writes the XOR of the 64-bit words
+ * each wave read to out[wave] (device memory owned by the caller, at least
+ * blocks * threads / 64 words).  Its duration, taken with start_event /
+ * stop_event as in pcal_extract_timed, is the measured ceiling the
+ * bandwidth-bound kernels are compared with.  Asynchronous on stream.
+ * Errors: PCAL_EINVAL for a null or misaligned (16-byte) pointer, bytes not a
+ * positive multiple of 16, threads not a multiple of 64 in [64, 1024], or
+ * blocks < 1; PCAL_EHIP. */
+int pcal_read_probe(const void *dev_ptr, int64_t bytes, int blocks, int threads, uint64_t *out,
+                    pcal_stream_t stream, void *start_event, void *stop_event);
+
 /* Text of a status code. */
 const char *pcal_strerror(int code);
 

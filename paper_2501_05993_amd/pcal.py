@@ -106,6 +106,8 @@ _SIGS = {
     "pcal_server_stats": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_server_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "pcal_read_probe": ([ctypes.c_void_p, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_last_error": ([], ctypes.c_char_p),
 }
 
@@ -136,6 +138,25 @@ def last_error() -> str:
 def _check(code: int, what: str) -> None:
     if code != OK:
         raise PcalError(code, what)
+
+
+def read_probe(data, out, blocks: int, threads: int, stream=None, events=None) -> None:
+    """Streaming-read reference pass over a contiguous device tensor (pcal_read_probe).
+
+    out: int64 device tensor of at least blocks * threads / 64 elements (the
+    XOR of the 64-bit words each wave read); events: optional (start, stop)
+    torch.cuda.Event pair, already recorded once, stamped with the kernel's own
+    start and end."""
+    if not (isinstance(data, torch.Tensor) and data.is_cuda and data.is_contiguous()):
+        raise ValueError("read_probe needs a contiguous device tensor")
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.int64
+            and out.numel() >= blocks * threads // 64):
+        raise ValueError("out needs blocks * threads / 64 int64 elements on the device")
+    e0, e1 = (None, None) if events is None else \
+        (ctypes.c_void_p(int(e.cuda_event)) if e is not None else None for e in events)
+    _check(lib().pcal_read_probe(ctypes.c_void_p(data.data_ptr()), data.numel() * data.element_size(), blocks,
+                                 threads, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream_handle(stream)),
+                                 e0, e1), "pcal_read_probe")
 
 
 def plan(fs: int, f_comb: int, f_offset: int, nbits: int, method: int = METHOD_AUTO,
