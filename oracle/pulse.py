@@ -1,4 +1,4 @@
-"""Delay at the power peak of the folded pulse (oracle side, numpy FP64).
+"""Delay at the power peak of the folded pulse, and the delay-corrected band-pass (oracle side, numpy FP64).
 
 Test infrastructure only.  Section 2 notes that bin b of the fold P[b]
 stands for a time delay of b / fs and that the delay can be read off near the
@@ -49,3 +49,18 @@ def pulse_peak(P, fs: int, sideband: int = 1):
         pos -= n
     delay = (-pos if sideband > 0 else pos) / float(fs)
     return b0, float(s * d), float(delay), float(power[b0])
+
+
+def bandpass(C, fs: int, f_comb: int, f_offset: int, delay: float, sideband: int = 1):
+    """Band-pass corrected for a group delay (Section 3): arg(C_k exp(-j 2 pi f_k delay)) for every tone.
+
+    C are the raw correlations of :func:`oracle.correlate`; a lower-sideband
+    stream is reported as their conjugate (as :func:`oracle.results` does)
+    before the correction; f_k = f_offset + k f_comb.  A comb whose tone
+    phases grow as 2 pi f_k t_d, corrected by t_d, has flat phases.
+    """
+    C = np.asarray(C, dtype=np.complex128)
+    if sideband < 0:
+        C = np.conj(C)
+    f = f_offset + f_comb * np.arange(C.size, dtype=np.float64)
+    return np.angle(C * np.exp(-2j * np.pi * f * delay))

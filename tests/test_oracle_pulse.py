@@ -195,3 +195,30 @@ def test_fold_pins_catch_mutant(tmp_path, name):
     assert src.count(old) == 1, name
     variant = core.build_variant(src.replace(old, new), str(tmp_path / ("mut_%s.so" % name)))
     assert not _fold_pins_hold(variant), name
+
+
+# ------------------------------------------------------------- delay-corrected band-pass
+
+@pytest.mark.parametrize("fs,fo,td,jit", [
+    (64_000_000, 10_000, 3.7e-9, 0.0),
+    (64_000_000, 10_000, 3.7e-9, 0.1),
+    (16_000_000, 250_000, -120e-9, 0.0),
+    (32_000_000, 510_000, 10e-9, 0.05),
+])
+def test_bandpass_of_noiseless_comb_is_flat(oracle_lib, fs, fo, td, jit):
+    """Closed-form C_k of the Eq. 1 comb corrected by its own t_d: phase -pi/2 + eps_k for every tone."""
+    spec = synth.CombSpec(fs, 1_000_000, fo, 2, amp=0.3, t_d=td, jitter=jit, seed=(9,))
+    L = synth.comb_period_length(spec) * 4
+    C = _closed_form(spec, L)
+    got = oracle_lib.bandpass(C, fs, 1_000_000, fo, td)
+    want = np.angle(np.exp(1j * (synth.tone_jitter(spec) - np.pi / 2)))
+    assert np.abs(np.angle(np.exp(1j * (got - want)))).max() < 1e-9
+    # raw correlations that are the conjugate of these, read as a lower sideband, give the same band-pass
+    got_l = oracle_lib.bandpass(np.conj(C), fs, 1_000_000, fo, td, sideband=-1)
+    assert np.abs(np.angle(np.exp(1j * (got_l - want)))).max() < 1e-9
+
+
+def test_bandpass_zero_delay_is_the_phase(oracle_lib):
+    rng = np.random.default_rng(3)
+    C = rng.standard_normal(64) + 1j * rng.standard_normal(64)
+    assert np.array_equal(oracle_lib.bandpass(C, 64_000_000, 1_000_000, 10_000, 0.0), np.angle(C))
