@@ -180,6 +180,16 @@ int pcal_bins(pcal_t h, double *re, double *im, int64_t *int_bins);
  * PCAL_EINVAL (null handle), PCAL_EHIP. */
 int pcal_pulse(pcal_t h, double *re, double *im, double *delay, double *peak);
 
+/* The band-pass of the current integration corrected for the group delay at
+ * the pulse's power peak (Section 3): amp[N] as pcal_results gives it,
+ * phase[N] = arg(C_k exp(-j 2 pi f_k t_g)) in (-pi, pi] with C_k the reported
+ * spectrum (pcal_spectrum), f_k = f_offset + k f_comb and t_g the delay of
+ * pcal_pulse, which is returned in delay[1].  A comb whose tone phases grow
+ * as 2 pi f_k t_g comes out flat.  Any output may be NULL.  Runs the finalize
+ * and the pulse readout on the device (the handle's last stream);
+ * synchronises.  Errors: PCAL_EINVAL (null handle), PCAL_EHIP. */
+int pcal_bandpass(pcal_t h, double *amp, double *phase, double *delay);
+
 /* Start a new integration: zero the accumulators; the global sample index
  * keeps counting (rotator phase stays continuous).  Ordered on the handle's
  * last stream. */

@@ -382,7 +382,7 @@ int build(pcal_ctx *h) {
         (rc = dalloc(h, &h->v, N)) || (rc = dalloc(h, &h->tw, N)) || (rc = dalloc(h, &h->acc_mem, 2 * kAccSlots * N)) ||
         (rc = dalloc(h, &h->acc_int_mem, 2 * kAccSlots * N)) || (rc = dalloc(h, &h->accf_mem, 2 * kAccSlots * N)) ||
         (rc = dalloc(h, &h->counters, 2)) || (rc = dalloc(h, &h->out, 2 * (4 * N + 1))) ||
-        (rc = dalloc(h, &h->phases, N)) || (rc = dalloc(h, &h->pulse, 2 * N + 4)) ||
+        (rc = dalloc(h, &h->phases, N)) || (rc = dalloc(h, &h->pulse, 3 * N + 4)) ||
         (rc = dalloc(h, &h->pulse_int, N)))
         return rc;
     {
@@ -805,8 +805,9 @@ int pcal_spectrum(pcal_t h, double *re, double *im) {
 }
 
 // Run the pulse readout kernel on the handle's last stream and copy its
-// results (2N + 4 doubles, and the integer bins when host_int is set) to the host.
-static int read_pulse(pcal_ctx *h, double *host, long long *host_int) {
+// results (2N + 4 doubles, 3N + 4 with the band-pass of spec, and the integer
+// bins when host_int is set) to the host.
+static int read_pulse(pcal_ctx *h, double *host, long long *host_int, const double *spec = nullptr) {
     const Plan &p = h->plan;
     const size_t N = static_cast<size_t>(p.N);
     hipStream_t s = h->last_stream;
@@ -823,9 +824,12 @@ static int read_pulse(pcal_ctx *h, double *host, long long *host_int) {
     a.gain_im = h->gain_im;
     a.out = h->pulse;
     a.out_int = host_int ? h->pulse_int : nullptr;
+    a.spec = spec;
+    a.f_offset = static_cast<double>(p.fo);
+    a.f_comb = static_cast<double>(p.fc);
     launch_pulse(a, s);
     PCAL_HIP(hipGetLastError());
-    PCAL_HIP(hipMemcpyAsync(host, h->pulse, sizeof(double) * (2 * N + 4), hipMemcpyDeviceToHost, s));
+    PCAL_HIP(hipMemcpyAsync(host, h->pulse, sizeof(double) * ((spec ? 3 : 2) * N + 4), hipMemcpyDeviceToHost, s));
     if (host_int) PCAL_HIP(hipMemcpyAsync(host_int, h->pulse_int, sizeof(long long) * N, hipMemcpyDeviceToHost, s));
     PCAL_HIP(hipStreamSynchronize(s));
     return PCAL_OK;
@@ -857,6 +861,21 @@ int pcal_pulse(pcal_t h, double *re, double *im, double *delay, double *peak) {
     if (im) memcpy(im, out.data() + N, sizeof(double) * N);
     if (delay) *delay = out[2 * N];
     if (peak) memcpy(peak, out.data() + 2 * N + 1, sizeof(double) * 3);
+    return PCAL_OK;
+}
+
+int pcal_bandpass(pcal_t h, double *amp, double *phase, double *delay) {
+    if (!h) return PCAL_EINVAL;
+    DeviceGuard guard(h->device);
+    // the finalize leaves amp, phase, re, im and the slope delay in h->out
+    int rc = run_finalize(h);
+    if (rc) return rc;
+    const size_t N = static_cast<size_t>(h->plan.N);
+    std::vector<double> out(3 * N + 4);
+    if ((rc = read_pulse(h, out.data(), nullptr, h->out + 2 * N))) return rc;
+    if (amp) memcpy(amp, h->host_out, sizeof(double) * N);
+    if (phase) memcpy(phase, out.data() + 2 * N + 4, sizeof(double) * N);
+    if (delay) *delay = out[2 * N];
     return PCAL_OK;
 }
 

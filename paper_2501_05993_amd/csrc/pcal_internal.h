@@ -100,8 +100,11 @@ struct PulseArgs {
     double fs;                 // Hz
     double inv_L;              // 1 / samples in the integration (0 if none)
     double gain_re, gain_im;   // known gain of the rotator table (identity unless the mixed form)
-    double *out;               // [2N + 4]: re[N], im[N], delay (s), peak bin, offset (bins), peak power
+    double *out;               // [2N + 4] (3N + 4 with spec): re[N], im[N], delay (s), peak bin,
+                               // offset (bins), peak power, then the corrected phases [N]
     long long *out_int;        // [N] integer bins, or null
+    const double *spec;        // [2N] reported spectrum (re[N], im[N]) to correct by the delay, or null
+    double f_offset, f_comb;   // Hz: tone k is at f_offset + k f_comb
 };
 
 // Arguments of the fused unpack-rotate-fold kernel (one launch per pcal_extract).

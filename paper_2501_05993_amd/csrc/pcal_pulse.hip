@@ -13,6 +13,10 @@
 // neighbours give d = 0.  The position b0 + s d, taken in (-N/2, N/2], is
 // turned into a delay in the convention of the phase-slope delay: -pos / fs
 // for an upper sideband, +pos / fs for a lower one.
+//
+// Delay-corrected band-pass (Section 3): given the reported spectrum C_k, the
+// phases arg(C_k exp(-j 2 pi f_k t)) with t that delay, f_k = f_offset +
+// k f_comb: flat for a comb whose phases grow as 2 pi f_k t.
 #include "pcal.h"
 #include "pcal_internal.h"
 
@@ -44,9 +48,39 @@ __device__ __forceinline__ double power_of(double2 p) {
     return __dadd_rn(__dmul_rn(p.x, p.x), __dmul_rn(p.y, p.y));
 }
 
+// Offset and delay of the pulse peak at bin b0 of power p0; writes
+// out[2N .. 2N + 3] and returns the delay.
+__device__ double peak_delay(const PulseArgs &a, int b0, double p0) {
+    const int N = a.N;
+    const double a0 = sqrt(p0);
+    const double am = sqrt(power_of(pulse_bin(a, b0 == 0 ? N - 1 : b0 - 1)));
+    const double ap = sqrt(power_of(pulse_bin(a, b0 == N - 1 ? 0 : b0 + 1)));
+    int s = 0;
+    double as = 0.0;
+    if (ap > am) {
+        s = 1;
+        as = ap;
+    } else if (am > ap) {
+        s = -1;
+        as = am;
+    }
+    const double u = M_PI / N;
+    const double d = s ? atan2(as * sin(u), a0 + as * cos(u)) / u : 0.0;
+    double pos = b0 + s * d;
+    if (pos > 0.5 * N) pos -= N;
+    const double g2 = a.gain_re * a.gain_re + a.gain_im * a.gain_im;
+    const double delay = (a.sideband > 0 ? -pos : pos) / a.fs;
+    a.out[2 * N] = delay;
+    a.out[2 * N + 1] = b0;
+    a.out[2 * N + 2] = s * d;
+    a.out[2 * N + 3] = p0 * g2 * a.inv_L * a.inv_L;
+    return delay;
+}
+
 __global__ void __launch_bounds__(kPulseThreads) pulse_kernel(PulseArgs a) {
     __shared__ double s_pw[kPulseThreads];
     __shared__ int s_ix[kPulseThreads];
+    __shared__ double s_delay;
     const int N = a.N, t = static_cast<int>(threadIdx.x);
     double best = -1.0;  // below any power: a thread without bins never wins
     int bi = 0;
@@ -79,29 +113,16 @@ __global__ void __launch_bounds__(kPulseThreads) pulse_kernel(PulseArgs a) {
         }
         __syncthreads();
     }
-    if (t != 0) return;
-    const int b0 = s_ix[0];
-    const double a0 = sqrt(s_pw[0]);
-    const double am = sqrt(power_of(pulse_bin(a, b0 == 0 ? N - 1 : b0 - 1)));
-    const double ap = sqrt(power_of(pulse_bin(a, b0 == N - 1 ? 0 : b0 + 1)));
-    int s = 0;
-    double as = 0.0;
-    if (ap > am) {
-        s = 1;
-        as = ap;
-    } else if (am > ap) {
-        s = -1;
-        as = am;
+    if (t == 0) s_delay = peak_delay(a, s_ix[0], s_pw[0]);
+    if (!a.spec) return;
+    __syncthreads();
+    const double delay = s_delay;
+    for (int k = t; k < N; k += kPulseThreads) {
+        const double th = 2.0 * M_PI * (a.f_offset + k * a.f_comb) * delay;
+        const double c = cos(th), sn = sin(th);
+        const double re = a.spec[k], im = a.spec[N + k];
+        a.out[2 * N + 4 + k] = atan2(im * c - re * sn, re * c + im * sn);
     }
-    const double u = M_PI / N;
-    const double d = s ? atan2(as * sin(u), a0 + as * cos(u)) / u : 0.0;
-    double pos = b0 + s * d;
-    if (pos > 0.5 * N) pos -= N;
-    const double g2 = a.gain_re * a.gain_re + a.gain_im * a.gain_im;
-    a.out[2 * N] = (a.sideband > 0 ? -pos : pos) / a.fs;
-    a.out[2 * N + 1] = b0;
-    a.out[2 * N + 2] = s * d;
-    a.out[2 * N + 3] = s_pw[0] * g2 * a.inv_L * a.inv_L;
 }
 
 }  // namespace

@@ -70,6 +70,7 @@ _SIGS = {
     "pcal_bins": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_pulse": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
                    ctypes.c_int),
+    "pcal_bandpass": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_reset": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_num_tones": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -271,6 +272,14 @@ class PCal:
         _check(lib().pcal_pulse(self._h, re.ctypes.data, im.ctypes.data, ctypes.byref(delay), peak.ctypes.data),
                "pcal_pulse")
         return re + 1j * im, delay.value, int(peak[0]), float(peak[1]), float(peak[2])
+
+    def bandpass(self):
+        """(amp[N], phase[N] corrected for the pulse's group delay, that delay in s)."""
+        amp = np.zeros(self.ntones)
+        ph = np.zeros(self.ntones)
+        delay = ctypes.c_double()
+        _check(lib().pcal_bandpass(self._h, amp.ctypes.data, ph.ctypes.data, ctypes.byref(delay)), "pcal_bandpass")
+        return amp, ph, delay.value
 
     def reset(self) -> None:
         _check(lib().pcal_reset(self._h), "pcal_reset")

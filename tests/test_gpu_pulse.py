@@ -141,3 +141,26 @@ def test_pulse_full_size_properties(pc):
     assert b0 == wb0 and abs(off - woff) <= 1e-9 and abs(delay - wdelay) * spec.fs <= 1e-9
     assert abs(power - wpower / float(L) ** 2) <= 1e-12 * power
     assert abs(delay - spec.t_d) * spec.fs < 0.1
+
+
+@pytest.mark.parametrize("name,sideband,L", [("fold2_64M_10k", 1, 1 << 24), ("fold2_64M_10k", -1, 1 << 22),
+                                             ("wide8_1024M_510k", 1, 1 << 22)])
+def test_bandpass_matches_oracle(pc, name, sideband, L):
+    """Band-pass corrected for the pulse's group delay (Section 3) against the oracle's, tone by tone."""
+    spec = synth.WORKLOADS[name]["spec"]
+    say("bandpass %s sideband %d L=%d" % (name, sideband, L))
+    packed = synth.make_stream(spec, L)
+    with pc.PCal(spec.fs, spec.f_comb, spec.f_offset, spec.nbits, sideband=sideband) as h:
+        h.extract(_dev(packed), L)
+        amp, ph, delay = h.bandpass()
+        amp_r, _, _ = h.results()
+    C = oracle.correlate(packed, spec.nbits, L, spec.fs, spec.f_comb, spec.f_offset)
+    P = oracle.fold_rot(packed, spec.nbits, L, spec.fs, spec.f_offset, spec.ntones)
+    _, _, wdelay, _ = oracle.pulse_peak(P, spec.fs, sideband=sideband)
+    want = oracle.bandpass(C, spec.fs, spec.f_comb, spec.f_offset, wdelay, sideband=sideband)
+    strong = np.abs(C) >= 1e-5 * np.abs(C).max()
+    err = np.abs(np.angle(np.exp(1j * (ph - want))))[strong].max()
+    say("bandpass phase err %.3e rad, delay %.6e s (oracle %.6e)" % (err, delay, wdelay))
+    assert np.array_equal(amp, amp_r)
+    assert abs(delay - wdelay) * spec.fs <= 1e-7
+    assert err <= 1e-6
