@@ -124,3 +124,37 @@ def test_batch_rejects_a_stream_listed_twice(pc):
     for i, s in enumerate(specs):
         Co = oracle.correlate(packed[i], 2, L, s.fs, s.f_comb, s.f_offset)
         assert_spectra(C[i], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6, what="after rejected %d" % i)
+
+
+def test_batch_calls_on_several_streams(pc):
+    """Batched calls, and one member's own call, alternate over three streams.
+
+    Each call must order after the listed members' previous work on other
+    streams (their events are recorded only when a stream changes), and each
+    staged work-list, copied on the batch's copy stream, must reach the device
+    before its launch.  Every member equals the oracle."""
+    import ctypes
+
+    specs = synth.batch_specs(12, seed=13)
+    L = 1 << 20
+    packed = [synth.make_stream(s, L) for s in specs]
+    devs = [torch.from_numpy(p).cuda() for p in packed]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    q = L // 4
+    say("batch of 12 streams over 3 HIP streams")
+    with pc.PCalBatch(12) as b:
+        ids = [b.add(s.fs, s.f_comb, s.f_offset, s.nbits) for s in specs]
+        for c in range(4):
+            ptrs = [d.data_ptr() + c * q // 4 for d in devs]
+            if c == 2:  # member 0 alone (its own launch) on another stream, the other 11 batched
+                h = ctypes.c_void_p()
+                assert pc.lib().pcal_batch_handle(b._b, ids[0], ctypes.byref(h)) == 0
+                assert pc.lib().pcal_extract(h, ctypes.c_void_p(ptrs[0]), q,
+                                             ctypes.c_void_p(streams[(c + 1) % 3].cuda_stream)) == 0
+                b.extract(ids[1:], ptrs[1:], [q] * 11, stream=streams[c % 3])
+            else:
+                b.extract(ids, ptrs, [q] * 12, stream=streams[c % 3])
+        C = b.spectra(ids)
+    for i, s in enumerate(specs):
+        Co = oracle.correlate(packed[i], 2, L, s.fs, s.f_comb, s.f_offset)
+        assert_spectra(C[i], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6, what="streams %d" % i)
