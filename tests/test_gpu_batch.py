@@ -158,3 +158,36 @@ def test_batch_calls_on_several_streams(pc):
     for i, s in enumerate(specs):
         Co = oracle.correlate(packed[i], 2, L, s.fs, s.f_comb, s.f_offset)
         assert_spectra(C[i], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6, what="streams %d" % i)
+
+
+def test_batch_full_size_sampled(pc):
+    """The benchmark's batched configuration (64 streams x 2^26 2-bit samples, generated on the device, the
+    default launch shape): two tones per stream against the oracle, and the exact integer bins of every
+    f_offset = 0 stream."""
+    import ctypes
+
+    specs = synth.batch_specs()
+    L = 1 << 26
+    say("batch full size: 64 streams x 2^26 samples")
+    devs = [synth.make_stream_device(s, L) for s in specs]
+    with pc.PCalBatch(len(specs)) as b:
+        ids = [b.add(s.fs, s.f_comb, s.f_offset, 2) for s in specs]
+        b.extract(ids, devs, [L] * len(ids))
+        C = b.spectra(ids)
+        ib = {}
+        for i, s in enumerate(specs):
+            if s.f_offset == 0:
+                h = ctypes.c_void_p()
+                assert pc.lib().pcal_batch_handle(b._b, ids[i], ctypes.byref(h)) == 0
+                ib[i] = np.zeros(s.ntones, dtype=np.int64)
+                assert pc.lib().pcal_bins(h, None, None, ib[i].ctypes.data) == 0
+    assert ib
+    for i, s in enumerate(specs):
+        host = devs[i].cpu().numpy()
+        tones = [1, s.ntones // 3]
+        Co = oracle.correlate(host, 2, L, s.fs, s.f_comb, s.f_offset, tones=tones)
+        err = np.abs(C[i][tones] - Co).max() / np.abs(Co).max()
+        assert err <= F64_RTOL, (i, err)
+        if i in ib:
+            np.testing.assert_array_equal(ib[i], oracle.fold_int(host, 2, L, s.ntones))
+    say("batch full size: %d streams, %d with integer bins" % (len(specs), len(ib)))
