@@ -356,8 +356,8 @@ def batched_study(pcal, torch, synth):
 def rotator_study(pcal, torch, synth):
     """8-bit wide workload (fs = 1024 MHz, f_offset = 510 kHz, N = 1024, rotator period 102400): one
     integration of 2^33 samples streamed in 2^28-sample chunks (the global sample index runs on across
-    chunks) through each rotator form -- the period fold, the per-sample rotator table and the recurrence
-    (Eq. 7) -- timed with events around the 32 launches, with each form's HBM roofline fraction (1 B per
+    chunks) through each rotator form -- the period fold, the per-sample rotator table, the recurrence
+    (Eq. 7) and the coupled-form oscillator -- timed with events around the 32 launches, with each form's HBM roofline fraction (1 B per
     sample read once) and its spectrum's spread against the period fold's (tones with signal)."""
     w = synth.WORKLOADS["wide8_1024M_510k"]
     spec, L, chunk = w["spec"], w["nsamples"], w["chunk"]
@@ -365,7 +365,8 @@ def rotator_study(pcal, torch, synth):
     buf = synth.make_stream_device(spec, L)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    forms = (("period_fold", pcal.METHOD_PERIOD_FOLD), ("table", pcal.METHOD_LUT), ("recurrence", pcal.METHOD_OSC))
+    forms = (("period_fold", pcal.METHOD_PERIOD_FOLD), ("table", pcal.METHOD_LUT), ("recurrence", pcal.METHOD_OSC),
+             ("coupled_form", pcal.METHOD_CFO))
     out, spectra = {}, {}
     for name, method in forms:
         h = pcal.PCal(spec.fs, spec.f_comb, spec.f_offset, spec.nbits, method=method)

@@ -61,12 +61,16 @@ enum pcal_status {
  *      table, Section 4.1), accumulate in FP32.
  *  OSC: multiply every sample by a recurrence sinewave generator (Eq. 6-7
  *      direct-form resonator), re-seeded exactly at intervals.
+ *  CFO: as OSC with the coupled-form oscillator of Section 2.2 (the rotator
+ *      times exp(-j d) per step, d the rotator advance of one step), for
+ *      comparison with the direct-form resonator.
  *  AUTO: PERIOD_FOLD when the joint period fits, else OSC. */
 enum pcal_method {
     PCAL_METHOD_AUTO = 0,
     PCAL_METHOD_PERIOD_FOLD = 1,
     PCAL_METHOD_LUT = 2,
-    PCAL_METHOD_OSC = 3
+    PCAL_METHOD_OSC = 3,
+    PCAL_METHOD_CFO = 4
 };
 
 /* Arithmetic of the rotation and the per-block fold.  The cross-block

@@ -115,7 +115,7 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
               int force_threads) {
     int rc = check_params(fs, fc, fo, nbits, sideband);
     if (rc) return rc;
-    if (method < PCAL_METHOD_AUTO || method > PCAL_METHOD_OSC) return PCAL_EINVAL;
+    if (method < PCAL_METHOD_AUTO || method > PCAL_METHOD_CFO) return PCAL_EINVAL;
     if (prec < PCAL_PREC_F64 || prec > PCAL_PREC_F32) return PCAL_EINVAL;
     p->fs = fs;
     p->fc = fc;
@@ -145,7 +145,7 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
         method = (fold_ok && p->Sp <= kAutoFoldPeriod) ? PCAL_METHOD_PERIOD_FOLD : PCAL_METHOD_OSC;
     if (method == PCAL_METHOD_PERIOD_FOLD && !fold_ok) return PCAL_ENOTSUP;
     if (method == PCAL_METHOD_LUT && (p->R > kMaxLutPeriod || !osc_ok)) return PCAL_ENOTSUP;
-    if (method == PCAL_METHOD_OSC && !osc_ok) return PCAL_ENOTSUP;
+    if ((method == PCAL_METHOD_OSC || method == PCAL_METHOD_CFO) && !osc_ok) return PCAL_ENOTSUP;
     p->method = method;
     if (method == PCAL_METHOD_PERIOD_FOLD) {
         p->geom = plan_geom(p->Sp, spv_of(nbits), kMaxLdsPositions, kMaxFoldThreads, force_threads,

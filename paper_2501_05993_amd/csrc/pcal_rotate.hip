@@ -1,9 +1,11 @@
 // Per-sample rotation forms of libpcal: every sample is multiplied by the
 // rotator exp(-j w_o n) of Eq. 3 before it is folded into bin n mod N (Eq. 2).
 // The rotator comes either from a precomputed table of one rotator period
-// (Eq. 4, the precomputed method of Section 4.1) or from the direct-form
+// (Eq. 4, the precomputed method of Section 4.1), from the direct-form
 // resonator recurrence y[r+1] = 2 cos(d) y[r] - y[r-1] (Eq. 6-7, the
-// oscillator method), re-seeded exactly at fixed intervals.
+// oscillator method) or from the coupled-form oscillator z[r+1] = z[r]
+// exp(-j d) (the first of the recursions Section 2.2 lists); both recurrences
+// are re-seeded exactly at fixed intervals.
 //
 // Layout.  A thread owns 16 consecutive samples of every row (one 16-byte
 // load at 8-bit, one 4-byte load at 2-bit); rows are a multiple of N samples,
@@ -122,13 +124,16 @@ struct LaneTot<2> {
     __device__ __forceinline__ double2 get(int k) const { return make_double2(r[k], i[k]); }
 };
 
-// Row rotator source: table (METHOD 2) or recurrence (METHOD 3).
+// Row rotator source: table (METHOD 2), direct-form resonator (METHOD 3) or
+// coupled-form oscillator (METHOD 4).
 template <int METHOD, int PREC>
 struct RowRot {
     // table state
     int64_t idx = 0, step = 0, R = 1;
-    // recurrence state (real and imaginary parts run the same two-term recurrence)
-    float zr = 0.f, zi = 0.f, pr = 0.f, pi = 0.f, c2 = 0.f;
+    // recurrence state: the DFR runs the same two-term recurrence on the real
+    // and imaginary parts (c2 = 2 cos d); the CFO multiplies the rotator by
+    // m = exp(-j d) each row (d = w_o times the samples per row)
+    float zr = 0.f, zi = 0.f, pr = 0.f, pi = 0.f, c2 = 0.f, mr = 0.f, mi = 0.f;
     int64_t n = 0, dn = 0;  // global index of the row's first lane sample, row stride in samples
 
     __device__ __forceinline__ float2 table(const RotArgs &a, int64_t n) const {
@@ -156,12 +161,18 @@ struct RowRot {
                 z[u] = table(a, idx);
                 idx += step;
                 if (idx >= R) idx -= R;
-            } else {
+            } else if constexpr (METHOD == 3) {
                 z[u] = make_float2(zr, zi);
                 // Eq. 7: one FMA per component and row
                 const float nr = fmaf(c2, zr, -pr), ni = fmaf(c2, zi, -pi);
                 pr = zr;
                 pi = zi;
+                zr = nr;
+                zi = ni;
+            } else {
+                z[u] = make_float2(zr, zi);
+                // coupled form: a complex multiply by exp(-j d) per row
+                const float nr = fmaf(zr, mr, -zi * mi), ni = fmaf(zr, mi, zi * mr);
                 zr = nr;
                 zi = ni;
             }
@@ -199,6 +210,8 @@ __global__ void __launch_bounds__(kMaxRotThreads) rot_kernel(RotArgs a) {
             rot.idx = rot.n % a.R;
         } else {
             rot.c2 = a.c2;
+            rot.mr = static_cast<float>(a.back.x);   // exp(-j d) = conj(exp(+j d))
+            rot.mi = static_cast<float>(-a.back.y);
             rot.seed(a);
         }
         LaneTot<PREC> tot;
@@ -250,7 +263,7 @@ __global__ void __launch_bounds__(kMaxRotThreads) rot_kernel(RotArgs a) {
                 else
                     tot.add(k, 2.f * ar[k] - 3.f * sr, 2.f * ai[k] - 3.f * si);
             }
-            if constexpr (METHOD == 3) rot.seed(a);  // exact restart of the recurrence
+            if constexpr (METHOD != 2) rot.seed(a);  // exact restart of the recurrence
         }
         // lane factor exp(-j w_o i) in FP64, then into the workgroup's bins
         const int bbase = static_cast<int>((a.g0 + static_cast<int64_t>(colr) * kLanes) % N);
@@ -307,14 +320,18 @@ void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStrea
     if (a.nbits == 2) {
         if (a.method == 2) {
             if (a.prec == 0) PCAL_ROT(2, 2, 0); else if (a.prec == 1) PCAL_ROT(2, 2, 1); else PCAL_ROT(2, 2, 2);
-        } else {
+        } else if (a.method == 3) {
             if (a.prec == 0) PCAL_ROT(2, 3, 0); else if (a.prec == 1) PCAL_ROT(2, 3, 1); else PCAL_ROT(2, 3, 2);
+        } else {
+            if (a.prec == 0) PCAL_ROT(2, 4, 0); else if (a.prec == 1) PCAL_ROT(2, 4, 1); else PCAL_ROT(2, 4, 2);
         }
     } else {
         if (a.method == 2) {
             if (a.prec == 0) PCAL_ROT(8, 2, 0); else if (a.prec == 1) PCAL_ROT(8, 2, 1); else PCAL_ROT(8, 2, 2);
-        } else {
+        } else if (a.method == 3) {
             if (a.prec == 0) PCAL_ROT(8, 3, 0); else if (a.prec == 1) PCAL_ROT(8, 3, 1); else PCAL_ROT(8, 3, 2);
+        } else {
+            if (a.prec == 0) PCAL_ROT(8, 4, 0); else if (a.prec == 1) PCAL_ROT(8, 4, 1); else PCAL_ROT(8, 4, 2);
         }
     }
 #undef PCAL_ROT

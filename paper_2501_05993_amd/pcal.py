@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpcal.so")
 
 OK, EINVAL, ENOMEM, EHIP, EAGAIN, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
-METHOD_AUTO, METHOD_PERIOD_FOLD, METHOD_LUT, METHOD_OSC = 0, 1, 2, 3
+METHOD_AUTO, METHOD_PERIOD_FOLD, METHOD_LUT, METHOD_OSC, METHOD_CFO = 0, 1, 2, 3, 4
 PREC_F64, PREC_MIXED, PREC_F32 = 0, 1, 2
 
 _i64 = ctypes.c_int64

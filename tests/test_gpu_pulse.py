@@ -105,9 +105,9 @@ def test_pulse_lower_sideband(pc):
     _check(got, want, spec.fs, L, sideband=-1, what="LSB")
 
 
-@pytest.mark.parametrize("method,prec", [(3, 0), (2, 0), (1, 1), (1, 2)])
+@pytest.mark.parametrize("method,prec", [(3, 0), (4, 0), (2, 0), (1, 1), (1, 2)])
 def test_pulse_other_forms(pc, method, prec):
-    """Per-sample rotator forms (table, recurrence) and the mixed / all-FP32 precision forms."""
+    """Per-sample rotator forms (table, recurrences) and the mixed / all-FP32 precision forms."""
     spec = synth.CombSpec(32_000_000, 1_000_000, 10_000, 8, amp=1.0, t_d=20e-9, sigma=20.0, seed=(4, method, prec))
     L = 1 << 22
     say("pulse method=%d precision=%d L=%d" % (method, prec, L))

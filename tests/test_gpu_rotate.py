@@ -1,8 +1,9 @@
-"""Per-sample rotation forms (rotator table, Eq. 4; recurrence, Eq. 6-7) on the GPU.
+"""Per-sample rotation forms (rotator table, Eq. 4; recurrences, Eq. 6-7 and the coupled form) on the GPU.
 
 Every sample is multiplied by an FP32 rotator; the table form reads it from
-one rotator period, the recurrence form steps a direct-form resonator per
-row with exact FP64 restarts every 64 rows.  Checked against the FP64 oracle
+one rotator period, the recurrence forms step a direct-form resonator
+(method 3) or a coupled-form oscillator (method 4) per row with exact FP64
+restarts every 64 rows.  Checked against the FP64 oracle
 to the contract tolerance (1e-5 relative amplitude, 1e-4 rad phase).
 """
 import numpy as np
@@ -45,7 +46,7 @@ def _extract(pc, spec, packed, L, method, prec=0, chunks=None, offset=0):
     return C, res
 
 
-@pytest.mark.parametrize("method", [2, 3])
+@pytest.mark.parametrize("method", [2, 3, 4])
 def test_wide8_per_sample(pc, method):
     spec = synth.WORKLOADS["wide8_1024M_510k"]["spec"]
     L = (1 << 22) + 4096 + 7
@@ -58,7 +59,7 @@ def test_wide8_per_sample(pc, method):
     assert abs(d - do) < 1e-11
 
 
-@pytest.mark.parametrize("method", [2, 3])
+@pytest.mark.parametrize("method", [2, 3, 4])
 def test_fold2_per_sample_chunks(pc, method):
     spec = synth.WORKLOADS["fold2_64M_10k"]["spec"]
     L = 4 * 700_001
@@ -86,7 +87,7 @@ def test_prime_offset_recurrence(pc):
     assert_spectra(C, Co, what="prime offset")
 
 
-@pytest.mark.parametrize("method", [2, 3])
+@pytest.mark.parametrize("method", [2, 3, 4])
 @pytest.mark.parametrize("prec", [1, 2])
 def test_per_sample_reduced_precision(pc, method, prec):
     spec = synth.WORKLOADS["wide8_1024M_510k"]["spec"]
