@@ -26,7 +26,9 @@
  *     block sums are added pairwise in block order (deterministic).
  *
  * It also provides the integer fold of Eq. 2 (bins P[b] = sum of x[n] with
- * n = b mod N, exact in int64) and its own decoder of the packed samples
+ * n = b mod N, exact in int64), the rotated fold of Eqs. 2-3 (the pulse
+ * P[b] = sum of x[n] exp(-j*w_offset*n), with the same exact phase index),
+ * and its own decoder of the packed samples
  * (2-bit offset-binary LSB-first codes -> levels {-3,-1,+1,+3}; 8-bit two's
  * complement), written independently of the library's unpacking.
  *
