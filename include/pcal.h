@@ -132,9 +132,12 @@ int pcal_results(pcal_t h, double *amp, double *phase, double *delay);
  *   keeps its bins in two banks: the finalize of the current bank (which also
  *   clears it) is left pending and the handle switches banks, so the next
  *   pcal_extract runs that finalize inside its own launch, in one of its
- *   workgroups (period fold; the per-sample forms run it at once).  Any other
- *   call on the handle runs a pending finalize on its own first; pcal_sync
- *   runs it and waits.  With host_out in pinned host memory (hipHostMalloc)
+ *   workgroups (period fold; the per-sample forms run it at once).  The calls
+ *   that finalize (pcal_results, pcal_spectrum, pcal_bandpass, another
+ *   pcal_results_async) and pcal_flush run a pending finalize on its own
+ *   first, pcal_sync runs it and waits; pcal_bins, pcal_pulse and pcal_reset
+ *   work on the new integration's bank and leave it pending.  With host_out
+ *   in pinned host memory (hipHostMalloc)
  *   the finalize writes host_out directly; otherwise a device copy is
  *   enqueued after it. */
 int pcal_results_async(pcal_t h, double *host_out, int reset);
