@@ -353,6 +353,41 @@ def batched_study(pcal, torch, synth):
             "one_handle_per_stream_integration_ms_p50": round(float(np.median(single)) * 1e3, 3)}
 
 
+def precision_single(pcal, torch, synth):
+    """Precision of the mixed and all-FP32 forms against the FP64 form on the single-stream workloads: the
+    2-bit fs 64 MHz / 10 kHz stream (2^30 samples, one launch) and the 8-bit fs 1024 MHz / 510 kHz stream
+    (2^33 samples in 2^28-sample launches, the global index running on), period fold."""
+    out = {}
+    for name in ("fold2_64M_10k", "wide8_1024M_510k"):
+        w = synth.WORKLOADS[name]
+        spec, L = w["spec"], w["nsamples"]
+        chunk = w.get("chunk", L)
+        print("[bench] precision study: %s" % name, file=sys.stderr, flush=True)
+        buf = synth.make_stream_device(spec, L)
+        torch.cuda.synchronize()
+        res = {}
+        for prec in (pcal.PREC_F64, pcal.PREC_MIXED, pcal.PREC_F32):
+            with pcal.PCal(spec.fs, spec.f_comb, spec.f_offset, spec.nbits, precision=prec) as h:
+                for k in range(L // chunk):
+                    h.extract(buf, chunk, byte_offset=k * chunk * spec.nbits // 8)
+                C = h.spectrum()
+                _, _, d = h.results()
+            res[prec] = (C, d)
+        del buf
+        torch.cuda.empty_cache()
+        C64, d64 = res[pcal.PREC_F64]
+        strong = np.abs(C64) >= 1e-5 * np.abs(C64).max()
+        entry = {}
+        for label, prec in (("mixed", pcal.PREC_MIXED), ("f32", pcal.PREC_F32)):
+            C, d = res[prec]
+            entry[label] = {
+                "amp_rel_err_max": float(np.max(np.abs(np.abs(C[strong]) - np.abs(C64[strong])) / np.abs(C64[strong]))),
+                "phase_err_rad_max": float(np.max(np.abs(np.angle(C[strong] * np.conj(C64[strong]))))),
+                "delay_err_s": float(abs(d - d64))}
+        out[name] = entry
+    return out
+
+
 def rotator_study(pcal, torch, synth):
     """8-bit wide workload (fs = 1024 MHz, f_offset = 510 kHz, N = 1024, rotator period 102400): one
     integration of 2^33 samples streamed in 2^28-sample chunks (the global sample index runs on across
@@ -441,7 +476,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes": 256 << 20, "copies": 10}), flush=True)
         return
     if args.precision_report:
-        print(json.dumps({"precision_report": precision_report(pcal, torch, synth)}), flush=True)
+        print(json.dumps({"precision_report": precision_report(pcal, torch, synth),
+                          "precision_single_stream": precision_single(pcal, torch, synth)}), flush=True)
         return
     w = synth.WORKLOADS[WORKLOAD]
     spec, L = w["spec"], w["nsamples"]
