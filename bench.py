@@ -63,18 +63,30 @@ def cpu_baseline(host_bytes, spec, target_s=12.0):
     import oracle
 
     threads = oracle.max_threads()
+    n1 = 1 << 23  # the same work on one core (run first: every call below sets its own thread count)
+    t0 = time.perf_counter()
+    oracle.correlate(host_bytes[: n1 // 4], 2, n1, spec.fs, spec.f_comb, spec.f_offset, nthreads=1)
+    dt1 = time.perf_counter() - t0
     n = 1 << 20
     t0 = time.perf_counter()
-    oracle.correlate(host_bytes[: n // 4], 2, n, spec.fs, spec.f_comb, spec.f_offset)
+    oracle.correlate(host_bytes[: n // 4], 2, n, spec.fs, spec.f_comb, spec.f_offset, nthreads=threads)
     dt = time.perf_counter() - t0
     n2 = int(min(len(host_bytes) * 4, max(n, n * target_s / max(dt, 1e-6))))
     n2 -= n2 % (1 << 20)
     t0 = time.perf_counter()
-    oracle.correlate(host_bytes[: n2 // 4], 2, n2, spec.fs, spec.f_comb, spec.f_offset)
+    oracle.correlate(host_bytes[: n2 // 4], 2, n2, spec.fs, spec.f_comb, spec.f_offset, nthreads=threads)
     dt2 = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(n2 / dt2 / 1e9, 6), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
             "sample": "first %d samples (2^%.1f) of the bench's 2-bit input buffers, all %d tones, FP64 "
-                      "per-tone correlation, %.1f s" % (n2, np.log2(n2), spec.ntones, dt2)}
+                      "per-tone correlation, %.1f s" % (n2, np.log2(n2), spec.ntones, dt2),
+            "one_core": {"value": round(n1 / dt1 / 1e9, 6), "sample": "first 2^23 samples, %.1f s" % dt1},
+            "cpu_model": model, "cost": "N x L complex multiply-adds (N = %d tones)" % spec.ntones}
 
 
 SERVED_POOL = 1 << 24  # samples of the pre-staged device pool per stream configuration
