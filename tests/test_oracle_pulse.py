@@ -222,3 +222,55 @@ def test_bandpass_zero_delay_is_the_phase(oracle_lib):
     rng = np.random.default_rng(3)
     C = rng.standard_normal(64) + 1j * rng.standard_normal(64)
     assert np.array_equal(oracle_lib.bandpass(C, 64_000_000, 1_000_000, 10_000, 0.0), np.angle(C))
+
+
+PULSE_MUTANTS = {
+    "delay_sign": ("delay = (-pos if sideband > 0 else pos) / float(fs)", "delay = (pos if sideband > 0 else -pos) / float(fs)"),
+    "neighbour_swapped": ("if a_p > a_m:\n        s, a_s = 1, a_p", "if a_p > a_m:\n        s, a_s = -1, a_p"),
+    "envelope_period": ("u = math.pi / n", "u = 2.0 * math.pi / n"),
+    "plain_hyperbola": ("d = math.atan2(a_s * math.sin(u), a_0 + a_s * math.cos(u)) / u if s else 0.0",
+                        "d = a_s / (a_0 + a_s) if s else 0.0"),
+    "no_wrap": ("    if pos > n / 2.0:\n        pos -= n\n", ""),
+    "bandpass_sign": ("np.exp(-2j * np.pi * f * delay)", "np.exp(2j * np.pi * f * delay)"),
+    "bandpass_no_offset": ("f = f_offset + f_comb * np.arange", "f = f_comb * np.arange"),
+}
+
+
+def _pulse_variant(old, new):
+    import types
+
+    import oracle.pulse as op
+
+    src = open(op.__file__).read()
+    assert src.count(old) == 1, old
+    mod = types.ModuleType("pulse_variant")
+    exec(compile(src.replace(old, new), "pulse_variant", "exec"), mod.__dict__)
+    return mod
+
+
+def _pulse_pins_hold(m) -> bool:
+    fs, N = 64_000_000, 64
+    P = np.zeros(N, dtype=np.complex128)
+    P[50] = 1.0
+    if m.pulse_peak(P, fs)[2] != 14 / fs:
+        return False
+    for tau in (0.25, 3.7, -5.3):
+        k = np.arange(N)
+        Pc = np.fft.ifft(np.exp(2j * np.pi * k * tau / N))
+        if abs(m.pulse_peak(Pc, N * 1_000_000)[2] * N * 1_000_000 - tau) > 1e-9:
+            return False
+    spec = synth.CombSpec(64_000_000, 1_000_000, 10_000, 2, amp=0.3, t_d=3.7e-9, seed=(9,))
+    C = _closed_form(spec, synth.comb_period_length(spec) * 4)
+    got = m.bandpass(C, spec.fs, 1_000_000, 10_000, spec.t_d)
+    return bool(np.abs(np.angle(np.exp(1j * (got + np.pi / 2)))).max() < 1e-9)
+
+
+def test_pulse_pins_hold_on_oracle():
+    import oracle.pulse as op
+
+    assert _pulse_pins_hold(op)
+
+
+@pytest.mark.parametrize("name", sorted(PULSE_MUTANTS))
+def test_pulse_pins_catch_mutant(name):
+    assert not _pulse_pins_hold(_pulse_variant(*PULSE_MUTANTS[name])), name
