@@ -162,7 +162,9 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
     p->target_blocks = env_int("PCAL_TARGET_BLOCKS", 0);
     p->target_from_env = p->target_blocks > 0;
     if (!p->target_from_env)
-        p->target_blocks = (method != PCAL_METHOD_PERIOD_FOLD && nbits == 8) ? kRotTargetBlocks8 : kTargetBlocks;
+        p->target_blocks = (method == PCAL_METHOD_PERIOD_FOLD || nbits == 2) ? kTargetBlocks
+                           : method == PCAL_METHOD_LUT                    ? kLutTargetBlocks8
+                                                                          : kRotTargetBlocks8;
     p->max_blocks = std::max(p->geom.col_tiles, p->target_blocks) + p->geom.col_tiles;
     return PCAL_OK;
 }

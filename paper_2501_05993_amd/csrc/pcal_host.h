@@ -54,12 +54,15 @@ constexpr int64_t kMaxTableRows = int64_t(1) << 20;   // u table entries
 constexpr int64_t kMaxLutPeriod = int64_t(1) << 24;   // rotator table entries (table method)
 constexpr int kRotLanes = 16;                          // samples per thread-row, per-sample forms
 // Workgroups per launch before the period fold's persistent grid replaces it
-// (PCAL_TARGET_BLOCKS overrides).  The 8-bit per-sample forms run best with
-// fewer (256 MiB launches, N = 64-1024: the recurrence at 512 workgroups
-// 55-62 % of the HBM peak against 42-51 % at 1024, the table 35-37 % against
-// 30-34 %); at 2 bits 512-2048 measure alike.
+// (PCAL_TARGET_BLOCKS overrides).  The 8-bit per-sample forms (256-thread
+// workgroups) run best with fewer (256 MiB launches, N = 64 and 1024): the
+// recurrences at 512 workgroups reach 56-62 % of the HBM peak against 42-51 %
+// at 1024 and 42-47 % at 768; the table, whose row reads want more waves in
+// flight, 39-40 % at 768 against 35-36 % at 512 and 30-34 % at 1024.  At
+// 2 bits 512-2048 measure alike.
 constexpr int kTargetBlocks = 1024;
 constexpr int kRotTargetBlocks8 = 512;
+constexpr int kLutTargetBlocks8 = 768;
 constexpr int64_t kAutoFoldPeriod = int64_t(1) << 22;  // longest fold period AUTO folds
 
 int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int method, int prec, Plan *p,

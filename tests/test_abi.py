@@ -79,15 +79,15 @@ def test_unsupported_forms_reported():
 
 def test_per_sample_forms_share_one_plan():
     """The recurrence forms (direct-form resonator, coupled form) and the table form plan the same rows; the
-    8-bit per-sample forms default to 512 workgroups per launch, the 2-bit ones to 1024; unknown methods
-    are rejected."""
+    8-bit per-sample forms default to 768 (table) or 512 (recurrences) workgroups per launch, the 2-bit
+    ones to 1024; unknown methods are rejected."""
     for nbits in (2, 8):
         plans = [pcal.plan(1_024_000_000, 1_000_000, 510_000, nbits, method=m)
                  for m in (pcal.METHOD_LUT, pcal.METHOD_OSC, pcal.METHOD_CFO)]
         assert [p["method"] for p in plans] == [pcal.METHOD_LUT, pcal.METHOD_OSC, pcal.METHOD_CFO]
-        keys = [k for k in plans[0] if k != "method"]
+        keys = [k for k in plans[0] if k not in ("method", "target_blocks")]
         assert all(p[k] == plans[0][k] for p in plans for k in keys)
-        assert plans[0]["target_blocks"] == (512 if nbits == 8 else 1024)
+        assert [p["target_blocks"] for p in plans] == ([768, 512, 512] if nbits == 8 else [1024] * 3)
     with pytest.raises(pcal.PcalError) as e:
         pcal.plan(64_000_000, 1_000_000, 10_000, 2, method=5)
     assert e.value.code == pcal.EINVAL
