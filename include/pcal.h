@@ -58,13 +58,18 @@ enum pcal_status {
  *      moved after the accumulation (Section 4.1 proposes accumulating over a
  *      rotator period and folding into the bins after the sample loop).
  *  LUT: multiply every sample by a precomputed rotator table value (Eq. 4
- *      table, Section 4.1), accumulate in FP32.
+ *      table, Section 4.1), accumulate in the precision form's arithmetic.
  *  OSC: multiply every sample by a recurrence sinewave generator (Eq. 6-7
- *      direct-form resonator), re-seeded exactly at intervals.
+ *      direct-form resonator), re-seeded exactly at intervals.  The
+ *      generator steps once per row of samples by d = w_offset * (row length);
+ *      the row length is chosen so that d stays away from 0 and pi, where the
+ *      rounded coefficient 2 cos d would detune it (Section 2.2).
  *  CFO: as OSC with the coupled-form oscillator of Section 2.2 (the rotator
  *      times exp(-j d) per step, d the rotator advance of one step), for
  *      comparison with the direct-form resonator.
- *  AUTO: PERIOD_FOLD when the joint period fits, else OSC. */
+ *  AUTO: PERIOD_FOLD when the joint period fits (at most 2^22 samples), else
+ *      OSC; CFO instead of OSC in the FP32-state forms (MIXED, F32) when no
+ *      row length keeps |sin d| >= 0.1. */
 enum pcal_method {
     PCAL_METHOD_AUTO = 0,
     PCAL_METHOD_PERIOD_FOLD = 1,
@@ -76,10 +81,16 @@ enum pcal_method {
 /* Arithmetic of the rotation and the per-block fold.  The cross-block
  * reduction, the N-point DFT and the delay fit always run in FP64 except in
  * PCAL_PREC_F32, the all-FP32 comparison form.
- *  F64:   rotator table in FP64, products and per-block sums in FP64.
- *  MIXED: rotator table in FP16, FP32 products, Kahan-compensated FP32
- *         per-block sums; FP64 from the cross-block reduction on.
- *  F32:   FP32 table, plain FP32 sums, FP32 reduction and DFT. */
+ *  F64:   rotator in FP64 (table entries, recurrence state), products and
+ *         per-block sums in FP64.  The period fold sums integer samples
+ *         exactly and rotates each period position once with an FP64 entry.
+ *  MIXED: rotator table entries as two FP16 terms, the rounded value and its
+ *         rounded residual (about 22 bits together; the recurrences keep FP32
+ *         state), FP32 products, Kahan-compensated FP32 per-block sums; FP64
+ *         from the cross-block reduction on, with the table's known mean
+ *         gain divided out.
+ *  F32:   FP32 table or recurrence state, plain FP32 sums, FP32 reduction
+ *         and DFT. */
 enum pcal_precision { PCAL_PREC_F64 = 0, PCAL_PREC_MIXED = 1, PCAL_PREC_F32 = 2 };
 
 /* Create a handle for one stream.

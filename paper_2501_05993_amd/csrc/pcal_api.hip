@@ -141,7 +141,8 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
     const bool osc_ok = fs < (int64_t(1) << 32);
     // The fold pays off while a launch spans many fold periods; for long periods
     // (offsets sharing few factors with fs, Section 6) AUTO takes the recurrence.
-    if (method == PCAL_METHOD_AUTO)
+    const bool auto_method = method == PCAL_METHOD_AUTO;
+    if (auto_method)
         method = (fold_ok && p->Sp <= kAutoFoldPeriod) ? PCAL_METHOD_PERIOD_FOLD : PCAL_METHOD_OSC;
     if (method == PCAL_METHOD_PERIOD_FOLD && !fold_ok) return PCAL_ENOTSUP;
     if (method == PCAL_METHOD_LUT && (p->R > kMaxLutPeriod || !osc_ok)) return PCAL_ENOTSUP;
@@ -154,6 +155,43 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
         // rows of a multiple of lcm(N, 16) samples: every lane keeps its bin
         const int64_t per = p->N / gcd64(p->N, kRotLanes) * kRotLanes;
         p->geom = plan_geom(per, kRotLanes, INT64_MAX, kMaxRotThreads, force_threads, 256, 0);
+        if (method == PCAL_METHOD_OSC && !force_threads && env_int("PCAL_FOLD_THREADS", 0) == 0) {
+            // The resonator steps once per row by d = w_o * (samples per row) with
+            // the coefficient 2 cos d rounded to the form's precision; the
+            // frequency that rounding leaves is off by about delta / (2 |sin d|),
+            // so a d near 0 or pi makes the recurrence drift (Section 2.2 notes the
+            // resonator's loss of accuracy at low steps).  Rows hold k periods of
+            // lcm(N, 16) samples, k the workgroup's sub-rows: among the workgroup
+            // sizes that waste no more lanes, take the k whose d is farthest from
+            // 0 and pi (|sin d| >= 0.2 counts as far enough: the FP32 coefficient
+            // then moves the frequency by at most 1.5e-7 rad per row, 1e-5 rad over
+            // a 64-row run between exact re-seeds), then the smallest workgroup.
+            const FoldGeom &g0 = p->geom;
+            int best_t = g0.threads;
+            double best_s = -1.0, best_eff = -1.0;
+            for (int t = 256; t <= kMaxRotThreads; t += 64) {
+                const int64_t k = t / g0.tile_vecs;
+                if (k < 1) continue;
+                const double eff = static_cast<double>(k * g0.tile_vecs) / t;
+                const int64_t di = static_cast<int64_t>((static_cast<unsigned __int128>(fo) * (k * per)) % fs);
+                double c, sn;
+                phasor(di, fs, &c, &sn);
+                const double sc = std::min(std::fabs(sn), 0.2);
+                if (sc > best_s + 1e-12 || (sc > best_s - 1e-12 && eff > best_eff + 1e-9)) {
+                    best_s = sc;
+                    best_eff = eff;
+                    best_t = t;
+                }
+            }
+            p->geom.threads = best_t;
+            p->geom.row_vecs = static_cast<int>((best_t / g0.tile_vecs) * g0.period_vecs);
+            p->osc_sin = best_s;
+            // Even the best row length leaves d near 0 or pi: AUTO takes the
+            // coupled form instead, whose rounding does not depend on d, unless
+            // the recurrence runs in FP64 (its coefficient error is 2^-29 of FP32's).
+            if (auto_method && best_s < 0.1 && prec != PCAL_PREC_F64) method = PCAL_METHOD_CFO;
+            p->method = method;
+        }
     }
     {
         const int sp = env_int("PCAL_SYNC_PAIRS", kSyncPairs);  // power of two or 0
@@ -220,6 +258,25 @@ pcal_launch_t plan_launch(const Plan &p, uint64_t addr, int64_t n_before, int64_
     return L;
 }
 
+// Device bytes a handle of this plan allocates (build() below), computed
+// without allocating: what admission under a memory budget compares.
+int64_t plan_device_bytes(const Plan &p) {
+    const bool fold = p.method == PCAL_METHOD_PERIOD_FOLD;
+    const int64_t N = p.N, M = fold ? p.M : 1, NS = 2 * kAccSlots * N;
+    auto b = [](int64_t size, int64_t count) { return size * (count ? count : 1); };
+    int64_t bytes = b(16, M) + b(8, M) + b(4, 2 * M)          // u64, u32, u16 (two terms)
+                    + b(16, N) + b(16, N)                     // v, tw
+                    + b(16, NS) + b(8, NS) + b(8, NS)         // acc, acc_int, accf (two banks)
+                    + b(4, 2) + b(8, 2 * (4 * N + 1))         // counters, out
+                    + b(8, N) + b(8, 3 * N + 4) + b(8, N);    // phases, pulse, pulse_int
+    if (!fold) {
+        bytes += b(16, kRotLanes);                            // lane factors
+        if (p.method == PCAL_METHOD_LUT)
+            bytes += p.prec == PCAL_PREC_F64 ? b(16, p.R) : p.prec == PCAL_PREC_MIXED ? b(4, 2 * p.R) : b(8, p.R);
+    }
+    return bytes;
+}
+
 void fill_info(const Plan &p, pcal_info_t *info) {
     memset(info, 0, sizeof(*info));
     info->ntones = p.N;
@@ -235,6 +292,7 @@ void fill_info(const Plan &p, pcal_info_t *info) {
     info->period_vectors = p.geom.period_vecs;
     info->tile_vectors = p.geom.tile_vecs;
     info->target_blocks = p.target_blocks;
+    info->device_bytes = plan_device_bytes(p);
 }
 
 
@@ -252,7 +310,7 @@ int dalloc(pcal_ctx *h, T **p, size_t count) {
 
 void release(pcal_ctx *h) {
     void *ptrs[] = {h->u64, h->u32, h->u16, h->v, h->tw, h->acc_mem, h->acc_int_mem, h->accf_mem, h->counters,
-                    h->out, h->phases, h->pulse, h->pulse_int, h->rot32, h->rot16, h->w};
+                    h->out, h->phases, h->pulse, h->pulse_int, h->rot64, h->rot32, h->rot16, h->w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->host_out) (void)hipHostFree(h->host_out);
@@ -341,26 +399,21 @@ int build(pcal_ctx *h) {
         const int64_t di = static_cast<int64_t>((static_cast<unsigned __int128>(p.fo) * dn) % p.fs);
         phasor(di, p.fs, &br, &bi);
         h->back = make_double2(br, -bi);
-        h->c2 = static_cast<float>(2.0 * br);
+        h->c2 = 2.0 * br;
         if ((rc = dalloc(h, &h->w, kRotLanes))) return rc;
         PCAL_HIP(hipMemcpy(h->w, w.data(), sizeof(double2) * kRotLanes, hipMemcpyHostToDevice));
         if (p.method == PCAL_METHOD_LUT) {
+            // One rotator period from exact integer phase indices (Eq. 4-5), in
+            // FP64, then in the form's storage: FP64, two FP16 terms (hi = the
+            // rounded entry, lo = the rounded rest; hi + lo is exact in FP32,
+            // about 22 bits) or FP32.
             const int64_t R = p.R;
             std::vector<double2> t(R);
-            std::vector<float2> tf(R);
-            std::vector<__half2> th(R);
             int64_t idx = 0;
             for (int64_t n = 0; n < R; ++n) {
                 phasor(idx, p.fs, &t[n].x, &t[n].y);
-                tf[n] = make_float2(static_cast<float>(t[n].x), static_cast<float>(t[n].y));
-                th[n] = to_half2(t[n]);
                 idx += p.fo;
                 if (idx >= p.fs) idx -= p.fs;
-            }
-            if (p.prec == PCAL_PREC_MIXED) {
-                std::vector<double2> tr(R);
-                for (int64_t n = 0; n < R; ++n) tr[n] = from_half2(th[n]);
-                table_gain(t, tr, &h->gain_re, &h->gain_im);
             }
             // de-interleaved by D (the largest power of two <= 16 dividing R):
             // entry n at (n mod D) * (R / D) + n / D, so that the lookups of
@@ -369,16 +422,34 @@ int build(pcal_ctx *h) {
             while (shift < 4 && R % (int64_t(2) << shift) == 0) ++shift;
             h->lut_shift = shift;
             h->lut_rows = R >> shift;
-            std::vector<float2> tfd(R);
-            std::vector<__half2> thd(R);
-            for (int64_t n = 0; n < R; ++n) {
-                const int64_t k = (n & ((int64_t(1) << shift) - 1)) * h->lut_rows + (n >> shift);
-                tfd[k] = tf[n];
-                thd[k] = th[n];
+            auto slot = [&](int64_t n) { return (n & ((int64_t(1) << shift) - 1)) * h->lut_rows + (n >> shift); };
+            if (p.prec == PCAL_PREC_F64) {
+                std::vector<double2> td(R);
+                for (int64_t n = 0; n < R; ++n) td[slot(n)] = t[n];
+                if ((rc = dalloc(h, &h->rot64, R))) return rc;
+                PCAL_HIP(hipMemcpy(h->rot64, td.data(), sizeof(double2) * R, hipMemcpyHostToDevice));
+            } else if (p.prec == PCAL_PREC_MIXED) {
+                std::vector<__half2> thd(2 * R);
+                std::vector<double2> tr(R);
+                for (int64_t n = 0; n < R; ++n) {
+                    const __half2 hi = to_half2(t[n]);
+                    const double2 h0 = from_half2(hi);
+                    const __half2 lo = to_half2(make_double2(t[n].x - h0.x, t[n].y - h0.y));
+                    const double2 l0 = from_half2(lo);
+                    tr[n] = make_double2(h0.x + l0.x, h0.y + l0.y);
+                    thd[2 * slot(n)] = hi;
+                    thd[2 * slot(n) + 1] = lo;
+                }
+                table_gain(t, tr, &h->gain_re, &h->gain_im);
+                if ((rc = dalloc(h, &h->rot16, 2 * R))) return rc;
+                PCAL_HIP(hipMemcpy(h->rot16, thd.data(), sizeof(__half2) * 2 * R, hipMemcpyHostToDevice));
+            } else {
+                std::vector<float2> tfd(R);
+                for (int64_t n = 0; n < R; ++n)
+                    tfd[slot(n)] = make_float2(static_cast<float>(t[n].x), static_cast<float>(t[n].y));
+                if ((rc = dalloc(h, &h->rot32, R))) return rc;
+                PCAL_HIP(hipMemcpy(h->rot32, tfd.data(), sizeof(float2) * R, hipMemcpyHostToDevice));
             }
-            if ((rc = dalloc(h, &h->rot32, R)) || (rc = dalloc(h, &h->rot16, R))) return rc;
-            PCAL_HIP(hipMemcpy(h->rot32, tfd.data(), sizeof(float2) * R, hipMemcpyHostToDevice));
-            PCAL_HIP(hipMemcpy(h->rot16, thd.data(), sizeof(__half2) * R, hipMemcpyHostToDevice));
         }
     }
     if ((rc = dalloc(h, &h->u64, M)) || (rc = dalloc(h, &h->u32, M)) || (rc = dalloc(h, &h->u16, 2 * M)) ||
@@ -705,8 +776,9 @@ int pcal_extract_timed(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_str
         a.fs = p.fs;
         a.fo = p.fo;
         a.R = p.R;
-        a.rot32 = h->rot32;
+        a.rot64 = h->rot64;
         a.rot16 = h->rot16;
+        a.rot32 = h->rot32;
         a.lut_shift = h->lut_shift;
         a.lut_rows = h->lut_rows;
         a.w = h->w;

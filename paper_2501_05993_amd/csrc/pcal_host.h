@@ -35,6 +35,7 @@ struct Plan {
     int sync_pairs;   // fold walk: workgroup barrier every sync_pairs pairs of groups (0: none)
     bool target_from_env;  // PCAL_TARGET_BLOCKS set: keep it on every device
     int max_blocks;
+    double osc_sin = 1.0;  // resonator: |sin d| of the row step d (capped at 0.2 by the row choice)
 };
 
 constexpr int kSyncPairs = 1;  // fold walk: a workgroup barrier after every pair of groups (PCAL_SYNC_PAIRS)
@@ -71,6 +72,8 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
 pcal_launch_t plan_launch(const Plan &p, uint64_t addr, int64_t n_before, int64_t nsamples,
                           int target_blocks = 0);
 void fill_info(const Plan &p, pcal_info_t *info);
+// Device bytes a handle of this plan allocates (no allocation made).
+int64_t plan_device_bytes(const Plan &p);
 
 }  // namespace host
 }  // namespace pcal
@@ -106,11 +109,12 @@ struct pcal_ctx {
     unsigned *counters = nullptr;  // [0] finalize of bank 0's pending form / plain, [1] bank 1
     double *out = nullptr;         // device results [2][4N + 1]
     double *host_out = nullptr;    // pinned copy
-    float2 *rot32 = nullptr;       // rotator table [R] (table method)
-    __half2 *rot16 = nullptr;
+    double2 *rot64 = nullptr;      // rotator table of the table method, in the precision form's
+    __half2 *rot16 = nullptr;      // arithmetic (RotArgs): only the one the form reads is allocated
+    float2 *rot32 = nullptr;
     double2 *w = nullptr;          // [16] lane factors (per-sample forms)
     double2 back = {1.0, 0.0};     // exp(+j w_o * samples per row)
-    float c2 = 2.0f;               // 2 cos(w_o * samples per row)
+    double c2 = 2.0;               // 2 cos(w_o * samples per row)
     double gain_re = 1.0, gain_im = 0.0;  // 1 / (1 + gamma) of the FP16 table (mixed form)
     int64_t n_total = 0;
     int64_t n_integ = 0;

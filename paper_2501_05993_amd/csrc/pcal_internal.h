@@ -160,8 +160,13 @@ struct RotArgs {
     int N, nbits, prec, method;
     int64_t g0;              // global index of the first full-vector sample
     int64_t fs, fo, R;       // Hz, Hz, rotator period (Eq. 4)
-    const float2 *rot32;     // rotator table [R] in FP32 (table method), de-interleaved (below)
-    const __half2 *rot16;    // the same in FP16 (mixed form)
+    // Rotator table of one period (table method), in the handle's precision form:
+    // FP64 entries (F64), two FP16 terms per entry, the rounded value and its
+    // rounded residual, stored as neighbours (MIXED), or FP32 entries (F32).
+    // Entries de-interleaved as described below.
+    const double2 *rot64;    // [R]
+    const __half2 *rot16;    // [2R]: entry k = rot16[2k] + rot16[2k + 1]
+    const float2 *rot32;     // [R]
     // Entry n of the table is stored at (n mod D) * (R / D) + n / D, D = 2^lut_shift
     // the largest power of two <= 16 dividing R: the lanes of a wave look up
     // entries 16 apart, which this places next to each other.
@@ -169,7 +174,7 @@ struct RotArgs {
     int64_t lut_rows;        // R / D
     const double2 *w;        // [16] lane factors exp(-j w_o i)
     double2 back;            // exp(+j w_o * samples per row): one row back, FP64
-    float c2;                // 2 cos(w_o * samples per row), recurrence coefficient
+    double c2;               // 2 cos(w_o * samples per row), recurrence coefficient (FP32 forms round it)
     const uint8_t *head;
     int head_bytes;
     int64_t head_n;          // global index of the first head sample

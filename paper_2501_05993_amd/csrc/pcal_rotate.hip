@@ -13,16 +13,39 @@
 // lane i in row r is n = n_r + i with n_r the row's first sample of the
 // thread, and exp(-j w_o n) = exp(-j w_o n_r) exp(-j w_o i): the row factor
 // z_r is produced once per row (table read or one recurrence step), every
-// sample costs two FP32 FMAs against it, and the fixed lane factor
-// exp(-j w_o i) is applied once per lane at the end, in FP64.
+// sample costs two FMAs against it, and the fixed lane factor exp(-j w_o i)
+// is applied once per lane at the end, in FP64.
+//
+// Arithmetic by precision form.  F64: FP64 table entries or FP64 recurrence
+// state, FP64 products, run sums and totals.  MIXED: table entries as two
+// FP16 terms summed in FP32 (or FP32 recurrence state), FP32 products and run
+// sums, Kahan-compensated FP32 totals.  F32: FP32 throughout up to the lane
+// totals.  Workgroup bins and the cross-workgroup sums are FP64 except in F32.
+#include <type_traits>
+
 #include "pcal_internal.h"
 
 namespace pcal {
 namespace {
 
 constexpr int kLanes = 16;   // samples per thread and row
-constexpr int kRun = 64;     // rows per run: run sums in FP32, then folded into totals
-constexpr int kUnroll = 8;   // rows loaded ahead
+constexpr int kRun = 64;     // rows per run: run sums, then folded into the lane totals
+// rows loaded ahead: 8 in the FP32 forms, 4 in the FP64 form (twice the
+// registers per lane sum)
+template <int PREC>
+constexpr int unroll_of() { return PREC == 0 ? 4 : 8; }
+
+// Arithmetic type of the products and run sums of a precision form.
+template <int PREC>
+using real_t = typename std::conditional<PREC == 0, double, float>::type;
+
+__device__ __forceinline__ float mad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double mad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <class T>
+struct cplx {
+    T x, y;
+};
 
 __device__ __forceinline__ int edge_level(const uint8_t *p, int nbits, int i) {
     if (nbits == 2) return 2 * ((p[i >> 2] >> (2 * (i & 3))) & 3) - 3;
@@ -42,7 +65,7 @@ __device__ __forceinline__ double2 exact_rotator(int64_t n, int64_t fs, int64_t 
 
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
-// The 16 sample values of one thread-row as floats: biased bytes x + 128
+// The 16 sample values of one thread-row: biased bytes x + 128
 // (8-bit) or offset-binary codes c (2-bit), lane i = sample i.
 template <int NBITS>
 struct RowVec;
@@ -54,9 +77,10 @@ struct RowVec<8> {
         const u32x4_t x = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(base) + idx);
         v = make_uint4(x.x ^ 0x80808080u, x.y ^ 0x80808080u, x.z ^ 0x80808080u, x.w ^ 0x80808080u);
     }
-    __device__ __forceinline__ float get(int i) const {
+    template <class T>
+    __device__ __forceinline__ T get(int i) const {
         const uint32_t w = i < 4 ? v.x : i < 8 ? v.y : i < 12 ? v.z : v.w;
-        return static_cast<float>((w >> (8 * (i & 3))) & 0xFFu);
+        return static_cast<T>((w >> (8 * (i & 3))) & 0xFFu);
     }
 };
 
@@ -68,8 +92,9 @@ struct RowVec<2> {
 #pragma unroll
         for (int j = 0; j < 4; ++j) q[j] = (d >> (2 * j)) & 0x03030303u;
     }
-    __device__ __forceinline__ float get(int i) const {
-        return static_cast<float>((q[i & 3] >> (8 * (i >> 2))) & 0xFFu);
+    template <class T>
+    __device__ __forceinline__ T get(int i) const {
+        return static_cast<T>((q[i & 3] >> (8 * (i >> 2))) & 0xFFu);
     }
 };
 
@@ -81,7 +106,7 @@ struct LaneTot {
 #pragma unroll
         for (int k = 0; k < kLanes; ++k) r[k] = i[k] = 0.0;
     }
-    __device__ __forceinline__ void add(int k, float a, float b) {
+    __device__ __forceinline__ void add(int k, double a, double b) {
         r[k] += a;
         i[k] += b;
     }
@@ -125,36 +150,48 @@ struct LaneTot<2> {
 };
 
 // Row rotator source: table (METHOD 2), direct-form resonator (METHOD 3) or
-// coupled-form oscillator (METHOD 4).
+// coupled-form oscillator (METHOD 4), in the arithmetic of the precision form.
 template <int METHOD, int PREC>
 struct RowRot {
+    using T = real_t<PREC>;
     // table state
     int64_t idx = 0, step = 0, R = 1;
     // recurrence state: the DFR runs the same two-term recurrence on the real
     // and imaginary parts (c2 = 2 cos d); the CFO multiplies the rotator by
     // m = exp(-j d) each row (d = w_o times the samples per row)
-    float zr = 0.f, zi = 0.f, pr = 0.f, pi = 0.f, c2 = 0.f, mr = 0.f, mi = 0.f;
+    T zr = 0, zi = 0, pr = 0, pi = 0, c2 = 0, mr = 0, mi = 0;
     int64_t n = 0, dn = 0;  // global index of the row's first lane sample, row stride in samples
 
-    __device__ __forceinline__ float2 table(const RotArgs &a, int64_t n) const {
+    __device__ __forceinline__ cplx<T> table(const RotArgs &a, int64_t n) const {
         const int64_t k = (n & ((int64_t(1) << a.lut_shift) - 1)) * a.lut_rows + (n >> a.lut_shift);
-        if constexpr (PREC == 1)
-            return __half22float2(a.rot16[k]);
-        else
-            return a.rot32[k];
+        if constexpr (PREC == 0) {
+            const double2 e = a.rot64[k];
+            return {e.x, e.y};
+        } else if constexpr (PREC == 1) {
+            // two FP16 terms in one 8-byte load; their FP32 sum is exact
+            const uint2 w = reinterpret_cast<const uint2 *>(a.rot16)[k];
+            __half2 hi, lo;
+            __builtin_memcpy(&hi, &w.x, 4);
+            __builtin_memcpy(&lo, &w.y, 4);
+            const float2 h = __half22float2(hi), l = __half22float2(lo);
+            return {h.x + l.x, h.y + l.y};
+        } else {
+            const float2 e = a.rot32[k];
+            return {e.x, e.y};
+        }
     }
     // exact seed at global sample n (recurrence): z(n) and z(n - dn) in FP64, rounded once
     __device__ __forceinline__ void seed(const RotArgs &a) {
         const double2 z = exact_rotator(n, a.fs, a.fo);
         const double2 zp = make_double2(z.x * a.back.x - z.y * a.back.y, z.x * a.back.y + z.y * a.back.x);
-        zr = static_cast<float>(z.x);
-        zi = static_cast<float>(z.y);
-        pr = static_cast<float>(zp.x);
-        pi = static_cast<float>(zp.y);
+        zr = static_cast<T>(z.x);
+        zi = static_cast<T>(z.y);
+        pr = static_cast<T>(zp.x);
+        pi = static_cast<T>(zp.y);
     }
     // rotators of the next U rows, then move U rows on
     template <int U>
-    __device__ __forceinline__ void fetch(const RotArgs &a, float2 (&z)[U]) {
+    __device__ __forceinline__ void fetch(const RotArgs &a, cplx<T> (&z)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if constexpr (METHOD == 2) {
@@ -162,17 +199,17 @@ struct RowRot {
                 idx += step;
                 if (idx >= R) idx -= R;
             } else if constexpr (METHOD == 3) {
-                z[u] = make_float2(zr, zi);
+                z[u] = {zr, zi};
                 // Eq. 7: one FMA per component and row
-                const float nr = fmaf(c2, zr, -pr), ni = fmaf(c2, zi, -pi);
+                const T nr = mad(c2, zr, -pr), ni = mad(c2, zi, -pi);
                 pr = zr;
                 pi = zi;
                 zr = nr;
                 zi = ni;
             } else {
-                z[u] = make_float2(zr, zi);
+                z[u] = {zr, zi};
                 // coupled form: a complex multiply by exp(-j d) per row
-                const float nr = fmaf(zr, mr, -zi * mi), ni = fmaf(zr, mi, zi * mr);
+                const T nr = mad(zr, mr, -zi * mi), ni = mad(zr, mi, zi * mr);
                 zr = nr;
                 zi = ni;
             }
@@ -201,6 +238,7 @@ __global__ void __launch_bounds__(kMaxRotThreads) rot_kernel(RotArgs a) {
         const int64_t rfull = a.nvec / stride;
         const bool last_ok = colr < a.nvec - rfull * stride;
         const int64_t rend = r1 < rfull ? r1 : (r1 > rfull && last_ok ? r1 : rfull);
+        using T = real_t<PREC>;
         RowRot<METHOD, PREC> rot;
         rot.n = a.g0 + (r0 * stride + colr) * kLanes;
         rot.dn = stride * kLanes;
@@ -209,9 +247,9 @@ __global__ void __launch_bounds__(kMaxRotThreads) rot_kernel(RotArgs a) {
             rot.step = (stride * kLanes) % a.R;
             rot.idx = rot.n % a.R;
         } else {
-            rot.c2 = a.c2;
-            rot.mr = static_cast<float>(a.back.x);   // exp(-j d) = conj(exp(+j d))
-            rot.mi = static_cast<float>(-a.back.y);
+            rot.c2 = static_cast<T>(a.c2);
+            rot.mr = static_cast<T>(a.back.x);   // exp(-j d) = conj(exp(+j d))
+            rot.mi = static_cast<T>(-a.back.y);
             rot.seed(a);
         }
         LaneTot<PREC> tot;
@@ -219,12 +257,13 @@ __global__ void __launch_bounds__(kMaxRotThreads) rot_kernel(RotArgs a) {
         int64_t r = r0;
         while (r < rend) {
             const int64_t run_end = (r + kRun) < rend ? (r + kRun) : rend;
-            float ar[kLanes], ai[kLanes];
+            T ar[kLanes], ai[kLanes];
 #pragma unroll
-            for (int k = 0; k < kLanes; ++k) ar[k] = ai[k] = 0.f;
-            float sr = 0.f, si = 0.f;  // sum of the row rotators of the run (bias term)
+            for (int k = 0; k < kLanes; ++k) ar[k] = ai[k] = T(0);
+            T sr = 0, si = 0;  // sum of the row rotators of the run (bias term)
+            constexpr int kUnroll = unroll_of<PREC>();
             for (; r + kUnroll <= run_end; r += kUnroll) {
-                float2 z[kUnroll];
+                cplx<T> z[kUnroll];
                 rot.fetch(a, z);  // table reads are issued with the sample loads
                 RowVec<NBITS> x[kUnroll];
 #pragma unroll
@@ -233,24 +272,24 @@ __global__ void __launch_bounds__(kMaxRotThreads) rot_kernel(RotArgs a) {
                 for (int u = 0; u < kUnroll; ++u) {
 #pragma unroll
                     for (int k = 0; k < kLanes; ++k) {
-                        const float xv = x[u].get(k);
-                        ar[k] = fmaf(xv, z[u].x, ar[k]);
-                        ai[k] = fmaf(xv, z[u].y, ai[k]);
+                        const T xv = x[u].template get<T>(k);
+                        ar[k] = mad(xv, z[u].x, ar[k]);
+                        ai[k] = mad(xv, z[u].y, ai[k]);
                     }
                     sr += z[u].x;
                     si += z[u].y;
                 }
             }
             for (; r < run_end; ++r) {
-                float2 z[1];
+                cplx<T> z[1];
                 rot.fetch(a, z);
                 RowVec<NBITS> x;
                 x.load(a.data, r * stride + colr);
 #pragma unroll
                 for (int k = 0; k < kLanes; ++k) {
-                    const float xv = x.get(k);
-                    ar[k] = fmaf(xv, z[0].x, ar[k]);
-                    ai[k] = fmaf(xv, z[0].y, ai[k]);
+                    const T xv = x.template get<T>(k);
+                    ar[k] = mad(xv, z[0].x, ar[k]);
+                    ai[k] = mad(xv, z[0].y, ai[k]);
                 }
                 sr += z[0].x;
                 si += z[0].y;
@@ -259,9 +298,9 @@ __global__ void __launch_bounds__(kMaxRotThreads) rot_kernel(RotArgs a) {
 #pragma unroll
             for (int k = 0; k < kLanes; ++k) {
                 if constexpr (NBITS == 8)
-                    tot.add(k, ar[k] - 128.f * sr, ai[k] - 128.f * si);
+                    tot.add(k, ar[k] - T(128) * sr, ai[k] - T(128) * si);
                 else
-                    tot.add(k, 2.f * ar[k] - 3.f * sr, 2.f * ai[k] - 3.f * si);
+                    tot.add(k, T(2) * ar[k] - T(3) * sr, T(2) * ai[k] - T(3) * si);
             }
             if constexpr (METHOD != 2) rot.seed(a);  // exact restart of the recurrence
         }

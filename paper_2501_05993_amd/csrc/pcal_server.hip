@@ -58,6 +58,7 @@ struct pcal_server_ctx {
     pcal_batch_t batch = nullptr;
     int64_t budget = 0;
     int64_t used = 0;
+    int prec = PCAL_PREC_F64;
     int max_streams = 0;
     std::vector<SrvStream> streams;
     std::deque<Inflight> inflight;
@@ -102,6 +103,7 @@ int pcal_server_create(int64_t mem_budget_bytes, int max_streams, int precision,
         return rc;
     }
     s->budget = mem_budget_bytes;
+    s->prec = precision;
     s->max_streams = max_streams;
     s->streams.resize(max_streams);
     *out = s;
@@ -121,18 +123,19 @@ int pcal_server_open(pcal_server_t s, int64_t fs_hz, int64_t f_comb_hz, int64_t 
             break;
         }
     if (slot < 0) return PCAL_EAGAIN;
+    // admission, before anything is allocated: the device memory of the
+    // stream's tables and accumulators, from its plan, must fit the budget left
+    Plan plan{};
+    int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_PERIOD_FOLD, s->prec, &plan);
+    if (rc) return rc;
+    if (s->used + plan_device_bytes(plan) > s->budget) return PCAL_EAGAIN;
     int bid = -1;
-    int rc = pcal_batch_add(s->batch, fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, &bid);
+    rc = pcal_batch_add(s->batch, fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, &bid);
     if (rc) return rc;
     pcal_t h = nullptr;
     if ((rc = pcal_batch_handle(s->batch, bid, &h))) return rc;
     const int N = static_cast<int>(h->plan.N);
     const int64_t slots_bytes = static_cast<int64_t>(sizeof(double)) * kResultDepth * (4 * N + 1);
-    // admission: the stream's tables and accumulators must fit the budget left
-    if (s->used + h->device_bytes > s->budget) {
-        (void)batch_release(s->batch, bid);
-        return PCAL_EAGAIN;
-    }
     SrvStream &st = s->streams[slot];
     {
         hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&st.slots), static_cast<size_t>(slots_bytes),

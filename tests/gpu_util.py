@@ -43,3 +43,29 @@ def assert_spectra(got, want, amp_rtol=AMP_RTOL, phase_atol=PHASE_ATOL, rel_floo
     assert p <= phase_atol, (what, p)
     assert w <= rel_floor, (what, w)
     return a, p
+
+
+def rounded_tables(fs, fo, N, M, prec):
+    """The rotator factors a reduced-precision period-fold form multiplies by, rounded here with numpy.
+
+    The fold rotates period position q = m N + b by u[m] v[b], u[m] = exp(-j w_o N m),
+    v[b] = exp(-j w_o b) (Eq. 3 with the phase index reduced exactly).  Returns
+    (u, v, gain) for oracle.correlate_rotator: MIXED stores each u[m] as two FP16
+    terms (the rounded value and its rounded residual) and divides the table's
+    mean gain 1 + gamma out, v exact; F32 rounds u and v to FP32, gain 1.
+    """
+    m = np.arange(M, dtype=np.int64)
+    b = np.arange(N, dtype=np.int64)
+    u = np.exp(-2j * np.pi * ((fo * N * m) % fs) / fs)
+    v = np.exp(-2j * np.pi * ((fo * b) % fs) / fs)
+    if prec == 1:
+        def f16(z):
+            return z.real.astype(np.float16).astype(float) + 1j * z.imag.astype(np.float16).astype(float)
+        hi = f16(u)
+        uh = hi + f16(u - hi)
+        gamma = np.mean(np.conj(u) * (uh - u))
+        return uh, v, 1.0 / (1.0 + gamma)
+
+    def f32(z):
+        return z.real.astype(np.float32).astype(float) + 1j * z.imag.astype(np.float32).astype(float)
+    return f32(u), f32(v), 1.0

@@ -78,16 +78,32 @@ def test_unsupported_forms_reported():
 
 
 def test_per_sample_forms_share_one_plan():
-    """The recurrence forms (direct-form resonator, coupled form) and the table form plan the same rows; the
+    """At 510 kHz (a resonator row step with |sin d| >= 0.2 at the smallest workgroup) the recurrence forms
+    (direct-form resonator, coupled form) and the table form plan the same rows; the
     8-bit per-sample forms default to 768 (table) or 512 (recurrences) workgroups per launch, the 2-bit
     ones to 1024; unknown methods are rejected."""
     for nbits in (2, 8):
         plans = [pcal.plan(1_024_000_000, 1_000_000, 510_000, nbits, method=m)
                  for m in (pcal.METHOD_LUT, pcal.METHOD_OSC, pcal.METHOD_CFO)]
         assert [p["method"] for p in plans] == [pcal.METHOD_LUT, pcal.METHOD_OSC, pcal.METHOD_CFO]
-        keys = [k for k in plans[0] if k not in ("method", "target_blocks")]
+        keys = [k for k in plans[0] if k not in ("method", "target_blocks", "device_bytes")]
         assert all(p[k] == plans[0][k] for p in plans for k in keys)
         assert [p["target_blocks"] for p in plans] == ([768, 512, 512] if nbits == 8 else [1024] * 3)
     with pytest.raises(pcal.PcalError) as e:
         pcal.plan(64_000_000, 1_000_000, 10_000, 2, method=5)
     assert e.value.code == pcal.EINVAL
+
+
+def test_plan_device_bytes():
+    """pcal_plan reports the device bytes a handle would allocate, without allocating: the fold's
+    factorised tables grow with the fold period, the table form's rotator with its precision."""
+    fold = pcal.plan(64_000_000, 1_000_000, 10_000, 2, method=pcal.METHOD_PERIOD_FOLD)
+    M = fold["fold_period"] // 64
+    assert fold["device_bytes"] > 28 * M
+    lut = {p: pcal.plan(1_024_000_000, 1_000_000, 510_000, 8, method=pcal.METHOD_LUT, precision=p)["device_bytes"]
+           for p in (pcal.PREC_F64, pcal.PREC_MIXED, pcal.PREC_F32)}
+    R = 102_400
+    assert lut[pcal.PREC_F64] - lut[pcal.PREC_MIXED] == 8 * R
+    assert lut[pcal.PREC_F64] - lut[pcal.PREC_F32] == 8 * R
+    osc = pcal.plan(1_024_000_000, 1_000_000, 510_000, 8, method=pcal.METHOD_OSC)["device_bytes"]
+    assert lut[pcal.PREC_F64] - osc == 16 * R

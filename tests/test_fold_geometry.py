@@ -278,3 +278,40 @@ def test_fold_plan_rules(fs, fo, nbits):
     ties = [t for t in range(448, 769, 64) if t >= tile and abs(eff(t) - best) < 1e-9]
     assert abs(thr - 640) == min(abs(t - 640) for t in ties)
     assert info["row_vectors"] == (thr // tile) * W if tiles == 1 else info["row_vectors"] % W == 0
+
+
+@pytest.mark.parametrize("fs,fc,fo", [(1_024_000_000, 1_000_000, 250_010), (64_000_000, 1_000_000, 15_626),
+                                      (64_000_000, 2_000_000, 10_007), (1_024_000_000, 1_000_000, 510_000),
+                                      (512_000_000, 1_000_000, 125_003), (48_000_000, 1_000_000, 250_001)])
+@pytest.mark.parametrize("prec", [pcal.PREC_F64, pcal.PREC_MIXED])
+def test_resonator_row_step_far_from_zero_and_pi(fs, fc, fo, prec):
+    """The resonator steps by d = w_o * (samples per row) with 2 cos d rounded: the planner picks the
+    row length (sub-rows of lcm(N, 16) samples, 256-512-thread workgroups) whose |sin d| is largest up
+    to 0.2, the smallest workgroup among those, wasting no more lanes than the others."""
+    info = pcal.plan(fs, fc, fo, 8, method=pcal.METHOD_OSC, precision=prec)
+    N = fs // fc
+    per = int(np.lcm(N, 16))
+    W = per // 16
+    dn = info["row_vectors"] * 16
+    assert dn % per == 0
+
+    def score(t):
+        k = t // W
+        return min(abs(np.sin(2 * np.pi * ((fo * k * per) % fs) / fs)), 0.2)
+    cands = [t for t in range(256, 513, 64) if t >= W]
+    best = max(score(t) for t in cands)
+    assert abs(score(info["block_threads"]) - best) < 1e-12
+    assert min(abs(np.sin(2 * np.pi * ((fo * dn) % fs) / fs)), 0.2) == pytest.approx(best, abs=1e-12)
+    assert best >= 0.2
+
+
+def test_auto_takes_coupled_form_when_no_row_step_suits_the_resonator():
+    """f_offset = 1000001 Hz at fs = 1024 MHz: the rotator advances by 2 pi 1e-6 per 1024 samples, so every
+    row length leaves d near 0.  AUTO keeps the resonator in FP64 (its coefficient error is 2^-29 of
+    FP32's) and takes the coupled form in the FP32-state forms."""
+    assert pcal.plan(1_024_000_000, 1_000_000, 1_000_001, 8, precision=pcal.PREC_F64)["method"] == pcal.METHOD_OSC
+    for prec in (pcal.PREC_MIXED, pcal.PREC_F32):
+        assert pcal.plan(1_024_000_000, 1_000_000, 1_000_001, 8, precision=prec)["method"] == pcal.METHOD_CFO
+    # an offset whose row step suits the resonator keeps it in every form
+    for prec in (pcal.PREC_F64, pcal.PREC_MIXED, pcal.PREC_F32):
+        assert pcal.plan(64_000_000, 2_000_000, 10_007, 8, precision=prec)["method"] == pcal.METHOD_OSC

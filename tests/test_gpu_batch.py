@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import F64_RTOL, assert_spectra, say
+from tests.gpu_util import AMP_RTOL, F64_RTOL, PHASE_ATOL, assert_spectra, compare_spectra, rounded_tables, say
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -191,3 +191,85 @@ def test_batch_full_size_sampled(pc):
         if i in ib:
             np.testing.assert_array_equal(ib[i], oracle.fold_int(host, 2, L, s.ntones))
     say("batch full size: %d streams, %d with integer bins" % (len(specs), len(ib)))
+
+
+def _member_reduced_check(pc, b, ids, specs, packed, L, prec, what):
+    """Each member of a reduced-precision batch against the oracle fed with the same rounded
+    rotator factors (the kernel's arithmetic alone), and against the exact FP64 oracle (the
+    contract: 1e-5 relative amplitude, 1e-4 rad phase).  Returns the per-member errors."""
+    C = b.spectra(ids)
+    rows = []
+    for j, i in enumerate(ids):
+        s = specs[j]
+        info = b.member_info(i)
+        assert info["precision"] == prec
+        u, v, gain = rounded_tables(s.fs, s.f_offset, s.ntones, info["fold_period"] // s.ntones, prec)
+        Cr = oracle.correlate_rotator(packed[j], s.nbits, L, s.ntones, u, v) * gain
+        err_kernel = np.abs(C[j] - Cr).max() / np.abs(Cr).max()
+        Co = oracle.correlate(packed[j], s.nbits, L, s.fs, s.f_comb, s.f_offset)
+        a, p, w = compare_spectra(C[j], Co, rel_floor=1e-6)
+        rows.append((err_kernel, a, p, w))
+        # MIXED: FP32 products with Kahan sums, FP64 from the cross-workgroup
+        # reduction on; F32: FP32 sums, reduction and DFT as well
+        assert err_kernel < (2e-6 if prec == 1 else 1e-5), (what, j, err_kernel)
+        assert a < AMP_RTOL and p < PHASE_ATOL and w < 1e-6, (what, j, a, p, w)
+    e = np.array(rows)
+    say("%s prec %d: kernel vs rounded tables max %.2e; vs FP64 oracle amp max %.2e phase max %.2e rad"
+        % (what, prec, e[:, 0].max(), e[:, 1].max(), e[:, 2].max()))
+    return e
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_batch_reduced_precision_mix(pc, prec):
+    """The 64-stream mix through the mixed-precision (FP16 two-term rotator rows,
+    Kahan FP32 block sums, FP64 reduction and DFT) and all-FP32 batched forms,
+    in two chunks per stream (the second misaligned)."""
+    specs = synth.batch_specs()
+    L = 1 << 20
+    packed = [synth.make_stream(s, L) for s in specs]
+    devs = [torch.from_numpy(p).cuda() for p in packed]
+    say("batch of %d streams, precision form %d" % (len(specs), prec))
+    with pc.PCalBatch(len(specs), precision=prec) as b:
+        ids = [b.add(s.fs, s.f_comb, s.f_offset, s.nbits) for s in specs]
+        c1 = 4 * 77_777
+        b.extract(ids, devs, [c1] * len(ids))
+        b.extract(ids, [d.data_ptr() + c1 // 4 for d in devs], [L - c1] * len(ids))
+        _member_reduced_check(pc, b, ids, specs, packed, L, prec, "mix64")
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_batch_reduced_precision_mixed_widths(pc, prec):
+    """2-bit and 8-bit members in one reduced-precision call, past the 8-item inline
+    work-list (9 members: the list is staged on the device)."""
+    specs = synth.batch_specs(9, seed=11, nbits=None)
+    assert {s.nbits for s in specs} == {2, 8}
+    L = 1 << 20
+    packed = [synth.make_stream(s, L) for s in specs]
+    devs = [torch.from_numpy(p).cuda() for p in packed]
+    with pc.PCalBatch(9, precision=prec) as b:
+        ids = [b.add(s.fs, s.f_comb, s.f_offset, s.nbits) for s in specs]
+        b.extract(ids, devs, [L] * 9)
+        _member_reduced_check(pc, b, ids, specs, packed, L, prec, "widths9")
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_batch_reduced_precision_alone_equals_mix(pc, prec):
+    """A member's result in a reduced-precision batch equals the same stream's own handle
+    in that form: the batch does not change the arithmetic."""
+    specs = synth.batch_specs(12, seed=17)
+    L = 1 << 20
+    packed = [synth.make_stream(s, L) for s in specs]
+    devs = [torch.from_numpy(p).cuda() for p in packed]
+    with pc.PCalBatch(12, precision=prec) as b:
+        ids = [b.add(s.fs, s.f_comb, s.f_offset, s.nbits) for s in specs]
+        b.extract(ids, devs, [L] * 12)
+        C = b.spectra(ids)
+    for i in (0, 5, 11):
+        s = specs[i]
+        with pc.PCal(s.fs, s.f_comb, s.f_offset, s.nbits, method=pc.METHOD_PERIOD_FOLD, precision=prec) as h:
+            h.extract(devs[i], L)
+            Cs = h.spectrum()
+        scale = np.abs(Cs).max()
+        err = np.abs(C[i] - Cs).max() / scale
+        say("alone vs mix prec %d member %d: %.2e" % (prec, i, err))
+        assert err < (1e-6 if prec == 1 else 1e-5), (i, err)

@@ -128,6 +128,42 @@ def test_wide8_chunks_sampled(pc):
     assert_spectra(C[tones], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="wide8 (sampled tones)")
 
 
+@pytest.fixture(scope="module")
+def wide8_real_chunks(pc):
+    """The 8-bit wide workload at its real chunk size: the first two 2^28-sample chunks
+    (one chunk boundary), 8 tones from the oracle."""
+    spec = synth.WORKLOADS["wide8_1024M_510k"]["spec"]
+    chunk = 1 << 28
+    say("wide8_1024M_510k: generating two chunks of 2^28 samples")
+    dev = synth.make_stream_device(spec, 2 * chunk)
+    tones = [0, 1, 100, 255, 511, 512, 777, 1023]
+    Co = oracle.correlate(dev.cpu().numpy(), 8, 2 * chunk, spec.fs, spec.f_comb, spec.f_offset, tones=tones)
+    yield spec, chunk, dev, tones, Co
+    del dev
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("method", [1, 2, 3, 4])
+def test_wide8_real_chunks_sampled(pc, wide8_real_chunks, method):
+    """Two 2^28-sample chunks, each one pcal_extract in the launch shape the benchmark
+    times (the period fold's persistent grid walks many 4-row groups per workgroup;
+    the per-sample forms cross a chunk boundary mid-period, 2^28 mod 102400 != 0).
+    The period fold (FP64 rotation of exact integer sums) to 1e-10; the per-sample
+    forms to the contract tolerance."""
+    spec, chunk, dev, tones, Co = wide8_real_chunks
+    say("wide8 real chunks, method %d" % method)
+    h = pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 8, method=method)
+    assert h.info()["method"] == method
+    h.extract(dev[:chunk], chunk)
+    h.extract(dev[chunk:], chunk)
+    C = h.spectrum()
+    h.close()
+    if method == 1:
+        assert_spectra(C[tones], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="wide8 2x2^28 fold")
+    else:
+        assert_spectra(C[tones], Co, what="wide8 2x2^28 method %d" % method)
+
+
 def test_wide8_small_all_tones(pc):
     spec = synth.WORKLOADS["wide8_1024M_510k"]["spec"]
     L = 3 * 102_400 + 4093

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import compare_spectra, say
+from tests.gpu_util import compare_spectra, rounded_tables, say
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -30,24 +30,6 @@ def pc():
     return pcal
 
 
-def _tables(spec, info, prec):
-    fs, fo = spec.fs, spec.f_offset
-    N = spec.ntones
-    M = info["fold_period"] // N
-    u = np.exp(-2j * np.pi * ((fo * N * np.arange(M)) % fs) / fs)
-    v = np.exp(-2j * np.pi * ((fo * np.arange(N)) % fs) / fs)
-    if prec == 1:
-        def f16(z):
-            return z.real.astype(np.float16).astype(float) + 1j * z.imag.astype(np.float16).astype(float)
-        hi = f16(u)
-        uh = hi + f16(u - hi)  # two FP16 terms
-        gamma = np.mean(np.conj(u) * (uh - u))
-        return uh, v, 1.0 / (1.0 + gamma)
-    uf = u.real.astype(np.float32).astype(float) + 1j * u.imag.astype(np.float32).astype(float)
-    vf = v.real.astype(np.float32).astype(float) + 1j * v.imag.astype(np.float32).astype(float)
-    return uf, vf, 1.0
-
-
 @pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("s", [0, 3, 4, 8, 9])
 def test_precision_form(pc, prec, s):
@@ -60,7 +42,7 @@ def test_precision_form(pc, prec, s):
         h.extract(dev, L)
         C = h.spectrum()
         info = h.info()
-    u, v, gain = _tables(spec, info, prec)
+    u, v, gain = rounded_tables(spec.fs, spec.f_offset, spec.ntones, info["fold_period"] // spec.ntones, prec)
     Cr = oracle.correlate_rotator(packed, 2, L, spec.ntones, u, v) * gain
     scale = np.abs(Cr).max()
     err_kernel = np.abs(C - Cr).max() / scale
@@ -74,6 +56,7 @@ def test_precision_form(pc, prec, s):
         # 1e-4 rad phase tolerance of the FP64 oracle
         assert amp_e < 1e-5 and ph_e < 1e-4
     else:
-        # FP32 sums over rows, workgroups (atomics) and the N-point DFT
-        assert err_kernel < 1e-4
-        assert amp_e < 1e-3 and ph_e < 1e-3
+        # FP32 sums over rows, workgroups (atomics) and the N-point DFT: measured
+        # at most 1.1e-6 against the FP64 form on the full workloads
+        assert err_kernel < 1e-5
+        assert amp_e < 1e-5 and ph_e < 1e-5

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import F64_RTOL, assert_spectra, say
+from tests.gpu_util import AMP_RTOL, F64_RTOL, PHASE_ATOL, assert_spectra, say
 
 pytestmark = pytest.mark.gpu
 
@@ -50,13 +50,13 @@ def _streams_on_device():
     return data
 
 
-def _plain_integrations(buf, fs, fc, fo, nbits, integ):
+def _plain_integrations(buf, fs, fc, fo, nbits, integ, prec=0):
     """Spectra of the complete integrations with one plain handle, extract + reset per integration."""
     from paper_2501_05993_amd import pcal
 
     spb = 8 // nbits
     out = []
-    with pcal.PCal(fs, fc, fo, nbits, method=pcal.METHOD_PERIOD_FOLD) as h:
+    with pcal.PCal(fs, fc, fo, nbits, method=pcal.METHOD_PERIOD_FOLD, precision=prec) as h:
         for k in range(TOTAL // integ):
             h.extract(buf, integ, byte_offset=k * integ // spb)
             out.append(h.spectrum())
@@ -64,12 +64,18 @@ def _plain_integrations(buf, fs, fc, fo, nbits, integ):
     return out
 
 
-def test_served_matches_plain_per_integration():
+# alone (one plain handle) vs in the served mix: the FP64 form to its rounding, the
+# reduced forms to the reordering of their FP32 sums (atomics, Kahan compensation)
+ALONE_TOL = {0: F64_RTOL, 1: 1e-6, 2: 1e-5}
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_served_matches_plain_per_integration(prec):
     from paper_2501_05993_amd import pcal
 
     bufs = _streams_on_device()
     rng = np.random.default_rng(5)
-    srv = pcal.PCalServer(mem_budget_bytes=1 << 30, max_streams=len(STREAMS))
+    srv = pcal.PCalServer(mem_budget_bytes=1 << 30, max_streams=len(STREAMS), precision=prec)
     sids = []
     for fs, fc, fo, nbits, integ in STREAMS:
         sids.append(srv.open(fs, fc, fo, nbits, integ))
@@ -89,7 +95,7 @@ def test_served_matches_plain_per_integration():
         i = queue[j][0]
         arrivals.append(per[i][pos[i]])
         pos[i] += 1
-    say("served: %d streams, %d chunks" % (len(STREAMS), len(arrivals)))
+    say("served (precision form %d): %d streams, %d chunks" % (prec, len(STREAMS), len(arrivals)))
     got = {}
     k = 0
     while k < len(arrivals) or srv.stats()["queued_samples"] > 0:
@@ -111,17 +117,22 @@ def test_served_matches_plain_per_integration():
         if srv.stats()["inflight_finalizes"] == 0:
             break
     for i, (fs, fc, fo, nbits, integ) in enumerate(STREAMS):
-        want = _plain_integrations(bufs[i], fs, fc, fo, nbits, integ)
+        want = _plain_integrations(bufs[i], fs, fc, fo, nbits, integ, prec)
         assert len(want) == TOTAL // integ
         for k2, w in enumerate(want):
             assert (sids[i], k2) in got, "integration %d of stream %d not reported" % (k2, i)
-            assert_spectra(got[(sids[i], k2)], w, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="stream %d integration %d" % (i, k2))
+            assert_spectra(got[(sids[i], k2)], w, amp_rtol=ALONE_TOL[prec], phase_atol=ALONE_TOL[prec],
+                           rel_floor=1e-6, what="stream %d integration %d" % (i, k2))
     # one stream against the oracle: its second integration (global index continues)
     fs, fc, fo, nbits, integ = STREAMS[0]
     host = bufs[0].cpu().numpy()
     sub = host[integ // 4:2 * integ // 4]
     want = oracle.correlate(sub, nbits, integ, fs, fc, fo, n0=integ)
-    assert_spectra(got[(sids[0], 1)], want, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="served vs oracle")
+    if prec == 0:
+        assert_spectra(got[(sids[0], 1)], want, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="served vs oracle")
+    else:
+        assert_spectra(got[(sids[0], 1)], want, amp_rtol=AMP_RTOL, phase_atol=PHASE_ATOL, rel_floor=1e-6,
+                       what="served form %d vs oracle" % prec)
     srv.close()
 
 
@@ -144,7 +155,35 @@ def test_served_admission_by_memory_budget():
     assert srv.stats()["device_bytes"] == 0
     b = srv.open(64_000_000, 1_000_000, 10_000, 2, 1 << 20)
     assert b >= 0
+    # the planner's device bytes (no allocation) are what the stream takes
+    assert pcal.plan(64_000_000, 1_000_000, 10_000, 2, method=pcal.METHOD_PERIOD_FOLD)["device_bytes"] == need
     with pytest.raises(pcal.PcalError) as e:
         srv.submit([b], [0], [3])  # not a multiple of the samples per byte
     assert e.value.code == pcal.EINVAL
+    srv.close()
+
+
+def test_served_admission_refuses_before_allocating():
+    """A budget below one stream's device bytes: the open is refused with PCAL_EAGAIN from the plan
+    alone, nothing is allocated (no device bytes in use, the free device memory unchanged), and a
+    stream that fits is admitted afterwards."""
+    import torch
+    from paper_2501_05993_amd import pcal
+
+    need = pcal.plan(128_000_000, 1_000_000, 250_000, 8, method=pcal.METHOD_PERIOD_FOLD,
+                     precision=pcal.PREC_MIXED)["device_bytes"]
+    small = pcal.plan(32_000_000, 1_000_000, 0, 2, method=pcal.METHOD_PERIOD_FOLD,
+                      precision=pcal.PREC_MIXED)["device_bytes"]
+    assert small < need
+    srv = pcal.PCalServer(mem_budget_bytes=need - 1, max_streams=2, precision=pcal.PREC_MIXED)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    with pytest.raises(pcal.PcalError) as e:
+        srv.open(128_000_000, 1_000_000, 250_000, 8, 1 << 20)
+    assert e.value.code == pcal.EAGAIN
+    assert srv.stats()["device_bytes"] == 0
+    assert torch.cuda.mem_get_info()[0] == free0
+    a = srv.open(32_000_000, 1_000_000, 0, 2, 1 << 20)
+    assert srv.stats()["device_bytes"] == small
+    srv.close_stream(a)
     srv.close()
