@@ -10,11 +10,13 @@ its Python binding) never does, and the two share no code.
 * :mod:`oracle.fit` -- amplitude, phase and delay from the C_k (numpy, FP64).
 * :mod:`oracle.params` -- rotator period (Eq. 4) and phase step (Eq. 5).
 * :mod:`oracle.pulse` -- the delay at the power peak of the folded pulse
-  (Sections 2-3) from the rotated bins P[b] (``fold_rot``, Eqs. 2-3), and
-  the band-pass corrected for that group delay (Section 3).
+  (Sections 2-3) from the rotated bins P[b] (``fold_rot``, Eqs. 2-3), the
+  band-pass corrected for that group delay (Section 3), and the multi-pass
+  refinement of the delay by counter-rotation with the residual phase
+  (Section 2).
 """
 from .core import (build, correlate, correlate_f64, correlate_rotator, decode, fold_int, fold_rot,  # noqa: F401
                    max_threads)
-from .pulse import bandpass, pulse_peak  # noqa: F401
+from .pulse import bandpass, pulse_peak, refine  # noqa: F401
 from .fit import delay_fit, in_band, results, tone_freqs  # noqa: F401
 from .params import ntones, phase_step, rotator_period  # noqa: F401

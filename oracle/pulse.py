@@ -64,3 +64,43 @@ def bandpass(C, fs: int, f_comb: int, f_offset: int, delay: float, sideband: int
         C = np.conj(C)
     f = f_offset + f_comb * np.arange(C.size, dtype=np.float64)
     return np.angle(C * np.exp(-2j * np.pi * f * delay))
+
+
+def refine(C, fs: int, f_comb: int, f_offset: int, t0: float, iters: int, sideband: int = 1):
+    """Multi-pass delay refinement (Section 2: a coarse delay from the pulse, then repeated passes that
+    counter-rotate by the current estimate and measure the residual phase).
+
+    Reading used here: the counter-rotation by a delay t is applied to the tone responses, which is what
+    counter-rotating the input by that delay does to them -- every tone k turns by exp(-j 2 pi f_k t),
+    f_k = f_offset + k f_comb.  Starting from t0, each pass takes the residual phases
+    psi_k = arg(C_k exp(-j 2 pi f_k t)) of the in-band tones (0 < f_k < fs/2), unwraps them along
+    increasing f_k, fits the least-squares line psi = a + 2 pi f t_res and moves the estimate to
+    t + t_res.  A lower-sideband stream is reported as the conjugate spectrum first (as
+    :func:`oracle.results` does).
+
+    Returns (delays, a, rms): delays[0] = t0 and delays[i] the estimate after pass i (seconds), then the
+    last pass's intercept a (rad, the line's phase at f = 0) and the rms of its phase residuals about
+    the line (rad).
+    """
+    from .fit import in_band, tone_freqs
+
+    if iters < 1:
+        raise ValueError("at least one pass")
+    C = np.asarray(C, dtype=np.complex128)
+    if sideband < 0:
+        C = np.conj(C)
+    k = in_band(fs, f_comb, f_offset)
+    f = tone_freqs(fs, f_comb, f_offset)[k]
+    Ck = C[k]
+    delays = [float(t0)]
+    t = float(t0)
+    a = rms = 0.0
+    for _ in range(iters):
+        psi = np.unwrap(np.angle(Ck * np.exp(-2j * np.pi * f * t)))
+        fm, um = f.mean(), psi.mean()
+        slope = np.sum((f - fm) * (psi - um)) / np.sum((f - fm) ** 2)
+        a = float(um - slope * fm)
+        rms = float(np.sqrt(np.mean((psi - a - slope * f) ** 2)))
+        t = t + float(slope / (2.0 * np.pi))
+        delays.append(t)
+    return np.asarray(delays), a, rms
