@@ -34,8 +34,9 @@ def _bind(path: str):
     lib.orc_decode.argtypes = [p, i32, i64, p]
     lib.orc_correlate_rotator.argtypes = [p, i32, i64, i64, i64, i64, p, p, p, p, i32, p, i32, p, p]
     lib.orc_fold_rot.argtypes = [p, i32, i64, i64, i64, i64, i64, i32, p, p]
+    lib.orc_fold_table_int.argtypes = [p, i32, i64, i64, i64, i64, p, p, p, p]
     for f in (lib.orc_correlate_packed, lib.orc_correlate_f64, lib.orc_fold_int, lib.orc_decode,
-              lib.orc_max_threads, lib.orc_correlate_rotator, lib.orc_fold_rot):
+              lib.orc_max_threads, lib.orc_correlate_rotator, lib.orc_fold_rot, lib.orc_fold_table_int):
         f.restype = ctypes.c_int
     return lib
 
@@ -180,6 +181,38 @@ def fold_rot(packed, nbits: int, nsamples: int, fs: int, f_offset: int, nbins: i
     if rc:
         raise ValueError("oracle rejected the arguments (code %d)" % rc)
     return re + 1j * im
+
+
+def fold_table_int(packed, nbits: int, nsamples: int, nbins: int, table, n0: int = 0):
+    """Eqs. 2-3 with an integer rotator table T (complex, integer parts, length R = the rotator period):
+    P[b] = sum of x[n] T[n mod R] over n = b (mod nbins), exact; returns (re, im) as int64 arrays."""
+    b = _bytes(packed)
+    t = np.asarray(table)
+    tr = np.ascontiguousarray(np.asarray(t.real, dtype=np.int32))
+    ti = np.ascontiguousarray(np.asarray(t.imag, dtype=np.int32))
+    if not (np.array_equal(tr, t.real) and np.array_equal(ti, t.imag)):
+        raise ValueError("table entries must be integers within int32")
+    re = np.zeros(nbins, dtype=np.int64)
+    im = np.zeros(nbins, dtype=np.int64)
+    rc = _load().orc_fold_table_int(_ptr(b), nbits, nsamples, n0, nbins, tr.size, _ptr(tr), _ptr(ti), _ptr(re),
+                                    _ptr(im))
+    if rc:
+        raise ValueError("oracle rejected the arguments (code %d)" % rc)
+    return re, im
+
+
+def fixed_rotator(fs: int, f_offset: int, frac_bits: int = 15) -> np.ndarray:
+    """The rotator exp(-j 2 pi f_offset r / fs) over one period R = fs / gcd(fs, f_offset) (Eq. 4), scaled by
+    2^frac_bits and rounded to the nearest integer (ties to even): the fixed-point rotator of Section 4.8.
+    Complex array whose parts are integers."""
+    from math import gcd
+
+    R = fs // gcd(fs, f_offset)
+    r = np.arange(R, dtype=np.int64)
+    idx = (f_offset * r) % fs                                  # exact phase index
+    ang = 2.0 * np.pi * idx.astype(np.float64) / float(fs)
+    scale = float(1 << frac_bits)
+    return np.rint(scale * np.cos(ang)) - 1j * np.rint(scale * np.sin(ang))
 
 
 def decode(packed, nbits: int, nsamples: int) -> np.ndarray:

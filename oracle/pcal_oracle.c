@@ -366,6 +366,30 @@ int orc_fold_rot(const uint8_t *packed, int nbits, int64_t nsamples, int64_t n0,
     return ORC_OK;
 }
 
+/* Eqs. 2-3 with the rotator given as a table of integers (the fixed-point
+ * rotator of Section 4.8: each rotator value scaled and rounded to an integer,
+ * products and sums in integers):
+ *   P[b] = sum of x[n] * T[n mod R] over n = b (mod N), n = n0 .. n0+nsamples-1,
+ * T[r] = t_re[r] + j t_im[r], exact in int64 (no rounding anywhere). */
+int orc_fold_table_int(const uint8_t *packed, int nbits, int64_t nsamples, int64_t n0, int64_t nbins, int64_t R,
+                       const int32_t *t_re, const int32_t *t_im, int64_t *re, int64_t *im)
+{
+    if ((!packed && nsamples > 0) || (nbits != 2 && nbits != 8) || nsamples < 0 || n0 < 0 || nbins <= 0 ||
+        R <= 0 || !t_re || !t_im || !re || !im)
+        return ORC_EINVAL;
+    memset(re, 0, sizeof(int64_t) * (size_t)nbins);
+    memset(im, 0, sizeof(int64_t) * (size_t)nbins);
+    int64_t b = n0 % nbins, r = n0 % R;
+    for (int64_t i = 0; i < nsamples; i++) {
+        const int64_t x = orc_level(packed, nbits, i);
+        re[b] += x * t_re[r];
+        im[b] += x * t_im[r];
+        if (++b == nbins) b = 0;
+        if (++r == R) r = 0;
+    }
+    return ORC_OK;
+}
+
 int orc_max_threads(void)
 {
 #ifdef _OPENMP
