@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Gsamples/s and % HBM peak, 2-bit fold @1e-4 rad; p99 latency per integration"
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "fold2_64M_10k"
-EVENT_EVERY = 10  # timed steps per kernel-stamped launch
+STAMPED_STEPS = 30  # kernel-stamped steps after the timed region (the kernel's duration)
 KERNEL_SRC = os.path.join(ROOT, "paper_2501_05993_amd", "csrc", "pcal_kernels.hip")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "fold_kernel_fold2_64M_10k_pmc.md")
 
@@ -87,6 +87,51 @@ def cpu_baseline(host_bytes, spec, target_s=12.0):
                       "per-tone correlation, %.1f s" % (n2, np.log2(n2), spec.ntones, dt2),
             "one_core": {"value": round(n1 / dt1 / 1e9, 6), "sample": "first 2^23 samples, %.1f s" % dt1},
             "cpu_model": model, "cost": "N x L complex multiply-adds (N = %d tones)" % spec.ntones}
+
+
+def cpu_baseline_configs(torch, synth, target_s=4.0):
+    """The oracle on the host cores on the other single-stream and batched workloads, each on a bounded
+    sample sized for about target_s of work: the small 2-bit f_offset = 0 stream in full, a prefix of the
+    8-bit wide stream, and a prefix of every stream of the 64-stream batch."""
+    import oracle
+
+    threads = oracle.max_threads()
+    out = {}
+
+    def timed(packed, nbits, n, sp):
+        t0 = time.perf_counter()
+        oracle.correlate(packed, nbits, n, sp.fs, sp.f_comb, sp.f_offset, nthreads=threads)
+        return time.perf_counter() - t0
+
+    w = synth.WORKLOADS["small_2bit_fo0"]
+    sp, L = w["spec"], w["nsamples"]
+    packed = synth.make_stream(sp, L)
+    dt = timed(packed, 2, L, sp)
+    out["small_2bit_fo0"] = {"value": round(L / dt / 1e9, 6), "unit": "Gsamples/s",
+                             "sample": "the whole stream: 2^24 samples, N = 32 tones, %.2f s" % dt}
+    w = synth.WORKLOADS["wide8_1024M_510k"]
+    sp = w["spec"]
+    n = 1 << 20
+    dev = synth.make_stream_device(sp, 1 << 26)
+    host = dev.cpu().numpy()
+    del dev
+    dt = timed(host, 8, n, sp)
+    n2 = int(min(1 << 26, max(n, n * target_s / max(dt, 1e-6)))) & ~((1 << 20) - 1)
+    dt2 = timed(host, 8, n2, sp)
+    out["wide8_1024M_510k"] = {"value": round(n2 / dt2 / 1e9, 6), "unit": "Gsamples/s",
+                               "sample": "first %d samples (2^%.1f) of the 8-bit stream, N = 1024 tones, %.1f s; "
+                                         "a prefix, not the 2^33-sample integration" % (n2, np.log2(n2), dt2)}
+    specs = synth.batch_specs()
+    per = 1 << 18
+    packs = [synth.make_stream(s_, per) for s_ in specs]
+    t0 = time.perf_counter()
+    for s_, pk in zip(specs, packs):
+        oracle.correlate(pk, 2, per, s_.fs, s_.f_comb, s_.f_offset, nthreads=threads)
+    dt = time.perf_counter() - t0
+    out["batch64"] = {"value": round(len(specs) * per / dt / 1e9, 6), "unit": "Gsamples/s",
+                      "sample": "first 2^18 samples of each of the 64 streams (N = 16-512 tones), %.1f s" % dt}
+    out["cores"] = threads
+    return out
 
 
 SERVED_POOL = 1 << 24  # samples of the pre-staged device pool per stream configuration
@@ -225,15 +270,20 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False):
             "wall_s": round(wall, 2)}
 
 
-def precision_report(pcal, torch, synth):
+def precision_report(pcal, torch, synth, oracle=None):
     """Config-4 precision study: 64 streams (fs 16-512 MHz, f_offset 0-510 kHz, 2-bit, 2^26 samples each)
-    through the batched form in the mixed (FP16 table, Kahan FP32) and all-FP32 forms, against the FP64 form."""
+    through the batched form in each precision form -- mixed (two-term FP16 table, Kahan FP32, FP64
+    reduce/DFT), all-FP32, and the literal single-FP16 mixed variant -- against the FP64 form, per stream;
+    the FP64 form itself against the FP64 oracle on two tones per stream."""
     specs = synth.batch_specs()
     L = 1 << 26
+    print("[bench] precision study: 64 streams x 2^26 samples in 4 precision forms", file=sys.stderr, flush=True)
     devs = [synth.make_stream_device(sp, L) for sp in specs]
     torch.cuda.synchronize()
+    forms = (("f64", pcal.PREC_F64), ("mixed", pcal.PREC_MIXED), ("f32", pcal.PREC_F32),
+             ("f16_single", pcal.PREC_F16))
     res = {}
-    for prec in (pcal.PREC_F64, pcal.PREC_MIXED, pcal.PREC_F32):
+    for name, prec in forms:
         b = pcal.PCalBatch(len(specs), precision=prec)
         ids = [b.add(sp.fs, sp.f_comb, sp.f_offset, 2) for sp in specs]
         b.extract(ids, devs, [L] * len(ids))
@@ -249,14 +299,24 @@ def precision_report(pcal, torch, synth):
             b.extract(ids, devs, [L] * len(ids))
             b.results(ids)
         dt = (time.perf_counter() - t0) / K
-        res[prec] = (C, d, dt)
+        res[name] = (C, d, dt)
         b.close()
-    C64, d64, t64 = res[pcal.PREC_F64]
+    C64, d64, t64 = res["f64"]
     out = {"workload": "64 streams, fs 16-512 MHz, f_offset {0,10,250,510} kHz, 2-bit, 2^26 samples each",
+           "streams": [[sp.fs // 1_000_000, sp.f_offset] for sp in specs],
+           "stream_key": "[fs MHz, f_offset Hz] per stream, in the order of the per-stream lists",
+           "bar": {"amp_rel": 1e-5, "phase_rad": 1e-4},
            "batched_step_ms": {"f64": round(t64 * 1e3, 3)}}
-    for name, prec in (("mixed", pcal.PREC_MIXED), ("f32", pcal.PREC_F32)):
-        C, d, dt = res[prec]
-        amp_e, ph_e, del_e = [], [], []
+    if oracle is not None:
+        errs = []
+        for sp, dv, c64 in zip(specs, devs, C64):
+            tones = [1, sp.ntones // 3]
+            Co = oracle.correlate(dv.cpu().numpy(), 2, L, sp.fs, sp.f_comb, sp.f_offset, tones=tones)
+            errs.append(float(np.abs(c64[tones] - Co).max() / np.abs(Co).max()))
+        out["f64_vs_oracle"] = {"rel_err_max": max(errs), "tones": "1 and N/3 of every stream"}
+    for name, _ in forms[1:]:
+        C, d, dt = res[name]
+        amp_e, ph_e = [], []
         for c, c64 in zip(C, C64):
             strong = np.abs(c64) >= 1e-5 * np.abs(c64).max()
             amp_e.append(float(np.max(np.abs(np.abs(c[strong]) - np.abs(c64[strong])) / np.abs(c64[strong]))))
@@ -264,8 +324,14 @@ def precision_report(pcal, torch, synth):
         del_e = np.abs(np.asarray(d) - np.asarray(d64))
         out[name] = {"amp_rel_err_max": max(amp_e), "amp_rel_err_median": float(np.median(amp_e)),
                      "phase_err_rad_max": max(ph_e), "phase_err_rad_median": float(np.median(ph_e)),
-                     "delay_err_s_max": float(del_e.max()), "delay_err_s_median": float(np.median(del_e))}
+                     "delay_err_s_max": float(del_e.max()), "delay_err_s_median": float(np.median(del_e)),
+                     "streams_within_bar": int(sum(a <= 1e-5 and p <= 1e-4 for a, p in zip(amp_e, ph_e))),
+                     "per_stream": {"amp_rel_err": [float("%.3g" % a) for a in amp_e],
+                                    "phase_err_rad": [float("%.3g" % p) for p in ph_e],
+                                    "delay_err_s": [float("%.3g" % x) for x in del_e]}}
         out["batched_step_ms"][name] = round(dt * 1e3, 3)
+    del devs
+    torch.cuda.empty_cache()
     return out
 
 
@@ -400,23 +466,81 @@ def precision_single(pcal, torch, synth):
     return out
 
 
+def per_sample_2bit_study(pcal, torch, synth, oracle=None):
+    """2-bit stream with a long rotator period (fs = 64 MHz, f_offset = 10008 Hz: the rotator repeats only
+    after 8e6 samples, beyond the 2^22-sample fold periods AUTO folds, so AUTO takes the per-sample
+    recurrence): one 2^30-sample
+    integration through the per-sample forms, timed with events, HBM roofline at 0.25 B per sample, and
+    each form's spectrum against the oracle on two tones."""
+    w = synth.WORKLOADS["osc2_64M_10008"]
+    spec, L = w["spec"], w["nsamples"]
+    print("[bench] per-sample 2-bit study (f_offset 10008 Hz)", file=sys.stderr, flush=True)
+    buf = synth.make_stream_device(spec, L)
+    torch.cuda.synchronize()
+    tones = [1, 21]
+    Co = None
+    if oracle is not None:
+        Co = oracle.correlate(buf.cpu().numpy(), 2, L, spec.fs, spec.f_comb, spec.f_offset, tones=tones)
+    stream = torch.cuda.current_stream()
+    forms = (("auto_f64", pcal.METHOD_AUTO, pcal.PREC_F64), ("recurrence_mixed", pcal.METHOD_OSC, pcal.PREC_MIXED),
+             ("coupled_form_mixed", pcal.METHOD_CFO, pcal.PREC_MIXED), ("recurrence_f32", pcal.METHOD_OSC,
+                                                                         pcal.PREC_F32))
+    out = {}
+    for name, method, prec in forms:
+        h = pcal.PCal(spec.fs, spec.f_comb, spec.f_offset, 2, method=method, precision=prec)
+        chosen = h.info()["method"]
+        h.extract(buf, L)  # the integration compared with the oracle (global index from 0)
+        C = h.spectrum()
+        K = 5
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        for a, b in evs:
+            a.record(stream)
+            b.record(stream)
+        for k in range(K):
+            h.extract(buf, L, events=evs[k])
+        torch.cuda.synchronize()
+        us = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e3
+        h.close()
+        gbs = L / 4 / (us * 1e-6) / 1e9
+        entry = {"method": {1: "period_fold", 2: "table", 3: "recurrence", 4: "coupled_form"}[chosen],
+                 "kernel_us": round(us, 1), "gsamples_per_s": round(L / (us * 1e-6) / 1e9, 1),
+                 "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+        if Co is not None:
+            entry["vs_oracle"] = {
+                "tones": tones,
+                "amp_rel_err_max": float(np.max(np.abs(np.abs(C[tones]) - np.abs(Co)) / np.abs(Co))),
+                "phase_err_rad_max": float(np.max(np.abs(np.angle(C[tones] * np.conj(Co)))))}
+        out[name] = entry
+    del buf
+    torch.cuda.empty_cache()
+    return {"workload": "2-bit, fs 64 MHz, f_comb 1 MHz (N = 64), f_offset 10008 Hz (rotator period 8e6), "
+                        "2^30 samples, one launch per form (kernel-stamped)", **out}
+
+
 def rotator_study(pcal, torch, synth):
     """8-bit wide workload (fs = 1024 MHz, f_offset = 510 kHz, N = 1024, rotator period 102400): one
     integration of 2^33 samples streamed in 2^28-sample chunks (the global sample index runs on across
-    chunks) through each rotator form -- the period fold, the per-sample rotator table, the recurrence
-    (Eq. 7) and the coupled-form oscillator -- timed with events around the 32 launches, with each form's HBM roofline fraction (1 B per
-    sample read once) and its spectrum's spread against the period fold's (tones with signal)."""
+    chunks) through each rotator form -- the period fold (FP64 rotation, and the fixed-point Q17 rotator),
+    the per-sample rotator table, the direct-form resonator (Eq. 7), the coupled-form and magic-circle
+    oscillators and the resonator with error feedback, in the FP64 and mixed precision forms -- timed with
+    events around the 32 launches, with each form's HBM roofline fraction (1 B per sample read once) and its
+    spectrum's spread against the FP64 period fold's (tones with signal)."""
     w = synth.WORKLOADS["wide8_1024M_510k"]
     spec, L, chunk = w["spec"], w["nsamples"], w["chunk"]
     print("[bench] rotator study: generating %d GiB of 8-bit samples" % (L >> 30), file=sys.stderr, flush=True)
     buf = synth.make_stream_device(spec, L)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    forms = (("period_fold", pcal.METHOD_PERIOD_FOLD), ("table", pcal.METHOD_LUT), ("recurrence", pcal.METHOD_OSC),
-             ("coupled_form", pcal.METHOD_CFO))
+    P64, PMX = pcal.PREC_F64, pcal.PREC_MIXED
+    forms = (("period_fold", pcal.METHOD_PERIOD_FOLD, P64), ("period_fold_q17", pcal.METHOD_PERIOD_FOLD, pcal.PREC_Q17),
+             ("table", pcal.METHOD_LUT, P64), ("table_mixed", pcal.METHOD_LUT, PMX),
+             ("recurrence", pcal.METHOD_OSC, P64), ("recurrence_mixed", pcal.METHOD_OSC, PMX),
+             ("coupled_form", pcal.METHOD_CFO, P64), ("coupled_form_mixed", pcal.METHOD_CFO, PMX),
+             ("magic_circle_mixed", pcal.METHOD_MCO, PMX), ("error_feedback_dfr_mixed", pcal.METHOD_DFR_EF, PMX))
     out, spectra = {}, {}
-    for name, method in forms:
-        h = pcal.PCal(spec.fs, spec.f_comb, spec.f_offset, spec.nbits, method=method)
+    for name, method, prec in forms:
+        h = pcal.PCal(spec.fs, spec.f_comb, spec.f_offset, spec.nbits, method=method, precision=prec)
         h.extract(buf, chunk)  # warm-up chunk, then a fresh integration (global index continues)
         torch.cuda.synchronize()
         h.reset()
@@ -435,7 +559,7 @@ def rotator_study(pcal, torch, synth):
         h.close()
     ref = spectra["period_fold"]
     strong = np.abs(ref) >= 1e-3 * np.abs(ref).max()
-    for name, _ in forms[1:]:
+    for name, _, _ in forms[1:]:
         c = spectra[name]
         out[name]["vs_period_fold"] = {
             "amp_rel_err_max": float(np.max(np.abs(np.abs(c[strong]) - np.abs(ref[strong])) / np.abs(ref[strong]))),
@@ -456,6 +580,10 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--precision-report", action="store_true",
                     help="only run the 64-stream precision study (mixed and FP32 forms against FP64)")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the 64-stream per-stream precision report of the precision forms")
+    ap.add_argument("--no-per-sample-study", action="store_true",
+                    help="skip the 2-bit long-period (f_offset 10008 Hz) per-sample forms")
     ap.add_argument("--no-batched-study", action="store_true",
                     help="skip the 64-stream batched-form measurement")
     ap.add_argument("--no-rotator-study", action="store_true",
@@ -488,7 +616,9 @@ def main():
         print(json.dumps({"copy_calibration_bytes": 256 << 20, "copies": 10}), flush=True)
         return
     if args.precision_report:
-        print(json.dumps({"precision_report": precision_report(pcal, torch, synth),
+        import oracle
+
+        print(json.dumps({"precision_report": precision_report(pcal, torch, synth, oracle),
                           "precision_single_stream": precision_single(pcal, torch, synth)}), flush=True)
         return
     w = synth.WORKLOADS[WORKLOAD]
@@ -521,26 +651,31 @@ def main():
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    # A kernel-stamped launch costs ~7 us more than a plain one (measured), so
-    # the events are taken on every EVENT_EVERY-th step of the timed region: a
-    # sample of its launches that adds <1 us to the average step.
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range((args.steps + EVENT_EVERY - 1) // EVENT_EVERY)]
-    for a, b in evs:  # torch creates an event at its first record
-        a.record(stream)
-        b.record(stream)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(i, evs[i // EVENT_EVERY] if i % EVENT_EVERY == 0 else None)
+        step(i)
     h.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in evs]
     last = ring[(args.steps - 1) % 8].numpy().copy()
     n_last = h.info()["samples_total"] - L   # global index of the last integration's first sample
+    # The kernel's own duration: a separate pass of the same steps after the
+    # timed region, every fold launch stamped at its start and end (a stamped
+    # launch costs the stream a few us more, so none is taken inside the timed
+    # region).
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(STAMPED_STEPS)]
+    for a, b in evs:  # torch creates an event at its first record
+        a.record(stream)
+        b.record(stream)
+    for i, ev in enumerate(evs):
+        step(args.steps + i, ev)
+    h.sync()
+    torch.cuda.synchronize()
+    kern_ms = [a.elapsed_time(b) for a, b in evs]
 
     # Latency per integration: extract then results, synchronised, one at a time.
+    h.reset()
     lat = []
     for i in range(max(20, min(args.steps, 50))):
         torch.cuda.synchronize()
@@ -569,6 +704,7 @@ def main():
                      "kernel_note": "each launch also runs the previous integration's finalize in 1 of its "
                                     "256 workgroups (pcal_results_async with reset defers it into the next fold)",
                      "kernel_avg_us": round(kavg_s * 1e6, 2),
+                     "kernel_stamped_launches": len(kern_ms),
                      "kernel_us_p10_p50_p90": [round(float(np.percentile(kern_ms, q)) * 1e3, 2) for q in (10, 50, 90)],
                      "read_ceiling": ceiling,
                      "frac_of_read_ceiling": round(achieved / ceiling["achieved"], 4),
@@ -596,6 +732,16 @@ def main():
     h.close()
     bufs.clear()
     torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"]["other_workloads"] = cpu_baseline_configs(torch, synth)
+    if not args.no_precision:
+        import oracle
+
+        out["precision"] = precision_report(pcal, torch, synth, oracle)
+    if not args.no_per_sample_study:
+        import oracle
+
+        out["per_sample_2bit"] = per_sample_2bit_study(pcal, torch, synth, oracle)
     if not args.no_batched_study:
         out["batched"] = batched_study(pcal, torch, synth)
     if not args.no_rotator_study:

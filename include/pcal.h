@@ -67,15 +67,25 @@ enum pcal_status {
  *  CFO: as OSC with the coupled-form oscillator of Section 2.2 (the rotator
  *      times exp(-j d) per step, d the rotator advance of one step), for
  *      comparison with the direct-form resonator.
+ *  MCO: as OSC with the magic-circle oscillator of Section 2.2 (x += e y,
+ *      then y -= e x with the new x, e = 2 sin(d/2)); its state is not in
+ *      quadrature, so each step's rotator is read out as x - j sin(a) with
+ *      -sin(a) = (y + x sin(d/2)) / cos(d/2).
+ *  DFR_EF: the direct-form resonator with truncation-error feedback (a remedy
+ *      Section 2.2 names): state and coefficient in two terms each, every
+ *      step's rounding error carried into the next.
  *  AUTO: PERIOD_FOLD when the joint period fits (at most 2^22 samples), else
  *      OSC; CFO instead of OSC in the FP32-state forms (MIXED, F32) when no
- *      row length keeps |sin d| >= 0.1. */
+ *      row length keeps |sin d| >= 0.1.
+ * The recurrence forms (OSC, CFO, MCO, DFR_EF) share one row choice. */
 enum pcal_method {
     PCAL_METHOD_AUTO = 0,
     PCAL_METHOD_PERIOD_FOLD = 1,
     PCAL_METHOD_LUT = 2,
     PCAL_METHOD_OSC = 3,
-    PCAL_METHOD_CFO = 4
+    PCAL_METHOD_CFO = 4,
+    PCAL_METHOD_MCO = 5,
+    PCAL_METHOD_DFR_EF = 6
 };
 
 /* Arithmetic of the rotation and the per-block fold.  The cross-block
@@ -90,8 +100,27 @@ enum pcal_method {
  *         from the cross-block reduction on, with the table's known mean
  *         gain divided out.
  *  F32:   FP32 table or recurrence state, plain FP32 sums, FP32 reduction
- *         and DFT. */
-enum pcal_precision { PCAL_PREC_F64 = 0, PCAL_PREC_MIXED = 1, PCAL_PREC_F32 = 2 };
+ *         and DFT.
+ *  F16:   the literal mixed form, for comparison: MIXED's arithmetic with each
+ *         table entry a single FP16 value (the rounded rotator) and no gain
+ *         correction.  Its rounding leaves errors of order 1e-5 in amplitude,
+ *         at or above the 1e-5 bar MIXED meets.
+ *  Q17:   fixed-point rotator (the integer arithmetic of Section 4.8's FPGA
+ *         design, whose 18-bit multiplier operands hold a rotator value with
+ *         17 fractional bits): each rotator value exp(-j w_offset n) over one
+ *         period (Eq. 4) scaled by 2^17 and rounded to an integer (int32
+ *         entries, so +1 itself is exact), integer products with the integer
+ *         samples and exact integer sums; the bins P[b] (times 2^17) are
+ *         integers, exact while each bin's sum of |x| * 2^17 stays below
+ *         2^53, and the FP64 DFT scales them by 2^-17.  Period fold only (PCAL_ENOTSUP for
+ *         the per-sample forms and for batches). */
+enum pcal_precision {
+    PCAL_PREC_F64 = 0,
+    PCAL_PREC_MIXED = 1,
+    PCAL_PREC_F32 = 2,
+    PCAL_PREC_F16 = 3,
+    PCAL_PREC_Q17 = 4
+};
 
 /* Create a handle for one stream.
  *   fs_hz > 0, f_comb_hz > 0, fs_hz % f_comb_hz == 0 (N integer, Section 2),
@@ -169,7 +198,10 @@ int pcal_flush(pcal_t h);
  * parts (after the sideband convention).  Synchronises. */
 int pcal_spectrum(pcal_t h, double *re, double *im);
 
-/* The rotated, folded bins P[b] (b = 0..N-1) of Eq. 2-3 in FP64.  When
+/* The rotated, folded bins P[b] (b = 0..N-1) of Eq. 2-3 in FP64, with the
+ * precision form's known gain taken out (the mixed form's table gain, the
+ * fixed-point form's 2^17 scale: a power of two, so its bins stay exact), so
+ * that their DFT is the upper-sideband C_k.  When
  * f_offset == 0 and int_bins != NULL, also the exact integer bins of Eq. 2
  * (int64); PCAL_ESTATE when int_bins is requested for any other handle.
  * Computed on the device (the accumulator slots added in slot order) on the
@@ -191,8 +223,7 @@ int pcal_bins(pcal_t h, double *re, double *im, int64_t *int_bins);
  *           equal neighbours give d = 0.  Upper sideband: delay = -(b0 + s d) / fs;
  *           lower sideband: +(b0 + s d) / fs.
  *   peak    [3] or NULL: b0, the signed offset s d (bins), and the peak power
- *           |P[b0]|^2 / L^2 (L = samples in the integration; the mixed form's
- *           known table gain divided out).
+ *           |P[b0]|^2 / L^2 (L = samples in the integration).
  * An integration with no samples gives b0 = 0 and delay 0.  Computed by one
  * device workgroup on the handle's last stream; synchronises.  Errors:
  * PCAL_EINVAL (null handle), PCAL_EHIP. */
@@ -207,6 +238,26 @@ int pcal_pulse(pcal_t h, double *re, double *im, double *delay, double *peak);
  * and the pulse readout on the device (the handle's last stream);
  * synchronises.  Errors: PCAL_EINVAL (null handle), PCAL_EHIP. */
 int pcal_bandpass(pcal_t h, double *amp, double *phase, double *delay);
+
+/* Multi-pass refinement of the delay of the current integration (Section 2:
+ * the delay read coarsely off the pulse peak, then refined by passes that
+ * counter-rotate by the current estimate and measure the residual phase).
+ * The counter-rotation by a delay t turns tone k by exp(-j 2 pi f_k t),
+ * f_k = f_offset + k f_comb, which is what counter-rotating the input by that
+ * delay does to the tone responses.  Pass 0 is the pulse-peak delay of
+ * pcal_pulse, t_0.  Pass i = 1..iters takes the residual phases
+ * psi_k = arg(C_k exp(-j 2 pi f_k t_{i-1})) of the tones with 0 < f_k < fs/2
+ * (C_k as pcal_spectrum reports it), unwraps them along increasing f_k, fits
+ * the least-squares line psi = a + 2 pi f t_res and sets t_i = t_{i-1} + t_res.
+ *   iters   1 .. 16.
+ *   delays  [iters + 1] or NULL: t_0 .. t_iters (seconds).
+ *   resid   [2] or NULL: the last pass's intercept a (rad, the line's phase
+ *           at f = 0) and the rms of its phase residuals about the line (rad).
+ * Fewer than two in-band tones leave the delay at t_0 (resid 0, 0).  Runs the
+ * finalize, the pulse readout and the passes on the device (one workgroup, the
+ * handle's last stream); synchronises.  Errors: PCAL_EINVAL (null handle,
+ * iters out of range), PCAL_EHIP. */
+int pcal_refine(pcal_t h, int iters, double *delays, double *resid);
 
 /* Start a new integration: zero the accumulators; the global sample index
  * keeps counting (rotator phase stays continuous).  Ordered on the handle's
@@ -379,6 +430,33 @@ int pcal_server_result(pcal_server_t s, int sid, int64_t integration, double *am
 int pcal_server_spectrum(pcal_server_t s, int sid, int64_t integration, double *re, double *im);
 int pcal_server_stats(pcal_server_t s, int64_t *queued_samples, int *inflight_finalizes, int64_t *device_bytes);
 int pcal_server_destroy(pcal_server_t s);
+
+/* Device-resident form of the served loop.  pcal_server_start launches one
+ * persistent kernel of `workgroups` workgroups on `stream`; from then on
+ * pcal_server_step launches nothing: it publishes the queued pieces (split at
+ * integration boundaries, every queued piece that fits, not one per stream)
+ * as descriptors in a work ring in pinned, coherent host memory and returns.
+ * The kernel's workgroups claim the pieces' tasks in order (a piece is up to
+ * 32 fold workgroups' worth, PCAL_SERVED_TASKS), fold them into the stream's
+ * accumulator bank in HBM (two banks per stream, alternating by
+ * integration), and the task that completes an integration runs its FP64
+ * finalize, writes the results into the stream's pinned result slot and
+ * appends a completion record that pcal_server_poll reads.  A piece that
+ * completes an integration is published only after the stream's previous
+ * integration has been reported.  A workgroup waits only for the host to
+ * publish: it leaves when pcal_server_stop sets the quit flag, or after about
+ * 9 s without work, so the kernel always ends.  pcal_server_stop waits (up
+ * to 30 s) for the published work, sets the quit flag and waits for the
+ * kernel; the server continues in the host-step form.  pcal_server_close
+ * and pcal_server_destroy wait for published work first.  Streams need at
+ * most 1792 tones and a fold period of at most 32 column tiles in this form
+ * (PCAL_ENOTSUP otherwise, at start or open), and the batch workgroup size
+ * of 512 threads (PCAL_BATCH_THREADS unset).
+ * Errors: PCAL_EINVAL, PCAL_ESTATE (already started / not started),
+ * PCAL_ENOTSUP, PCAL_ENOMEM, PCAL_EHIP (a launch failed, or the published
+ * work did not end in time). */
+int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream);
+int pcal_server_stop(pcal_server_t s);
 
 /* Streaming-read reference (not part of the extraction): reads `bytes`
  * bytes at dev_ptr once with 16-byte non-temporal loads, as the fold kernel

@@ -201,7 +201,7 @@ def fold_table_int(packed, nbits: int, nsamples: int, nbins: int, table, n0: int
     return re, im
 
 
-def fixed_rotator(fs: int, f_offset: int, frac_bits: int = 15) -> np.ndarray:
+def fixed_rotator(fs: int, f_offset: int, frac_bits: int = 17) -> np.ndarray:
     """The rotator exp(-j 2 pi f_offset r / fs) over one period R = fs / gcd(fs, f_offset) (Eq. 4), scaled by
     2^frac_bits and rounded to the nearest integer (ties to even): the fixed-point rotator of Section 4.8.
     Complex array whose parts are integers."""

@@ -19,6 +19,8 @@ void set_error(const char *what, hipError_t e) {
     snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
 }
 
+void set_message(const char *what) { snprintf(g_last_error, sizeof(g_last_error), "%s", what); }
+
 
 int64_t gcd64(int64_t a, int64_t b) {
     while (b) {
@@ -115,14 +117,15 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
               int force_threads) {
     int rc = check_params(fs, fc, fo, nbits, sideband);
     if (rc) return rc;
-    if (method < PCAL_METHOD_AUTO || method > PCAL_METHOD_CFO) return PCAL_EINVAL;
-    if (prec < PCAL_PREC_F64 || prec > PCAL_PREC_F32) return PCAL_EINVAL;
+    if (method < PCAL_METHOD_AUTO || method > PCAL_METHOD_DFR_EF) return PCAL_EINVAL;
+    if (prec < PCAL_PREC_F64 || prec > PCAL_PREC_Q17) return PCAL_EINVAL;
     p->fs = fs;
     p->fc = fc;
     p->fo = fo;
     p->nbits = nbits;
     p->sideband = sideband;
-    p->prec = prec;
+    p->prec = kernel_prec(prec);
+    p->prec_api = prec;
     p->N = fs / fc;
     p->R = fs / gcd64(fs, fo);  // Eq. 4 (gcd(fs, 0) = fs gives R = 1)
     p->S = lcm_capped(p->N, p->R, kMaxFoldPeriod);
@@ -137,6 +140,7 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
         p->Sp *= (64 + W - 1) / W;
     }
     p->M = p->Sp > 0 ? p->Sp / p->N : -1;
+    p->tab_rows = prec == PCAL_PREC_Q17 ? p->R : p->M;
     const bool fold_ok = p->Sp > 0 && p->M <= kMaxTableRows;
     const bool osc_ok = fs < (int64_t(1) << 32);
     // The fold pays off while a launch spans many fold periods; for long periods
@@ -144,9 +148,16 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
     const bool auto_method = method == PCAL_METHOD_AUTO;
     if (auto_method)
         method = (fold_ok && p->Sp <= kAutoFoldPeriod) ? PCAL_METHOD_PERIOD_FOLD : PCAL_METHOD_OSC;
+    // the fixed-point form is a period-fold form (any fold period that fits)
+    if (prec == PCAL_PREC_Q17) {
+        if (auto_method) method = PCAL_METHOD_PERIOD_FOLD;
+        if (method != PCAL_METHOD_PERIOD_FOLD) return PCAL_ENOTSUP;
+    }
     if (method == PCAL_METHOD_PERIOD_FOLD && !fold_ok) return PCAL_ENOTSUP;
     if (method == PCAL_METHOD_LUT && (p->R > kMaxLutPeriod || !osc_ok)) return PCAL_ENOTSUP;
-    if ((method == PCAL_METHOD_OSC || method == PCAL_METHOD_CFO) && !osc_ok) return PCAL_ENOTSUP;
+    const bool recurrence = method == PCAL_METHOD_OSC || method == PCAL_METHOD_CFO || method == PCAL_METHOD_MCO ||
+                            method == PCAL_METHOD_DFR_EF;
+    if (recurrence && !osc_ok) return PCAL_ENOTSUP;
     p->method = method;
     if (method == PCAL_METHOD_PERIOD_FOLD) {
         p->geom = plan_geom(p->Sp, spv_of(nbits), kMaxLdsPositions, kMaxFoldThreads, force_threads,
@@ -155,12 +166,14 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
         // rows of a multiple of lcm(N, 16) samples: every lane keeps its bin
         const int64_t per = p->N / gcd64(p->N, kRotLanes) * kRotLanes;
         p->geom = plan_geom(per, kRotLanes, INT64_MAX, kMaxRotThreads, force_threads, 256, 0);
-        if (method == PCAL_METHOD_OSC && !force_threads && env_int("PCAL_FOLD_THREADS", 0) == 0) {
+        if (recurrence && !force_threads && env_int("PCAL_FOLD_THREADS", 0) == 0) {
             // The resonator steps once per row by d = w_o * (samples per row) with
             // the coefficient 2 cos d rounded to the form's precision; the
             // frequency that rounding leaves is off by about delta / (2 |sin d|),
             // so a d near 0 or pi makes the recurrence drift (Section 2.2 notes the
-            // resonator's loss of accuracy at low steps).  Rows hold k periods of
+            // resonator's loss of accuracy at low steps); the magic circle's
+            // read-out divides by cos(d / 2), small near d = pi.  Every recurrence
+            // form takes the same row choice.  Rows hold k periods of
             // lcm(N, 16) samples, k the workgroup's sub-rows: among the workgroup
             // sizes that waste no more lanes, take the k whose d is farthest from
             // 0 and pi (|sin d| >= 0.2 counts as far enough: the FP32 coefficient
@@ -245,7 +258,7 @@ pcal_launch_t plan_launch(const Plan &p, uint64_t addr, int64_t n_before, int64_
     }
     L.threads = g.threads;
     if (p.method == PCAL_METHOD_PERIOD_FOLD) {
-        L.lds_bytes = static_cast<int64_t>(fold_lds_bytes(g.npos, g.spv, g.threads, p.M));
+        L.lds_bytes = static_cast<int64_t>(fold_lds_bytes(g.npos, g.spv, g.threads, p.tab_rows));
         L.q0 = g0 % p.Sp;
         L.head_q = n_before % p.Sp;
         L.tail_q = (g0 + L.nvec * g.spv) % p.Sp;
@@ -268,7 +281,9 @@ int64_t plan_device_bytes(const Plan &p) {
                     + b(16, N) + b(16, N)                     // v, tw
                     + b(16, NS) + b(8, NS) + b(8, NS)         // acc, acc_int, accf (two banks)
                     + b(4, 2) + b(8, 2 * (4 * N + 1))         // counters, out
-                    + b(8, N) + b(8, 3 * N + 4) + b(8, N);    // phases, pulse, pulse_int
+                    + b(8, N) + b(8, 3 * N + 4) + b(8, N)     // phases, pulse, pulse_int
+                    + b(8, kMaxRefinePasses + 3);             // refine_out
+    if (fold && p.prec_api == PCAL_PREC_Q17) bytes += b(8, p.R);  // Q17 rotator
     if (!fold) {
         bytes += b(16, kRotLanes);                            // lane factors
         if (p.method == PCAL_METHOD_LUT)
@@ -284,7 +299,7 @@ void fill_info(const Plan &p, pcal_info_t *info) {
     info->joint_period = p.S;
     info->fold_period = p.Sp;
     info->method = p.method;
-    info->precision = p.prec;
+    info->precision = p.prec_api;
     info->block_threads = p.geom.threads;
     info->row_vectors = p.geom.row_vecs;
     info->col_tiles = p.geom.col_tiles;
@@ -310,7 +325,7 @@ int dalloc(pcal_ctx *h, T **p, size_t count) {
 
 void release(pcal_ctx *h) {
     void *ptrs[] = {h->u64, h->u32, h->u16, h->v, h->tw, h->acc_mem, h->acc_int_mem, h->accf_mem, h->counters,
-                    h->out, h->phases, h->pulse, h->pulse_int, h->rot64, h->rot32, h->rot16, h->w};
+                    h->out, h->phases, h->pulse, h->pulse_int, h->refine_out, h->rot64, h->rot32, h->rot16, h->w, h->uq};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->host_out) (void)hipHostFree(h->host_out);
@@ -400,6 +415,11 @@ int build(pcal_ctx *h) {
         phasor(di, p.fs, &br, &bi);
         h->back = make_double2(br, -bi);
         h->c2 = 2.0 * br;
+        // half the row step (rows are an even number of samples), for the magic circle
+        double hr, hi;
+        phasor(static_cast<int64_t>((static_cast<unsigned __int128>(p.fo) * (dn / 2)) % p.fs), p.fs, &hr, &hi);
+        h->half_cos = hr;
+        h->half_sin = -hi;
         if ((rc = dalloc(h, &h->w, kRotLanes))) return rc;
         PCAL_HIP(hipMemcpy(h->w, w.data(), sizeof(double2) * kRotLanes, hipMemcpyHostToDevice));
         if (p.method == PCAL_METHOD_LUT) {
@@ -429,18 +449,22 @@ int build(pcal_ctx *h) {
                 if ((rc = dalloc(h, &h->rot64, R))) return rc;
                 PCAL_HIP(hipMemcpy(h->rot64, td.data(), sizeof(double2) * R, hipMemcpyHostToDevice));
             } else if (p.prec == PCAL_PREC_MIXED) {
+                // (the single-FP16 form keeps only the rounded entry, lo = 0, and
+                // divides no gain out)
+                const bool single16 = p.prec_api == PCAL_PREC_F16;
                 std::vector<__half2> thd(2 * R);
                 std::vector<double2> tr(R);
                 for (int64_t n = 0; n < R; ++n) {
                     const __half2 hi = to_half2(t[n]);
                     const double2 h0 = from_half2(hi);
-                    const __half2 lo = to_half2(make_double2(t[n].x - h0.x, t[n].y - h0.y));
+                    const __half2 lo = to_half2(single16 ? make_double2(0.0, 0.0)
+                                                         : make_double2(t[n].x - h0.x, t[n].y - h0.y));
                     const double2 l0 = from_half2(lo);
                     tr[n] = make_double2(h0.x + l0.x, h0.y + l0.y);
                     thd[2 * slot(n)] = hi;
                     thd[2 * slot(n) + 1] = lo;
                 }
-                table_gain(t, tr, &h->gain_re, &h->gain_im);
+                if (!single16) table_gain(t, tr, &h->gain_re, &h->gain_im);
                 if ((rc = dalloc(h, &h->rot16, 2 * R))) return rc;
                 PCAL_HIP(hipMemcpy(h->rot16, thd.data(), sizeof(__half2) * 2 * R, hipMemcpyHostToDevice));
             } else {
@@ -457,7 +481,7 @@ int build(pcal_ctx *h) {
         (rc = dalloc(h, &h->acc_int_mem, 2 * kAccSlots * N)) || (rc = dalloc(h, &h->accf_mem, 2 * kAccSlots * N)) ||
         (rc = dalloc(h, &h->counters, 2)) || (rc = dalloc(h, &h->out, 2 * (4 * N + 1))) ||
         (rc = dalloc(h, &h->phases, N)) || (rc = dalloc(h, &h->pulse, 3 * N + 4)) ||
-        (rc = dalloc(h, &h->pulse_int, N)))
+        (rc = dalloc(h, &h->pulse_int, N)) || (rc = dalloc(h, &h->refine_out, kMaxRefinePasses + 3)))
         return rc;
     {
         hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->host_out), sizeof(double) * (4 * N + 1),
@@ -481,7 +505,8 @@ int build(pcal_ctx *h) {
         uf[m] = make_float2(static_cast<float>(u[m].x), static_cast<float>(u[m].y));
         uh[2 * m] = to_half2(u[m]);
         const double2 hi = from_half2(uh[2 * m]);
-        uh[2 * m + 1] = to_half2(make_double2(u[m].x - hi.x, u[m].y - hi.y));
+        uh[2 * m + 1] = to_half2(p.prec_api == PCAL_PREC_F16 ? make_double2(0.0, 0.0)
+                                                             : make_double2(u[m].x - hi.x, u[m].y - hi.y));
         const double2 lo = from_half2(uh[2 * m + 1]);
         ur[m] = make_double2(hi.x + lo.x, hi.y + lo.y);
         idx += step_u;
@@ -499,7 +524,26 @@ int build(pcal_ctx *h) {
     // rounded rows change every tone's response by the same known complex gain
     // 1 + gamma, gamma = mean over m of conj(u[m]) * (u16[m] - u[m]) (the rows
     // sum against conj(u[m]) for every tone); the FP64 finalize divides it out.
-    if (fold && p.prec == PCAL_PREC_MIXED) table_gain(u, ur, &h->gain_re, &h->gain_im);
+    // The single-FP16 form (PCAL_PREC_F16) keeps hi alone and divides no gain out.
+    if (fold && p.prec_api == PCAL_PREC_MIXED) table_gain(u, ur, &h->gain_re, &h->gain_im);
+    if (fold && p.prec_api == PCAL_PREC_Q17) {
+        // fixed-point rotator of one period: exp(-j 2 pi (f_o r mod fs) / fs) * 2^17,
+        // each part rounded to the nearest integer (ties to even); the bins then
+        // hold integers times 2^17, which the finalize scales back
+        std::vector<int2> q(p.R);
+        int64_t iq = 0;
+        for (int64_t r = 0; r < p.R; ++r) {
+            double re, im;
+            phasor(iq, p.fs, &re, &im);
+            q[r] = make_int2(static_cast<int>(nearbyint(kFixedScale * re)), static_cast<int>(nearbyint(kFixedScale * im)));
+            iq += p.fo;
+            if (iq >= p.fs) iq -= p.fs;
+        }
+        if ((rc = dalloc(h, &h->uq, p.R))) return rc;
+        PCAL_HIP(hipMemcpy(h->uq, q.data(), sizeof(int2) * p.R, hipMemcpyHostToDevice));
+        h->gain_re = 1.0 / kFixedScale;
+        h->gain_im = 0.0;
+    }
     PCAL_HIP(hipMemcpy(h->u64, u.data(), sizeof(double2) * M, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemcpy(h->u32, uf.data(), sizeof(float2) * M, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemcpy(h->u16, uh.data(), sizeof(__half2) * 2 * M, hipMemcpyHostToDevice));
@@ -612,12 +656,13 @@ FoldArgs fold_args(pcal_ctx *h, const pcal_launch_t &L, const void *dev_ptr) {
     a.prec = p.prec;
     a.int_bins = p.fo == 0 ? 1 : 0;
     a.Sp = p.Sp;
-    a.M = p.M;
+    a.M = p.tab_rows;
     a.q0 = L.q0;
     a.u64 = h->u64;
     a.u32 = h->u32;
     a.u16 = h->u16;
     a.v = h->v;
+    a.uq = h->uq;
     a.head = static_cast<const uint8_t *>(dev_ptr);
     a.head_bytes = static_cast<int>(L.head_bytes);
     a.head_q = L.head_q;
@@ -657,7 +702,7 @@ int create(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int meth
         // adds an epilogue and N atomics of its own)
         int cus = 0;
         const int per_cu = fold_blocks_per_cu(p.nbits, p.prec, p.geom.threads,
-                                              fold_lds_bytes(p.geom.npos, p.geom.spv, p.geom.threads, p.M));
+                                              fold_lds_bytes(p.geom.npos, p.geom.spv, p.geom.threads, p.tab_rows));
         const int waves = (p.geom.threads + 63) / 64;
         const int use = std::min(per_cu, std::max(1, (kMinResidentWaves + waves - 1) / waves));
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
@@ -784,6 +829,8 @@ int pcal_extract_timed(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_str
         a.w = h->w;
         a.back = h->back;
         a.c2 = h->c2;
+        a.half_sin = h->half_sin;
+        a.half_cos = h->half_cos;
         a.head = static_cast<const uint8_t *>(dev_ptr);
         a.head_bytes = static_cast<int>(L.head_bytes);
         a.head_n = L.head_q;
@@ -882,14 +929,12 @@ int pcal_spectrum(pcal_t h, double *re, double *im) {
 // Run the pulse readout kernel on the handle's last stream and copy its
 // results (2N + 4 doubles, 3N + 4 with the band-pass of spec, and the integer
 // bins when host_int is set) to the host.
-static int read_pulse(pcal_ctx *h, double *host, long long *host_int, const double *spec = nullptr) {
+static PulseArgs pulse_args(pcal_ctx *h, bool ints, const double *spec) {
     const Plan &p = h->plan;
-    const size_t N = static_cast<size_t>(p.N);
-    hipStream_t s = h->last_stream;
     PulseArgs a{};
     a.acc = h->acc;
     a.accf = h->accf;
-    a.acc_int = host_int ? h->acc_int : nullptr;
+    a.acc_int = ints ? h->acc_int : nullptr;
     a.N = static_cast<int>(p.N);
     a.prec = p.prec;
     a.sideband = p.sideband;
@@ -898,11 +943,17 @@ static int read_pulse(pcal_ctx *h, double *host, long long *host_int, const doub
     a.gain_re = h->gain_re;
     a.gain_im = h->gain_im;
     a.out = h->pulse;
-    a.out_int = host_int ? h->pulse_int : nullptr;
+    a.out_int = ints ? h->pulse_int : nullptr;
     a.spec = spec;
     a.f_offset = static_cast<double>(p.fo);
     a.f_comb = static_cast<double>(p.fc);
-    launch_pulse(a, s);
+    return a;
+}
+
+static int read_pulse(pcal_ctx *h, double *host, long long *host_int, const double *spec = nullptr) {
+    const size_t N = static_cast<size_t>(h->plan.N);
+    hipStream_t s = h->last_stream;
+    launch_pulse(pulse_args(h, host_int != nullptr, spec), s);
     PCAL_HIP(hipGetLastError());
     PCAL_HIP(hipMemcpyAsync(host, h->pulse, sizeof(double) * ((spec ? 3 : 2) * N + 4), hipMemcpyDeviceToHost, s));
     if (host_int) PCAL_HIP(hipMemcpyAsync(host_int, h->pulse_int, sizeof(long long) * N, hipMemcpyDeviceToHost, s));
@@ -951,6 +1002,36 @@ int pcal_bandpass(pcal_t h, double *amp, double *phase, double *delay) {
     if (amp) memcpy(amp, h->host_out, sizeof(double) * N);
     if (phase) memcpy(phase, out.data() + 2 * N + 4, sizeof(double) * N);
     if (delay) *delay = out[2 * N];
+    return PCAL_OK;
+}
+
+int pcal_refine(pcal_t h, int iters, double *delays, double *resid) {
+    if (!h || iters < 1 || iters > kMaxRefinePasses) return PCAL_EINVAL;
+    DeviceGuard guard(h->device);
+    // the finalize leaves the reported spectrum in h->out, the pulse readout its peak delay in h->pulse
+    int rc = run_finalize(h);
+    if (rc) return rc;
+    hipStream_t s = h->last_stream;
+    launch_pulse(pulse_args(h, false, nullptr), s);
+    PCAL_HIP(hipGetLastError());
+    const FinArgs f = fin_args(h, h->out);
+    RefineArgs r{};
+    r.spec = h->out + 2 * h->plan.N;
+    r.t0 = h->pulse + 2 * h->plan.N;
+    r.N = static_cast<int>(h->plan.N);
+    r.k_lo = f.k_lo;
+    r.k_hi = f.k_hi;
+    r.iters = iters;
+    r.f_offset = static_cast<double>(h->plan.fo);
+    r.f_comb = static_cast<double>(h->plan.fc);
+    r.out = h->refine_out;
+    launch_refine(r, s);
+    PCAL_HIP(hipGetLastError());
+    double out[kMaxRefinePasses + 3];
+    PCAL_HIP(hipMemcpyAsync(out, h->refine_out, sizeof(double) * (iters + 3), hipMemcpyDeviceToHost, s));
+    PCAL_HIP(hipStreamSynchronize(s));
+    if (delays) memcpy(delays, out, sizeof(double) * (iters + 1));
+    if (resid) memcpy(resid, out + iters + 1, sizeof(double) * 2);
     return PCAL_OK;
 }
 

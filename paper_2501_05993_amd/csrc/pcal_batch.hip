@@ -177,6 +177,8 @@ int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, double *c
     return mark_members(b, count, ids, s);
 }
 
+int batch_threads(const pcal_batch_ctx *b) { return b->threads; }
+
 // Destroy member id (after its work) and free its slot for reuse.
 int batch_release(pcal_batch_ctx *b, int id) {
     if (!b || id < 0 || id >= static_cast<int>(b->members.size()) || !b->members[id]) return PCAL_EINVAL;
@@ -191,7 +193,8 @@ int batch_release(pcal_batch_ctx *b, int id) {
 extern "C" {
 
 int pcal_batch_create(int max_streams, int precision, pcal_batch_t *out) {
-    if (!out || max_streams <= 0 || precision < PCAL_PREC_F64 || precision > PCAL_PREC_F32) return PCAL_EINVAL;
+    if (!out || max_streams <= 0 || precision < PCAL_PREC_F64 || precision > PCAL_PREC_Q17) return PCAL_EINVAL;
+    if (precision == PCAL_PREC_Q17) return PCAL_ENOTSUP;  // the fixed-point form runs on single handles
     *out = nullptr;
     pcal_batch_ctx *b = new (std::nothrow) pcal_batch_ctx();
     if (!b) return PCAL_ENOMEM;
@@ -321,11 +324,11 @@ int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *co
     first[n] = grid;
     if (inl) {
         il.n = n;
-        launch_fold_batch(il, b->prec, grid2, grid - grid2, threads, lds[0], lds[1], s);
+        launch_fold_batch(il, kernel_prec(b->prec), grid2, grid - grid2, threads, lds[0], lds[1], s);
         PCAL_HIP(hipGetLastError());
     } else {
         PCAL_HIP(st->upload(n + 1, sizeof(FoldArgs) * n, b->up, s));
-        launch_fold_batch(DeviceList<FoldArgs>{st->d_items<FoldArgs>(), st->d_first(), n}, b->prec, grid2,
+        launch_fold_batch(DeviceList<FoldArgs>{st->d_items<FoldArgs>(), st->d_first(), n}, kernel_prec(b->prec), grid2,
                           grid - grid2, threads, lds[0], lds[1], s);
         PCAL_HIP(hipGetLastError());
         PCAL_HIP(hipEventRecord(st->done, s));

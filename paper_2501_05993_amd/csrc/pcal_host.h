@@ -13,6 +13,8 @@ namespace pcal {
 namespace host {
 
 void set_error(const char *what, hipError_t e);
+// A library error text for pcal_last_error() (no HIP status involved).
+void set_message(const char *what);
 
 #define PCAL_HIP(call)                      \
     do {                                    \
@@ -24,12 +26,20 @@ void set_error(const char *what, hipError_t e);
     } while (0)
 
 int64_t gcd64(int64_t a, int64_t b);
+// Kernel arithmetic of a precision form: the single-FP16 form is the mixed
+// form's arithmetic with single-term table entries.
+// Fixed-point rotator scale: 17 fractional bits (PCAL_PREC_Q17).
+constexpr double kFixedScale = 131072.0;
+inline int kernel_prec(int prec) { return prec == PCAL_PREC_F16 ? PCAL_PREC_MIXED : prec == PCAL_PREC_Q17 ? 3 : prec; }
 void phasor(int64_t num, int64_t den, double *re, double *im);
 
 struct Plan {
     int64_t fs, fc, fo;
-    int nbits, sideband, method, prec;
+    int nbits, sideband, method;
+    int prec;      // arithmetic of the kernels (F64, MIXED or F32; the single-FP16 form runs MIXED's)
+    int prec_api;  // enum pcal_precision as requested
     int64_t N, R, S, Sp, M;
+    int64_t tab_rows;  // entries of the fold's rotator table: M (factorised forms) or R (fixed-point form)
     FoldGeom geom;
     int target_blocks;
     int sync_pairs;   // fold walk: workgroup barrier every sync_pairs pairs of groups (0: none)
@@ -84,6 +94,7 @@ struct pcal_ctx {
     double2 *u64 = nullptr;
     float2 *u32 = nullptr;
     __half2 *u16 = nullptr;
+    int2 *uq = nullptr;            // fixed-point form: Q17 rotator of one period [R]
     double2 *v = nullptr;
     double2 *tw = nullptr;
     // Integration accumulators in two banks; acc / acc_int / accf point at the
@@ -106,6 +117,7 @@ struct pcal_ctx {
     double *phases = nullptr;      // [N] phases the last finalize workgroup reads back
     double *pulse = nullptr;       // [2N + 4] pulse readout (PulseArgs::out)
     long long *pulse_int = nullptr;  // [N] integer bins of the readout
+    double *refine_out = nullptr;  // [kMaxRefinePasses + 3] delay refinement (RefineArgs::out)
     unsigned *counters = nullptr;  // [0] finalize of bank 0's pending form / plain, [1] bank 1
     double *out = nullptr;         // device results [2][4N + 1]
     double *host_out = nullptr;    // pinned copy
@@ -115,6 +127,7 @@ struct pcal_ctx {
     double2 *w = nullptr;          // [16] lane factors (per-sample forms)
     double2 back = {1.0, 0.0};     // exp(+j w_o * samples per row)
     double c2 = 2.0;               // 2 cos(w_o * samples per row)
+    double half_sin = 0.0, half_cos = 1.0;  // sin, cos of half that row step (magic circle)
     double gain_re = 1.0, gain_im = 0.0;  // 1 / (1 + gamma) of the FP16 table (mixed form)
     int64_t n_total = 0;
     int64_t n_integ = 0;
@@ -169,6 +182,8 @@ int env_int(const char *name, int dflt);
 // memory allowed), or null for h->out; outs itself may be null.
 int batch_finalize_async(pcal_batch_ctx *b, int count, const int *ids, double *const *outs, hipStream_t s);
 int batch_release(pcal_batch_ctx *b, int id);
+// Workgroup size the batch plans its members for.
+int batch_threads(const pcal_batch_ctx *b);
 
 }  // namespace host
 }  // namespace pcal

@@ -107,6 +107,17 @@ struct PulseArgs {
     double f_offset, f_comb;   // Hz: tone k is at f_offset + k f_comb
 };
 
+// Arguments of the multi-pass delay refinement (one workgroup): the reported
+// spectrum of the integration and the pulse-peak delay it starts from.
+struct RefineArgs {
+    const double *spec;        // [2N] device: Re C[N], Im C[N] as reported
+    const double *t0;          // device address of the starting delay (s)
+    int N, k_lo, k_hi;         // tones; in-band tones [k_lo, k_hi): 0 < f_k < fs/2
+    int iters;                 // passes, >= 1
+    double f_offset, f_comb;   // Hz: tone k is at f_offset + k f_comb
+    double *out;               // [iters + 3]: delays t_0 .. t_iters (s), intercept (rad), rms residual (rad)
+};
+
 // Arguments of the fused unpack-rotate-fold kernel (one launch per pcal_extract).
 struct FoldArgs {
     const uint4 *data;       // 16-byte aligned start of the full vectors
@@ -126,6 +137,7 @@ struct FoldArgs {
     const float2 *u32;       // same, rounded to FP32
     const __half2 *u16;      // [2M]: u[m] ~ u16[2m] + u16[2m+1] (FP16 rounded, then its residual)
     const double2 *v;        // v[b] = exp(-j w_o b), b < N  (FP64)
+    const int2 *uq;          // fixed-point form: exp(-j w_o r) * 2^17 rounded, r < R (then M = R)
     // Samples outside the full vectors (misaligned head, short tail), <= 15 bytes each.
     const uint8_t *head;
     int head_bytes;
@@ -175,6 +187,7 @@ struct RotArgs {
     const double2 *w;        // [16] lane factors exp(-j w_o i)
     double2 back;            // exp(+j w_o * samples per row): one row back, FP64
     double c2;               // 2 cos(w_o * samples per row), recurrence coefficient (FP32 forms round it)
+    double half_sin, half_cos;  // sin and cos of half the row step (magic circle)
     const uint8_t *head;
     int head_bytes;
     int64_t head_n;          // global index of the first head sample
@@ -191,6 +204,53 @@ void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds
                  hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // Fold workgroups of the given shape resident at once on one compute unit (0 on error).
 int fold_blocks_per_cu(int nbits, int prec, int threads, size_t lds);
+// ---- Device-resident served loop (pcal_server_start) ----------------------
+//
+// One chunk of a served stream as the host publishes it in the work ring
+// (pinned, coherent host memory): the chunk's fold, planned for at most
+// `tasks` workgroups, and, when the chunk completes an integration, that
+// integration's finalize.  seq (chunk index + 1) is written last.
+struct ServedDesc {
+    FoldArgs fold;
+    FinArgs fin;
+    int sid;          // stream slot of the server
+    int bank;         // accumulator bank of the integration
+    int ntasks;       // fold workgroups of the chunk (<= the kernel's tasks per chunk)
+    int fin_total;    // tasks of the whole integration if this chunk completes it, else 0
+    long long integ;  // integration index (completion record)
+    unsigned long long seq;
+};
+
+// A finished integration, written by the device into the completion ring;
+// seq = record index + 1, written last.
+struct ServedDone {
+    int sid;
+    int pad;
+    long long integ;
+    unsigned long long seq;
+};
+
+// Arguments of the persistent served kernel.
+struct ServedArgs {
+    const ServedDesc *ring;      // [cap] work ring (host memory, device address)
+    unsigned long long *slot_free;  // [cap] host memory: chunk index + 1 of the last chunk whose tasks all ended
+    ServedDone *done;            // [done_cap] completion ring (host memory)
+    const int *quit;             // host memory: nonzero asks every workgroup to leave once its wait finds no work
+    int *status;                 // host memory: [0] workgroups that left, [1] workgroups that left on the spin limit
+    unsigned long long *cursor;  // device: next task index to claim
+    unsigned long long *done_cursor;  // device: next completion record
+    unsigned *slot_cnt;          // device [cap]: tasks of the chunk in the slot that ended
+    unsigned *task_done;         // device [streams][2]: tasks of the integration in the bank that ended
+    unsigned *fin_total;         // device [streams][2]: tasks of that integration, once its last chunk is known
+    int cap, done_cap, tasks;    // ring slots, completion records, tasks (workgroups) per chunk
+    unsigned long long spin_limit;  // polls of an empty ring slot before a workgroup leaves
+};
+
+void launch_served(const ServedArgs &a, int prec, int grid, int threads, size_t lds, hipStream_t s);
+constexpr int kServedThreads = 512;          // the batched form's member workgroup size
+constexpr size_t kServedLds = 61440;         // fold geometries up to 12800 positions, finalize up to 1792 tones
+constexpr int kServedMaxTones = 1792;
+
 // Work-lists of the batched kernels: item i owns workgroups [first[i],
 // first[i + 1]).  A list in device memory (copied there before the launch),
 // or a short one carried in the kernel arguments (no copy).
@@ -222,6 +282,8 @@ void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStrea
                    hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_finalize(const FinArgs &a, hipStream_t s);
 void launch_pulse(const PulseArgs &a, hipStream_t s);
+void launch_refine(const RefineArgs &a, hipStream_t s);
+constexpr int kMaxRefinePasses = 16;
 size_t finalize_lds_bytes(int N);
 void launch_finalize_batch(const DeviceList<FinArgs> &list, int grid, size_t lds, hipStream_t s);
 void launch_finalize_batch(const FinListInline &list, int grid, size_t lds, hipStream_t s);

@@ -288,10 +288,12 @@ struct Walk8 {
 
 // ---------------------------------------------------------------- per-workgroup bins
 
-// A partial bin sum in the arithmetic of one precision form (enum pcal_precision):
+// A partial bin sum in the arithmetic of one precision form (the kernels'
+// form: enum pcal_precision, with PCAL_PREC_F16 run as 1 and PCAL_PREC_Q17 as 3):
 //   0 (F64):   FP64 table, FP64 products and sums;
 //   1 (MIXED): two-term FP16 table (hi + lo, held as FP32), FP32 products, Kahan-compensated FP32 sums;
-//   2 (F32):   FP32 table, plain FP32 products and sums.
+//   2 (F32):   FP32 table, plain FP32 products and sums;
+//   3 (Q17):   integer full-period table, integer products, int64 sums.
 // si carries the exact integer sum (the Eq. 2 bin when f_offset = 0).
 template <int PREC>
 struct BinAcc;
@@ -359,9 +361,34 @@ struct BinAcc<2> {
     __device__ __forceinline__ double2 value() const { return make_double2(sr, sm); }
 };
 
+// Fixed-point form (3): the full-period rotator table in Q17 integers
+// (Section 4.8's integer rotator), integer products and exact int64 sums.
+// value() is the integer bin sum, exact in FP64 below 2^53; the finalize
+// scales it by 2^-17.
+template <>
+struct BinAcc<3> {
+    using Tab = int2;
+    long long sr = 0, sm = 0, si = 0;
+    __device__ __forceinline__ void add(int f, Tab u) {
+        sr += static_cast<long long>(f) * u.x;
+        sm += static_cast<long long>(f) * u.y;
+        si += f;
+    }
+    __device__ __forceinline__ void merge(const BinAcc &o) {
+        sr += o.sr;
+        sm += o.sm;
+        si += o.si;
+    }
+    __device__ __forceinline__ double2 value() const {
+        return make_double2(static_cast<double>(sr), static_cast<double>(sm));
+    }
+};
+
 template <int PREC>
 __device__ __forceinline__ typename BinAcc<PREC>::Tab table_row(const FoldArgs &a, int m) {
-    if constexpr (PREC == 0)
+    if constexpr (PREC == 3)
+        return load_global(a.uq + m);
+    else if constexpr (PREC == 0)
         return load_global(a.u64 + m);
     else if constexpr (PREC == 1) {
         // two FP16 terms; their FP32 sum is exact
@@ -387,6 +414,12 @@ __device__ __forceinline__ void commit_bin(const FoldArgs &a, int wg, int b, con
         const float vr = static_cast<float>(v.x), vi = static_cast<float>(v.y);
         unsafeAtomicAdd(&a.accf[k].x, qr * vr - qi * vi);
         unsafeAtomicAdd(&a.accf[k].y, qr * vi + qi * vr);
+    } else if constexpr (PREC == 3) {
+        // the table holds the whole rotator: no column factor; integer-valued
+        // FP64 adds stay exact below 2^53, in any order
+        (void)v;
+        unsafeAtomicAdd(&a.acc[k].x, Q.x);
+        unsafeAtomicAdd(&a.acc[k].y, Q.y);
     } else {
         unsafeAtomicAdd(&a.acc[k].x, Q.x * v.x - Q.y * v.y);
         unsafeAtomicAdd(&a.acc[k].y, Q.x * v.y + Q.y * v.x);
@@ -420,7 +453,7 @@ __device__ void add_edges(const FoldArgs &a, int b, BinAcc<PREC> &q, const Tab *
         int qb = static_cast<int>(qq % a.N);
         for (int i = 0; i < ns; ++i) {
             if (qb == b) {
-                const int m = static_cast<int>(qq / a.N);
+                const int m = static_cast<int>(PREC == 3 ? qq % a.M : qq / a.N);
                 q.add(level_of(src, a.nbits, i), u_lds ? UL[m] : table_row<PREC>(a, m));
             }
             if (++qq == a.Sp) qq = 0;
@@ -522,12 +555,15 @@ __device__ __forceinline__ void fold_body(const FoldArgs &a, const int wg, unsig
             int p = b >= qbN ? b - qbN : b - qbN + N;
             int q = qb + p;
             if (q >= Sp) q -= Sp;
-            int m = q / N;
+            // table entry of position q: the rotator row q / N (factorised
+            // forms) or the rotator itself at q mod R (fixed-point form)
+            int m = PREC == 3 ? q % M : q / N;
+            const int step_m = PREC == 3 ? N % M : 1;
             Acc acc;
             if (u_lds)
-                rotate_bin<SPV>(acc, F, p, m, N, 1, a.npos, M, [&](int mm) { return UL[mm]; });
+                rotate_bin<SPV>(acc, F, p, m, N, step_m, a.npos, M, [&](int mm) { return UL[mm]; });
             else
-                rotate_bin<SPV>(acc, F, p, m, N, 1, a.npos, M, [&](int mm) { return table_row<PREC>(a, mm); });
+                rotate_bin<SPV>(acc, F, p, m, N, step_m, a.npos, M, [&](int mm) { return table_row<PREC>(a, mm); });
             if (edges) add_edges<PREC>(a, b, acc, UL, u_lds);
             commit_bin<PREC>(a, wg, b, acc, load_global(a.v + b));
         }
@@ -541,8 +577,8 @@ __device__ __forceinline__ void fold_body(const FoldArgs &a, const int wg, unsig
             int p = (b >= qbN ? b - qbN : b - qbN + N) + N * gi;
             int q = qb + p;
             if (q >= Sp) q -= Sp;
-            int m = q / N;
-            const int step_m = G % M, step_p = N * G;
+            int m = PREC == 3 ? q % M : q / N;
+            const int step_p = N * G, step_m = PREC == 3 ? step_p % M : G % M;
             if (u_lds)
                 rotate_bin<SPV>(acc, F, p, m, step_p, step_m, a.npos, M, [&](int mm) { return UL[mm]; });
             else
@@ -813,6 +849,119 @@ __global__ void __launch_bounds__(256) finalize_batch_kernel(const List list) {
     finalize_body(a, wg - list_first(list, i), (a.N + 63) / 64, lds);
 }
 
+// ---------------------------------------------------------------- served loop
+
+// Copy n 32-bit words from coherent host memory with system-scope loads (the
+// host may have written them after this kernel started).
+__device__ __forceinline__ void copy_from_host(uint32_t *dst, const uint32_t *src, int n) {
+    for (int i = static_cast<int>(threadIdx.x); i < n; i += blockDim.x)
+        dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Persistent kernel of the served form: every workgroup claims tasks in
+// increasing order (task t is workgroup t mod tasks of chunk t / tasks),
+// waits for the chunk's descriptor to be published in the work ring, runs its
+// share of the chunk's fold into the stream's accumulator bank, and counts
+// the task.  The task that completes an integration (its count reaches the
+// integration's total, which the integration's last chunk records before
+// counting) runs that integration's finalize alone, then writes a completion
+// record.  No workgroup ever waits for another: a wait is only for the host
+// to publish, and it ends when the host sets quit or after spin_limit polls.
+template <int PREC>
+__global__ void __launch_bounds__(kServedThreads) served_kernel(ServedArgs sa) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ __align__(16) ServedDesc d;
+    __shared__ unsigned long long s_task;
+    __shared__ int s_go, s_fin;
+    const int t = static_cast<int>(threadIdx.x);
+    for (;;) {
+        if (t == 0) {
+            const unsigned long long task = atomicAdd(sa.cursor, 1ull);
+            const unsigned long long chunk = task / static_cast<unsigned>(sa.tasks);
+            const ServedDesc *slot = sa.ring + chunk % static_cast<unsigned>(sa.cap);
+            int go = 0;
+            for (unsigned long long spin = 0; spin < sa.spin_limit; ++spin) {
+                if (__hip_atomic_load(&slot->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == chunk + 1) {
+                    go = 1;
+                    break;
+                }
+                if (__hip_atomic_load(sa.quit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                    go = -1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(32);
+            }
+            s_task = task;
+            s_go = go;
+        }
+        __syncthreads();
+        if (s_go != 1) {
+            if (t == 0) {
+                __hip_atomic_fetch_add(sa.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (s_go == 0) __hip_atomic_fetch_add(sa.status + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            return;
+        }
+        const unsigned long long task = s_task;
+        const unsigned long long chunk = task / static_cast<unsigned>(sa.tasks);
+        const int wg = static_cast<int>(task % static_cast<unsigned>(sa.tasks));
+        const int slot = static_cast<int>(chunk % static_cast<unsigned>(sa.cap));
+        copy_from_host(reinterpret_cast<uint32_t *>(&d), reinterpret_cast<const uint32_t *>(sa.ring + slot),
+                       static_cast<int>(sizeof(ServedDesc) / 4));
+        __syncthreads();
+        if (wg < d.ntasks) {
+            if (d.fold.nbits == 2)
+                fold_body<2, PREC>(d.fold, wg, lds);
+            else
+                fold_body<8, PREC>(d.fold, wg, lds);
+        }
+        // every wave's atomics are acknowledged before the task is counted
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (t == 0) {
+            unsigned *done = sa.task_done + 2 * d.sid + d.bank;
+            unsigned *total = sa.fin_total + 2 * d.sid + d.bank;
+            if (d.fin_total > 0) __hip_atomic_store(total, static_cast<unsigned>(d.fin_total), __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned v = __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            const unsigned want = __hip_atomic_load(total, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            s_fin = (want != 0u && v == want) ? 1 : 0;
+            // the ring slot is free for the host once every task of its chunk ended
+            const unsigned c = __hip_atomic_fetch_add(sa.slot_cnt + slot, 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            if (c == static_cast<unsigned>(sa.tasks)) {
+                __hip_atomic_store(sa.slot_cnt + slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(sa.slot_free + slot, chunk + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        __syncthreads();
+        if (s_fin) {
+            // the whole integration is in the bank: finalize it here, every
+            // part in turn (read, DFT, results into the stream's pinned slot,
+            // clear the bank), then report it
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const int nwg = (d.fin.N + 63) / 64;
+            for (int part = 0; part < nwg; ++part) {
+                finalize_body(d.fin, part, nwg, lds);
+                __syncthreads();
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            if (t == 0) {
+                __hip_atomic_store(sa.task_done + 2 * d.sid + d.bank, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(sa.fin_total + 2 * d.sid + d.bank, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+                const unsigned long long k = atomicAdd(sa.done_cursor, 1ull);
+                ServedDone *r = sa.done + k % static_cast<unsigned>(sa.done_cap);
+                __hip_atomic_store(&r->sid, d.sid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&r->integ, d.integ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&r->seq, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Zero a list of buffers (one workgroup per buffer, grid-stride inside).
 __global__ void zero_list_kernel(const ZeroItem *items, int n) {
     for (int j = blockIdx.x; j < n; j += gridDim.x) {
@@ -844,11 +993,13 @@ void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds
     if (nbits == 2) {
         if (a.prec == 0) PCAL_FOLD(2, 0);
         else if (a.prec == 1) PCAL_FOLD(2, 1);
-        else PCAL_FOLD(2, 2);
+        else if (a.prec == 2) PCAL_FOLD(2, 2);
+        else PCAL_FOLD(2, 3);
     } else {
         if (a.prec == 0) PCAL_FOLD(8, 0);
         else if (a.prec == 1) PCAL_FOLD(8, 1);
-        else PCAL_FOLD(8, 2);
+        else if (a.prec == 2) PCAL_FOLD(8, 2);
+        else PCAL_FOLD(8, 3);
     }
 #undef PCAL_FOLD
 }
@@ -856,13 +1007,15 @@ void launch_fold(const FoldArgs &a, int nbits, int grid, int threads, size_t lds
 int fold_blocks_per_cu(int nbits, int prec, int threads, size_t lds) {
     const void *f = nullptr;
     if (nbits == 2)
-        f = prec == 0 ? reinterpret_cast<const void *>(&fold_kernel<2, 0>)
+        f = prec == 0   ? reinterpret_cast<const void *>(&fold_kernel<2, 0>)
             : prec == 1 ? reinterpret_cast<const void *>(&fold_kernel<2, 1>)
-                        : reinterpret_cast<const void *>(&fold_kernel<2, 2>);
+            : prec == 2 ? reinterpret_cast<const void *>(&fold_kernel<2, 2>)
+                        : reinterpret_cast<const void *>(&fold_kernel<2, 3>);
     else
-        f = prec == 0 ? reinterpret_cast<const void *>(&fold_kernel<8, 0>)
+        f = prec == 0   ? reinterpret_cast<const void *>(&fold_kernel<8, 0>)
             : prec == 1 ? reinterpret_cast<const void *>(&fold_kernel<8, 1>)
-                        : reinterpret_cast<const void *>(&fold_kernel<8, 2>);
+            : prec == 2 ? reinterpret_cast<const void *>(&fold_kernel<8, 2>)
+                        : reinterpret_cast<const void *>(&fold_kernel<8, 3>);
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, threads, lds) != hipSuccess) return 0;
     return n;
@@ -891,6 +1044,15 @@ void launch_fold_batch_list(const List &list, int prec, int grid2, int grid8, in
             PCAL_BATCH_LAUNCH(8, 2, grid8, lds8, grid2);
     }
 #undef PCAL_BATCH_LAUNCH
+}
+
+void launch_served(const ServedArgs &a, int prec, int grid, int threads, size_t lds, hipStream_t s) {
+    if (prec == 0)
+        hipLaunchKernelGGL(served_kernel<0>, dim3(grid), dim3(threads), lds, s, a);
+    else if (prec == 1)
+        hipLaunchKernelGGL(served_kernel<1>, dim3(grid), dim3(threads), lds, s, a);
+    else
+        hipLaunchKernelGGL(served_kernel<2>, dim3(grid), dim3(threads), lds, s, a);
 }
 
 void launch_fold_batch(const DeviceList<FoldArgs> &list, int prec, int grid2, int grid8, int threads, size_t lds2,

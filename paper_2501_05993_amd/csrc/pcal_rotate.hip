@@ -3,9 +3,11 @@
 // The rotator comes either from a precomputed table of one rotator period
 // (Eq. 4, the precomputed method of Section 4.1), from the direct-form
 // resonator recurrence y[r+1] = 2 cos(d) y[r] - y[r-1] (Eq. 6-7, the
-// oscillator method) or from the coupled-form oscillator z[r+1] = z[r]
-// exp(-j d) (the first of the recursions Section 2.2 lists); both recurrences
-// are re-seeded exactly at fixed intervals.
+// oscillator method), from the coupled-form oscillator z[r+1] = z[r]
+// exp(-j d) or the magic-circle oscillator (the first two recursions Section
+// 2.2 lists), or from the resonator with truncation-error feedback (one of the
+// remedies Section 2.2 names for the resonator's rounding); every recurrence is
+// re-seeded exactly at fixed intervals.
 //
 // Layout.  A thread owns 16 consecutive samples of every row (one 16-byte
 // load at 8-bit, one 4-byte load at 2-bit); rows are a multiple of N samples,
@@ -149,8 +151,18 @@ struct LaneTot<2> {
     __device__ __forceinline__ double2 get(int k) const { return make_double2(r[k], i[k]); }
 };
 
-// Row rotator source: table (METHOD 2), direct-form resonator (METHOD 3) or
-// coupled-form oscillator (METHOD 4), in the arithmetic of the precision form.
+// Exact sum s + e of two values (Knuth's two-sum): s = fl(a + b).
+template <class T>
+__device__ __forceinline__ void two_sum(T a, T b, T &s, T &e) {
+    s = a + b;
+    const T bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Row rotator source: table (METHOD 2), direct-form resonator (METHOD 3),
+// coupled-form oscillator (METHOD 4), magic-circle oscillator (METHOD 5) or
+// the direct-form resonator with error feedback (METHOD 6), in the arithmetic
+// of the precision form.
 template <int METHOD, int PREC>
 struct RowRot {
     using T = real_t<PREC>;
@@ -158,8 +170,17 @@ struct RowRot {
     int64_t idx = 0, step = 0, R = 1;
     // recurrence state: the DFR runs the same two-term recurrence on the real
     // and imaginary parts (c2 = 2 cos d); the CFO multiplies the rotator by
-    // m = exp(-j d) each row (d = w_o times the samples per row)
+    // m = exp(-j d) each row (d = w_o times the samples per row).  The MCO
+    // keeps x = cos a and y = -sin(a + d/2) of the row angle a in zr, pr
+    // (and zi unused) and steps x += eps y, y -= eps x with eps = 2 sin(d/2)
+    // (the second update uses the new x); the rotator is x - j sin a with
+    // -sin a = (y + x sin(d/2)) / cos(d/2).  The error-feedback DFR keeps each
+    // state value as an unevaluated sum hi + lo (zr + zlr, pr + plr, ...) and
+    // the coefficient as c2 + c2l: every step's rounding error, taken exactly
+    // by error-free transformations, is fed back into the next step.
     T zr = 0, zi = 0, pr = 0, pi = 0, c2 = 0, mr = 0, mi = 0;
+    T zlr = 0, zli = 0, plr = 0, pli = 0, c2l = 0;  // error-feedback parts
+    T eps = 0, hs = 0, ihc = 0;                      // magic circle: 2 sin(d/2), sin(d/2), 1 / cos(d/2)
     int64_t n = 0, dn = 0;  // global index of the row's first lane sample, row stride in samples
 
     __device__ __forceinline__ cplx<T> table(const RotArgs &a, int64_t n) const {
@@ -181,13 +202,41 @@ struct RowRot {
         }
     }
     // exact seed at global sample n (recurrence): z(n) and z(n - dn) in FP64, rounded once
+    // (the magic circle: cos a and -sin(a + d/2), the rotator at n + dn / 2)
     __device__ __forceinline__ void seed(const RotArgs &a) {
         const double2 z = exact_rotator(n, a.fs, a.fo);
+        if constexpr (METHOD == 5) {
+            const double2 zh = exact_rotator(n + dn / 2, a.fs, a.fo);
+            zr = static_cast<T>(z.x);
+            pr = static_cast<T>(zh.y);
+            return;
+        }
         const double2 zp = make_double2(z.x * a.back.x - z.y * a.back.y, z.x * a.back.y + z.y * a.back.x);
         zr = static_cast<T>(z.x);
         zi = static_cast<T>(z.y);
         pr = static_cast<T>(zp.x);
         pi = static_cast<T>(zp.y);
+        if constexpr (METHOD == 6) {
+            zlr = static_cast<T>(z.x - static_cast<double>(zr));
+            zli = static_cast<T>(z.y - static_cast<double>(zi));
+            plr = static_cast<T>(zp.x - static_cast<double>(pr));
+            pli = static_cast<T>(zp.y - static_cast<double>(pi));
+        }
+    }
+    // one error-feedback resonator step on one component: (y, yl) <- c2 (y, yl) - (yp, ypl)
+    __device__ __forceinline__ void ef_step(T &y, T &yl, T &yp, T &ypl) const {
+        const T ph = c2 * y;
+        T pl = mad(c2, y, -ph);                    // exact low part of the product c2 * y
+        pl = mad(c2, yl, mad(c2l, y, pl));         // + the small cross terms
+        T sh, sl;
+        two_sum(ph, -yp, sh, sl);                  // exact sum of the large parts
+        const T low = sl + (pl - ypl);
+        const T hi = sh + low;                     // renormalise: the rounding error stays in lo
+        const T lo = low - (hi - sh);
+        yp = y;
+        ypl = yl;
+        y = hi;
+        yl = lo;
     }
     // rotators of the next U rows, then move U rows on
     template <int U>
@@ -206,12 +255,21 @@ struct RowRot {
                 pi = zi;
                 zr = nr;
                 zi = ni;
-            } else {
+            } else if constexpr (METHOD == 4) {
                 z[u] = {zr, zi};
                 // coupled form: a complex multiply by exp(-j d) per row
                 const T nr = mad(zr, mr, -zi * mi), ni = mad(zr, mi, zi * mr);
                 zr = nr;
                 zi = ni;
+            } else if constexpr (METHOD == 5) {
+                // magic circle (Section 2.2's modified coupled form): x = zr, y = pr
+                z[u] = {zr, mad(zr, hs, pr) * ihc};
+                zr = mad(eps, pr, zr);
+                pr = mad(-eps, zr, pr);
+            } else {
+                z[u] = {zr + zlr, zi + zli};
+                ef_step(zr, zlr, pr, plr);
+                ef_step(zi, zli, pi, pli);
             }
         }
         n += U * dn;
@@ -248,8 +306,12 @@ __global__ void __launch_bounds__(kMaxRotThreads) rot_kernel(RotArgs a) {
             rot.idx = rot.n % a.R;
         } else {
             rot.c2 = static_cast<T>(a.c2);
+            rot.c2l = static_cast<T>(a.c2 - static_cast<double>(rot.c2));
             rot.mr = static_cast<T>(a.back.x);   // exp(-j d) = conj(exp(+j d))
             rot.mi = static_cast<T>(-a.back.y);
+            rot.eps = static_cast<T>(2.0 * a.half_sin);
+            rot.hs = static_cast<T>(a.half_sin);
+            rot.ihc = static_cast<T>(1.0 / a.half_cos);
             rot.seed(a);
         }
         LaneTot<PREC> tot;
@@ -356,23 +418,26 @@ void launch_rotate(const RotArgs &a, int grid, int threads, size_t lds, hipStrea
         else                                                                                 \
             hipLaunchKernelGGL((rot_kernel<NB, ME, PR>), gd, bd, lds, s, a);                 \
     } while (0)
-    if (a.nbits == 2) {
-        if (a.method == 2) {
-            if (a.prec == 0) PCAL_ROT(2, 2, 0); else if (a.prec == 1) PCAL_ROT(2, 2, 1); else PCAL_ROT(2, 2, 2);
-        } else if (a.method == 3) {
-            if (a.prec == 0) PCAL_ROT(2, 3, 0); else if (a.prec == 1) PCAL_ROT(2, 3, 1); else PCAL_ROT(2, 3, 2);
-        } else {
-            if (a.prec == 0) PCAL_ROT(2, 4, 0); else if (a.prec == 1) PCAL_ROT(2, 4, 1); else PCAL_ROT(2, 4, 2);
-        }
-    } else {
-        if (a.method == 2) {
-            if (a.prec == 0) PCAL_ROT(8, 2, 0); else if (a.prec == 1) PCAL_ROT(8, 2, 1); else PCAL_ROT(8, 2, 2);
-        } else if (a.method == 3) {
-            if (a.prec == 0) PCAL_ROT(8, 3, 0); else if (a.prec == 1) PCAL_ROT(8, 3, 1); else PCAL_ROT(8, 3, 2);
-        } else {
-            if (a.prec == 0) PCAL_ROT(8, 4, 0); else if (a.prec == 1) PCAL_ROT(8, 4, 1); else PCAL_ROT(8, 4, 2);
-        }
-    }
+#define PCAL_ROT_P(NB, ME)                                  \
+    do {                                                    \
+        if (a.prec == 0) PCAL_ROT(NB, ME, 0);               \
+        else if (a.prec == 1) PCAL_ROT(NB, ME, 1);          \
+        else PCAL_ROT(NB, ME, 2);                           \
+    } while (0)
+#define PCAL_ROT_M(NB)                                      \
+    do {                                                    \
+        if (a.method == 2) PCAL_ROT_P(NB, 2);               \
+        else if (a.method == 3) PCAL_ROT_P(NB, 3);          \
+        else if (a.method == 4) PCAL_ROT_P(NB, 4);          \
+        else if (a.method == 5) PCAL_ROT_P(NB, 5);          \
+        else PCAL_ROT_P(NB, 6);                             \
+    } while (0)
+    if (a.nbits == 2)
+        PCAL_ROT_M(2);
+    else
+        PCAL_ROT_M(8);
+#undef PCAL_ROT_M
+#undef PCAL_ROT_P
 #undef PCAL_ROT
 }
 

@@ -1,12 +1,18 @@
 // Served form of libpcal: many live streams under one device-memory budget,
-// continuously batched.  Chunks queue per stream on the host; every step folds
-// the oldest queued piece of each stream with one launch of the batched fused
-// kernel, and finalizes (reads and clears) with one batched launch every
-// stream whose integration that step completed.  Results reach pinned host
-// memory asynchronously and are picked up by polling.
+// continuously batched.  Chunks queue per stream on the host.  In the
+// host-step form every step folds the oldest queued piece of each stream with
+// one launch of the batched fused kernel, and finalizes (reads and clears)
+// with one batched launch every stream whose integration that step completed.
+// In the device-resident form (pcal_server_start) one persistent kernel runs
+// the loop: a step only publishes the queued pieces as descriptors in a work
+// ring in coherent host memory, the kernel's workgroups claim them, fold them
+// into the streams' accumulator banks and finalize each integration as its
+// last task ends, and report it in a completion ring.  Results reach pinned
+// host memory asynchronously and are picked up by polling.
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <deque>
 #include <new>
 #include <vector>
@@ -39,6 +45,9 @@ struct SrvStream {
     double *slots_dev = nullptr;     // the same memory's device address (the finalize writes it)
     int64_t slot_integ[kResultDepth];  // integration held by each slot (-1: none)
     bool slot_ready[kResultDepth];
+    // device-resident form
+    int64_t integ_chunks = 0;        // chunks published in the current integration
+    bool fin_inflight = false;       // an integration's last chunk is published, its completion not yet seen
 };
 
 struct Done {
@@ -70,6 +79,19 @@ struct pcal_server_ctx {
     std::vector<int64_t> ns;
     std::vector<Done> done;
     int rr = 0;  // first stream served next step (round robin)
+    // device-resident loop (pcal_server_start)
+    bool resident = false;
+    hipStream_t rstream = nullptr;
+    int rgrid = 0, tasks = 0, cap = 0, done_cap = 0;
+    ServedDesc *ring = nullptr;              // coherent host memory, written by the host
+    unsigned long long *slot_free = nullptr;  // coherent host memory, written by the device
+    ServedDone *dn = nullptr;
+    int *ctl = nullptr;                      // [0] quit, [1] workgroups that left, [2] of them on the spin limit
+    ServedArgs args{};
+    void *dmem = nullptr;                    // device counters
+    unsigned long long published = 0;        // chunks published
+    unsigned long long done_next = 0;        // next completion record to read
+    std::deque<Done> ready;                  // completions read while waiting, not yet polled
 };
 
 namespace {
@@ -86,6 +108,174 @@ int take_event(pcal_server_ctx *s, hipEvent_t *ev) {
 
 bool valid_sid(const pcal_server_ctx *s, int sid) {
     return sid >= 0 && sid < static_cast<int>(s->streams.size()) && s->streams[sid].open;
+}
+
+constexpr int kRingSlots = 256;        // chunks in the work ring
+constexpr int kDoneSlots = 4096;       // completion records
+constexpr int kTasksPerChunk = 32;     // workgroups per chunk (PCAL_SERVED_TASKS)
+// Polls of an unpublished ring slot before a workgroup leaves (about 9 s: each
+// poll sleeps about 3.4 us and reads host memory), so that the kernel ends even
+// if the host never sets quit.
+constexpr unsigned long long kSpinLimit = 2000000ull;
+
+template <class T>
+int coherent_alloc(T **host, size_t count) {
+    const hipError_t e = hipHostMalloc(reinterpret_cast<void **>(host), sizeof(T) * count,
+                                       hipHostMallocCoherent | hipHostMallocMapped);
+    if (e != hipSuccess) {
+        set_error("hipHostMalloc(coherent)", e);
+        *host = nullptr;
+        return e == hipErrorOutOfMemory ? PCAL_ENOMEM : PCAL_EHIP;
+    }
+    memset(*host, 0, sizeof(T) * count);
+    return PCAL_OK;
+}
+
+template <class T>
+int device_address(T *host, T **dev) {
+    const hipError_t e = hipHostGetDevicePointer(reinterpret_cast<void **>(dev), host, 0);
+    if (e != hipSuccess) {
+        set_error("hipHostGetDevicePointer", e);
+        return PCAL_EHIP;
+    }
+    return PCAL_OK;
+}
+
+// Resident form: move finished integrations from the completion ring to `ready`.
+void drain_done(pcal_server_ctx *s) {
+    for (;;) {
+        ServedDone *r = s->dn + s->done_next % static_cast<unsigned>(s->done_cap);
+        if (__atomic_load_n(&r->seq, __ATOMIC_ACQUIRE) != s->done_next + 1) return;
+        const Done d{r->sid, r->integ};
+        s->done_next += 1;
+        if (valid_sid(s, d.sid)) {
+            SrvStream &st = s->streams[d.sid];
+            const int k = static_cast<int>(d.integ % kResultDepth);
+            if (st.slot_integ[k] == d.integ) st.slot_ready[k] = true;
+            st.fin_inflight = false;
+        }
+        s->ready.push_back(d);
+    }
+}
+
+// Resident form: every published chunk's tasks have ended.
+bool ring_idle(const pcal_server_ctx *s) {
+    const unsigned long long lo = s->published > static_cast<unsigned long long>(s->cap)
+                                      ? s->published - static_cast<unsigned long long>(s->cap) : 0ull;
+    for (unsigned long long c = lo; c < s->published; ++c)
+        if (__atomic_load_n(s->slot_free + c % static_cast<unsigned>(s->cap), __ATOMIC_ACQUIRE) < c + 1) return false;
+    return true;
+}
+
+// Resident form: wait (bounded) until every published chunk has ended and every
+// published finalize has been reported.
+int wait_idle(pcal_server_ctx *s, double seconds) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        drain_done(s);
+        bool fin = false;
+        for (const SrvStream &st : s->streams) fin = fin || (st.open && st.fin_inflight);
+        if (!fin && ring_idle(s)) return PCAL_OK;
+        if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > seconds) {
+            set_message("served loop: published work did not finish in time");
+            return PCAL_EHIP;
+        }
+    }
+}
+
+void free_resident(pcal_server_ctx *s) {
+    if (s->ring) (void)hipHostFree(s->ring);
+    if (s->slot_free) (void)hipHostFree(s->slot_free);
+    if (s->dn) (void)hipHostFree(s->dn);
+    if (s->ctl) (void)hipHostFree(s->ctl);
+    if (s->dmem) (void)hipFree(s->dmem);
+    s->ring = nullptr;
+    s->slot_free = nullptr;
+    s->dn = nullptr;
+    s->ctl = nullptr;
+    s->dmem = nullptr;
+    s->resident = false;
+}
+
+// Resident form: whether a stream's plan fits the persistent kernel.
+bool resident_fits(const pcal_server_ctx *s, const Plan &p) {
+    return p.N <= kServedMaxTones && p.geom.col_tiles <= s->tasks;
+}
+
+// Resident form: publish queued pieces as long as the ring has room; a piece
+// that completes an integration waits while the stream's previous finalize
+// is still in flight (the two would share the finalize's scratch).
+int publish(pcal_server_ctx *s, int64_t *samples) {
+    const int M = s->max_streams;
+    bool progress = true;
+    while (progress) {
+        progress = false;
+        for (int j = 0; j < M; ++j) {
+            const int sid = (s->rr + j) % M;
+            SrvStream &st = s->streams[sid];
+            if (!st.open || st.queue.empty()) continue;
+            const unsigned long long c = s->published;
+            const int slot = static_cast<int>(c % static_cast<unsigned>(s->cap));
+            if (c >= static_cast<unsigned long long>(s->cap) &&
+                __atomic_load_n(s->slot_free + slot, __ATOMIC_ACQUIRE) < c - static_cast<unsigned>(s->cap) + 1)
+                return PCAL_OK;  // ring full
+            Piece &pc = st.queue.front();
+            const int64_t take = std::min(pc.n, st.integ_samples - st.in_integ);
+            const bool completes = st.in_integ + take == st.integ_samples;
+            if (completes && st.fin_inflight) continue;
+            pcal_t h = nullptr;
+            int rc = pcal_batch_handle(s->batch, st.bid, &h);
+            if (rc) return rc;
+            const Plan &p = h->plan;
+            const int bank = static_cast<int>(st.integ & 1);
+            const size_t NS = static_cast<size_t>(kAccSlots) * static_cast<size_t>(p.N);
+            ServedDesc &d = s->ring[slot];
+            const pcal_launch_t L = plan_launch(p, reinterpret_cast<uintptr_t>(pc.ptr), h->n_total, take, s->tasks);
+            d.fold = fold_args(h, L, pc.ptr);
+            d.fold.acc = h->acc_mem + bank * NS;
+            d.fold.acc_int = h->acc_int_mem + bank * NS;
+            d.fold.accf = h->accf_mem + bank * NS;
+            d.sid = sid;
+            d.bank = bank;
+            d.ntasks = static_cast<int>(L.grid);
+            d.integ = st.integ;
+            d.fin_total = 0;
+            if (completes) {
+                const int k = static_cast<int>(st.integ % kResultDepth);
+                FinArgs f = fin_args(h, st.slots_dev + static_cast<size_t>(k) * (4 * st.N + 1));
+                f.acc = d.fold.acc;
+                f.accf = d.fold.accf;
+                f.acc_clear = d.fold.acc;
+                f.accf_clear = d.fold.accf;
+                f.acc_int_clear = d.fold.acc_int;
+                f.counter = h->counters + bank;
+                f.inv_L = 1.0 / static_cast<double>(st.integ_samples);
+                f.clear = 1;
+                d.fin = f;
+                d.fin_total = s->tasks * static_cast<int>(st.integ_chunks + 1);
+                st.slot_integ[k] = st.integ;
+                st.slot_ready[k] = false;
+                st.fin_inflight = true;
+            }
+            __atomic_store_n(&d.seq, c + 1, __ATOMIC_RELEASE);  // the descriptor is complete: publish it
+            s->published = c + 1;
+            if (samples) *samples += take;
+            h->n_total += take;
+            pc.ptr += take / st.spb;
+            pc.n -= take;
+            if (pc.n == 0) st.queue.pop_front();
+            st.in_integ += take;
+            st.integ_chunks += 1;
+            if (completes) {
+                st.integ += 1;
+                st.in_integ = 0;
+                st.integ_chunks = 0;
+            }
+            progress = true;
+        }
+        s->rr = M > 0 ? (s->rr + 1) % M : 0;
+    }
+    return PCAL_OK;
 }
 
 }  // namespace
@@ -126,8 +316,10 @@ int pcal_server_open(pcal_server_t s, int64_t fs_hz, int64_t f_comb_hz, int64_t 
     // admission, before anything is allocated: the device memory of the
     // stream's tables and accumulators, from its plan, must fit the budget left
     Plan plan{};
-    int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_PERIOD_FOLD, s->prec, &plan);
+    int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_PERIOD_FOLD, s->prec, &plan,
+                       batch_threads(s->batch));
     if (rc) return rc;
+    if (s->resident && !resident_fits(s, plan)) return PCAL_ENOTSUP;
     if (s->used + plan_device_bytes(plan) > s->budget) return PCAL_EAGAIN;
     int bid = -1;
     rc = pcal_batch_add(s->batch, fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, &bid);
@@ -138,8 +330,9 @@ int pcal_server_open(pcal_server_t s, int64_t fs_hz, int64_t f_comb_hz, int64_t 
     const int64_t slots_bytes = static_cast<int64_t>(sizeof(double)) * kResultDepth * (4 * N + 1);
     SrvStream &st = s->streams[slot];
     {
+        // coherent: the device-resident loop's finalize writes here while its kernel runs on
         hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&st.slots), static_cast<size_t>(slots_bytes),
-                                     hipHostMallocDefault);
+                                     hipHostMallocCoherent | hipHostMallocMapped);
         if (e != hipSuccess) {
             set_error("hipHostMalloc", e);
             (void)batch_release(s->batch, bid);
@@ -164,6 +357,8 @@ int pcal_server_open(pcal_server_t s, int64_t fs_hz, int64_t f_comb_hz, int64_t 
     st.in_integ = 0;
     st.device_bytes = h->device_bytes;
     st.queue.clear();
+    st.integ_chunks = 0;
+    st.fin_inflight = false;
     for (int i = 0; i < kResultDepth; ++i) {
         st.slot_integ[i] = -1;
         st.slot_ready[i] = false;
@@ -178,6 +373,10 @@ int pcal_server_close(pcal_server_t s, int sid) {
     SrvStream &st = s->streams[sid];
     // its work and any results still in flight end before its memory goes
     for (Inflight &f : s->inflight) PCAL_HIP(hipEventSynchronize(f.ev));
+    if (s->resident) {
+        const int rc = wait_idle(s, 30.0);
+        if (rc) return rc;
+    }
     const int rc = batch_release(s->batch, st.bid);
     if (st.slots) (void)hipHostFree(st.slots);
     st.slots = nullptr;
@@ -205,6 +404,10 @@ int pcal_server_submit(pcal_server_t s, int count, const int *sids, const void *
 int pcal_server_step(pcal_server_t s, pcal_stream_t stream, int64_t *samples_dispatched) {
     if (!s) return PCAL_EINVAL;
     if (samples_dispatched) *samples_dispatched = 0;
+    if (s->resident) {
+        drain_done(s);
+        return publish(s, samples_dispatched);
+    }
     hipStream_t hs = static_cast<hipStream_t>(stream);
     s->ids.clear();
     s->ptrs.clear();
@@ -265,6 +468,13 @@ int pcal_server_step(pcal_server_t s, pcal_stream_t stream, int64_t *samples_dis
 int pcal_server_poll(pcal_server_t s, int max, int *sids, int64_t *integrations, int *n) {
     if (!s || !n || max < 0 || (max > 0 && (!sids || !integrations))) return PCAL_EINVAL;
     *n = 0;
+    if (s->resident) drain_done(s);
+    while (!s->ready.empty() && *n < max) {
+        sids[*n] = s->ready.front().sid;
+        integrations[*n] = s->ready.front().integ;
+        s->ready.pop_front();
+        ++*n;
+    }
     while (!s->inflight.empty() && *n < max) {
         Inflight &f = s->inflight.front();
         const hipError_t q = hipEventQuery(f.ev);
@@ -326,13 +536,110 @@ int pcal_server_stats(pcal_server_t s, int64_t *queued_samples, int *inflight_fi
                 for (const Piece &p : st.queue) q += p.n;
         *queued_samples = q;
     }
-    if (inflight_finalizes) *inflight_finalizes = static_cast<int>(s->inflight.size());
+    if (inflight_finalizes) {
+        int f = static_cast<int>(s->inflight.size());
+        for (const SrvStream &st : s->streams) f += (st.open && st.fin_inflight) ? 1 : 0;
+        *inflight_finalizes = f;
+    }
     if (device_bytes) *device_bytes = s->used;
+    return PCAL_OK;
+}
+
+int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
+    if (!s || workgroups < 1) return PCAL_EINVAL;
+    if (s->resident) return PCAL_ESTATE;
+    if (batch_threads(s->batch) != kServedThreads) return PCAL_ENOTSUP;
+    s->tasks = std::max(1, env_int("PCAL_SERVED_TASKS", kTasksPerChunk));
+    for (int i = 0; i < s->max_streams; ++i) {
+        if (!s->streams[i].open) continue;
+        pcal_t h = nullptr;
+        int rc = pcal_batch_handle(s->batch, s->streams[i].bid, &h);
+        if (rc) return rc;
+        if (!resident_fits(s, h->plan)) return PCAL_ENOTSUP;
+    }
+    // the host-step form's work ends first: its results are reported by later polls
+    for (Inflight &f : s->inflight) PCAL_HIP(hipEventSynchronize(f.ev));
+    int rc;
+    s->cap = kRingSlots;
+    s->done_cap = kDoneSlots;
+    if ((rc = coherent_alloc(&s->ring, s->cap)) || (rc = coherent_alloc(&s->slot_free, s->cap)) ||
+        (rc = coherent_alloc(&s->dn, s->done_cap)) || (rc = coherent_alloc(&s->ctl, 4))) {
+        free_resident(s);
+        return rc;
+    }
+    const size_t nsb = 2 * static_cast<size_t>(s->max_streams);
+    const size_t dbytes = 16 + 4 * static_cast<size_t>(s->cap) + 2 * 4 * nsb;
+    {
+        const hipError_t e = hipMalloc(&s->dmem, dbytes);
+        if (e != hipSuccess) {
+            set_error("hipMalloc", e);
+            free_resident(s);
+            return e == hipErrorOutOfMemory ? PCAL_ENOMEM : PCAL_EHIP;
+        }
+    }
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    launch_zero(s->dmem, dbytes, hs);
+    ServedArgs &a = s->args;
+    a = ServedArgs{};
+    unsigned char *dm = static_cast<unsigned char *>(s->dmem);
+    a.cursor = reinterpret_cast<unsigned long long *>(dm);
+    a.done_cursor = reinterpret_cast<unsigned long long *>(dm + 8);
+    a.slot_cnt = reinterpret_cast<unsigned *>(dm + 16);
+    a.task_done = a.slot_cnt + s->cap;
+    a.fin_total = a.task_done + nsb;
+    if ((rc = device_address(s->ring, const_cast<ServedDesc **>(&a.ring))) ||
+        (rc = device_address(s->slot_free, &a.slot_free)) || (rc = device_address(s->dn, &a.done)) ||
+        (rc = device_address(s->ctl, &a.status))) {
+        free_resident(s);
+        return rc;
+    }
+    a.quit = a.status;   // ctl[0]
+    a.status = a.status + 1;  // ctl[1], ctl[2]
+    a.cap = s->cap;
+    a.done_cap = s->done_cap;
+    a.tasks = s->tasks;
+    a.spin_limit = kSpinLimit;
+    s->published = 0;
+    s->done_next = 0;
+    s->rgrid = workgroups;
+    s->rstream = hs;
+    launch_served(a, kernel_prec(s->prec), workgroups, kServedThreads, kServedLds, hs);
+    {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            set_error("launch of the served loop", e);
+            (void)hipStreamSynchronize(hs);
+            free_resident(s);
+            return PCAL_EHIP;
+        }
+    }
+    for (SrvStream &st : s->streams) {
+        st.integ_chunks = 0;
+        st.fin_inflight = false;
+    }
+    s->resident = true;
+    return PCAL_OK;
+}
+
+int pcal_server_stop(pcal_server_t s) {
+    if (!s) return PCAL_EINVAL;
+    if (!s->resident) return PCAL_ESTATE;
+    const int idle = wait_idle(s, 30.0);
+    __atomic_store_n(s->ctl, 1, __ATOMIC_RELEASE);  // quit: every workgroup leaves at its next empty poll
+    PCAL_HIP(hipStreamSynchronize(s->rstream));
+    const int left = __atomic_load_n(s->ctl + 1, __ATOMIC_ACQUIRE);
+    free_resident(s);
+    if (idle) return idle;
+    if (left != s->rgrid) {
+        set_message("served loop: not every workgroup left at quit");
+        return PCAL_EHIP;
+    }
     return PCAL_OK;
 }
 
 int pcal_server_destroy(pcal_server_t s) {
     if (!s) return PCAL_EINVAL;
+    if (s->resident) (void)pcal_server_stop(s);
     for (Inflight &f : s->inflight) {
         (void)hipEventSynchronize(f.ev);
         (void)hipEventDestroy(f.ev);

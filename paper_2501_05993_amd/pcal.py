@@ -21,8 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpcal.so")
 
 OK, EINVAL, ENOMEM, EHIP, EAGAIN, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
-METHOD_AUTO, METHOD_PERIOD_FOLD, METHOD_LUT, METHOD_OSC, METHOD_CFO = 0, 1, 2, 3, 4
-PREC_F64, PREC_MIXED, PREC_F32 = 0, 1, 2
+METHOD_AUTO, METHOD_PERIOD_FOLD, METHOD_LUT, METHOD_OSC, METHOD_CFO, METHOD_MCO, METHOD_DFR_EF = 0, 1, 2, 3, 4, 5, 6
+PREC_F64, PREC_MIXED, PREC_F32, PREC_F16, PREC_Q17 = 0, 1, 2, 3, 4
 
 _i64 = ctypes.c_int64
 
@@ -71,6 +71,7 @@ _SIGS = {
     "pcal_pulse": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
                    ctypes.c_int),
     "pcal_bandpass": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "pcal_refine": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_reset": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_num_tones": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -106,6 +107,8 @@ _SIGS = {
                              ctypes.c_int),
     "pcal_server_stats": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_server_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "pcal_server_start": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "pcal_server_stop": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "pcal_read_probe": ([ctypes.c_void_p, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -281,6 +284,13 @@ class PCal:
         _check(lib().pcal_bandpass(self._h, amp.ctypes.data, ph.ctypes.data, ctypes.byref(delay)), "pcal_bandpass")
         return amp, ph, delay.value
 
+    def refine(self, iters: int):
+        """(delays[iters + 1] in s, intercept in rad, rms residual in rad) of the multi-pass refinement."""
+        d = np.zeros(iters + 1)
+        r = np.zeros(2)
+        _check(lib().pcal_refine(self._h, iters, d.ctypes.data, r.ctypes.data), "pcal_refine")
+        return d, float(r[0]), float(r[1])
+
     def reset(self) -> None:
         _check(lib().pcal_reset(self._h), "pcal_reset")
 
@@ -455,6 +465,15 @@ class PCalServer:
         _check(lib().pcal_server_spectrum(self._s, sid, integration, re.ctypes.data, im.ctypes.data),
                "pcal_server_spectrum")
         return re + 1j * im
+
+    def start(self, workgroups: int = 64, stream=None) -> None:
+        """Switch to the device-resident loop: one persistent kernel on `stream` (pcal_server_start)."""
+        _check(lib().pcal_server_start(self._s, workgroups, ctypes.c_void_p(_stream_handle(stream))),
+               "pcal_server_start")
+
+    def stop(self) -> None:
+        """Leave the device-resident loop once the published work has ended (pcal_server_stop)."""
+        _check(lib().pcal_server_stop(self._s), "pcal_server_stop")
 
     def stats(self) -> dict:
         q = ctypes.c_int64()

@@ -52,19 +52,22 @@ def rounded_tables(fs, fo, N, M, prec):
     v[b] = exp(-j w_o b) (Eq. 3 with the phase index reduced exactly).  Returns
     (u, v, gain) for oracle.correlate_rotator: MIXED stores each u[m] as two FP16
     terms (the rounded value and its rounded residual) and divides the table's
-    mean gain 1 + gamma out, v exact; F32 rounds u and v to FP32, gain 1.
+    mean gain 1 + gamma out, v exact; F16 (the literal single-FP16 form) rounds u
+    to one FP16 value, v exact, gain 1; F32 rounds u and v to FP32, gain 1.
     """
     m = np.arange(M, dtype=np.int64)
     b = np.arange(N, dtype=np.int64)
     u = np.exp(-2j * np.pi * ((fo * N * m) % fs) / fs)
     v = np.exp(-2j * np.pi * ((fo * b) % fs) / fs)
+    def f16(z):
+        return z.real.astype(np.float16).astype(float) + 1j * z.imag.astype(np.float16).astype(float)
     if prec == 1:
-        def f16(z):
-            return z.real.astype(np.float16).astype(float) + 1j * z.imag.astype(np.float16).astype(float)
         hi = f16(u)
         uh = hi + f16(u - hi)
         gamma = np.mean(np.conj(u) * (uh - u))
         return uh, v, 1.0 / (1.0 + gamma)
+    if prec == 3:  # the literal single-FP16 form: rounded rows, no gain correction
+        return f16(u), v, 1.0
 
     def f32(z):
         return z.real.astype(np.float32).astype(float) + 1j * z.imag.astype(np.float32).astype(float)

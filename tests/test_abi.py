@@ -83,14 +83,14 @@ def test_per_sample_forms_share_one_plan():
     8-bit per-sample forms default to 768 (table) or 512 (recurrences) workgroups per launch, the 2-bit
     ones to 1024; unknown methods are rejected."""
     for nbits in (2, 8):
-        plans = [pcal.plan(1_024_000_000, 1_000_000, 510_000, nbits, method=m)
-                 for m in (pcal.METHOD_LUT, pcal.METHOD_OSC, pcal.METHOD_CFO)]
-        assert [p["method"] for p in plans] == [pcal.METHOD_LUT, pcal.METHOD_OSC, pcal.METHOD_CFO]
+        forms = (pcal.METHOD_LUT, pcal.METHOD_OSC, pcal.METHOD_CFO, pcal.METHOD_MCO, pcal.METHOD_DFR_EF)
+        plans = [pcal.plan(1_024_000_000, 1_000_000, 510_000, nbits, method=m) for m in forms]
+        assert [p["method"] for p in plans] == list(forms)
         keys = [k for k in plans[0] if k not in ("method", "target_blocks", "device_bytes")]
         assert all(p[k] == plans[0][k] for p in plans for k in keys)
-        assert [p["target_blocks"] for p in plans] == ([768, 512, 512] if nbits == 8 else [1024] * 3)
+        assert [p["target_blocks"] for p in plans] == ([768] + [512] * 4 if nbits == 8 else [1024] * 5)
     with pytest.raises(pcal.PcalError) as e:
-        pcal.plan(64_000_000, 1_000_000, 10_000, 2, method=5)
+        pcal.plan(64_000_000, 1_000_000, 10_000, 2, method=7)
     assert e.value.code == pcal.EINVAL
 
 
@@ -107,3 +107,4 @@ def test_plan_device_bytes():
     assert lut[pcal.PREC_F64] - lut[pcal.PREC_F32] == 8 * R
     osc = pcal.plan(1_024_000_000, 1_000_000, 510_000, 8, method=pcal.METHOD_OSC)["device_bytes"]
     assert lut[pcal.PREC_F64] - osc == 16 * R
+

@@ -208,7 +208,7 @@ ROT_CASES = [
 ]
 
 
-@pytest.mark.parametrize("method", [2, 3])
+@pytest.mark.parametrize("method", [2, 3, 5])
 @pytest.mark.parametrize("fs,fc,fo,nbits,ns,addr,before", ROT_CASES)
 def test_per_sample_walk(method, fs, fc, fo, nbits, ns, addr, before):
     if method == 2 and fo == 10_007:

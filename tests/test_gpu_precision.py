@@ -2,7 +2,10 @@
 
 MIXED: rotator rows as two FP16 terms (the rounded row and its rounded
 residual), FP32 products with Kahan-compensated per-workgroup sums, FP64
-cross-workgroup reduction and DFT, the table's known gain divided out.  F32: FP32 rows, plain FP32 sums, FP32 reduction and DFT.
+cross-workgroup reduction and DFT, the table's known gain divided out.  F32:
+FP32 rows, plain FP32 sums, FP32 reduction and DFT.  F16: the literal mixed
+variant, single FP16 rows and no gain correction (reported, not held to the
+contract).
 
 Each form is checked twice: tightly against the oracle's rotator-form
 correlation fed with the same rounded tables (rounded here with numpy,
@@ -30,7 +33,7 @@ def pc():
     return pcal
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 @pytest.mark.parametrize("s", [0, 3, 4, 8, 9])
 def test_precision_form(pc, prec, s):
     spec = synth.batch_specs()[s]
@@ -55,8 +58,15 @@ def test_precision_form(pc, prec, s):
         # two-term FP16 rows (about 22 bits): within the 1e-5 amplitude and
         # 1e-4 rad phase tolerance of the FP64 oracle
         assert amp_e < 1e-5 and ph_e < 1e-4
+    elif prec == 3:
+        # the literal single-FP16 variant: the kernel is the mixed form's, exact to
+        # the same few FP32 ulps against its own (single-term) table; its table
+        # rounding (2^-11 relative per row, no gain correction) is what it reports
+        # against the FP64 oracle, within a few times the row rounding over sqrt(M)
+        assert err_kernel < 2e-6
+        assert amp_e < 2e-3 and ph_e < 2e-3
     else:
         # FP32 sums over rows, workgroups (atomics) and the N-point DFT: measured
-        # at most 1.1e-6 against the FP64 form on the full workloads
+        # at most 3.8e-6 against the FP64 oracle on the 64-stream mix
         assert err_kernel < 1e-5
         assert amp_e < 1e-5 and ph_e < 1e-5

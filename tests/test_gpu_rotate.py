@@ -3,7 +3,8 @@
 Every sample is multiplied by a rotator; the table form reads it from one
 rotator period, the recurrence forms step a direct-form resonator (method 3)
 or a coupled-form oscillator (method 4) per row with exact FP64 restarts
-every 64 rows.  The FP64 form (FP64 table or recurrence state, FP64 products
+every 64 rows; the magic-circle oscillator (method 5) and the resonator with
+truncation-error feedback (method 6) likewise.  The FP64 form (FP64 table or recurrence state, FP64 products
 and sums) is checked against the FP64 oracle to 1e-10; the mixed form (table
 entries as two FP16 terms, FP32 state, products and run sums, Kahan totals)
 and the all-FP32 form to the contract tolerance (1e-5 relative amplitude,
@@ -49,7 +50,7 @@ def _extract(pc, spec, packed, L, method, prec=0, chunks=None, offset=0):
     return C, res
 
 
-@pytest.mark.parametrize("method", [2, 3, 4])
+@pytest.mark.parametrize("method", [2, 3, 4, 5, 6])
 def test_wide8_per_sample(pc, method):
     spec = synth.WORKLOADS["wide8_1024M_510k"]["spec"]
     L = (1 << 22) + 4096 + 7
@@ -62,7 +63,7 @@ def test_wide8_per_sample(pc, method):
     assert abs(d - do) < 1e-15
 
 
-@pytest.mark.parametrize("method", [2, 3, 4])
+@pytest.mark.parametrize("method", [2, 3, 4, 5, 6])
 def test_fold2_per_sample_chunks(pc, method):
     spec = synth.WORKLOADS["fold2_64M_10k"]["spec"]
     L = 4 * 700_001
@@ -90,7 +91,7 @@ def test_prime_offset_recurrence(pc):
     assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="prime offset")
 
 
-@pytest.mark.parametrize("method", [2, 3, 4])
+@pytest.mark.parametrize("method", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("prec", [1, 2])
 def test_per_sample_reduced_precision(pc, method, prec):
     spec = synth.WORKLOADS["wide8_1024M_510k"]["spec"]
@@ -103,13 +104,14 @@ def test_per_sample_reduced_precision(pc, method, prec):
     assert a < AMP_RTOL and p < PHASE_ATOL and w < 1e-5
 
 
-@pytest.mark.parametrize("fs,fc,fo", [(1_024_000_000, 1_000_000, 250_010), (64_000_000, 1_000_000, 15_626)])
+@pytest.mark.parametrize("fs,fc,fo", [(64_000_000, 1_000_000, 15_650), (256_000_000, 1_000_000, 62_600)])
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_recurrence_near_zero_row_step(pc, fs, fc, fo, prec):
-    """Offsets whose rotator advance per 4096-sample row lies near 0 (mod 2 pi): with the
-    resonator coefficient 2 cos d rounded to FP32 the recurrence would drift.  The plan picks
-    a row length whose step is far from 0 and pi; the resonator then meets the contract in
-    the FP32 forms and FP64 accuracy in the FP64 form."""
+    """Offsets whose rotator advance per 4096-sample row lies near 0 (mod 2 pi; |sin d| = 0.01
+    there): with the resonator coefficient 2 cos d rounded to FP32 the recurrence would drift by
+    up to 2e-4 rad over a 64-row run.  The plan picks a row length whose step is far from 0 and
+    pi; the resonator then meets the contract in the FP32 forms and FP64 accuracy in the FP64
+    form.  (Comb periods of 1.28e6 samples keep the synthetic input quick to build.)"""
     spec = synth.CombSpec(fs, fc, fo, 8, amp=1.0, t_d=7e-9, sigma=20.0, seed=(43, fo))
     L = 1 << 22
     packed = synth.make_stream(spec, L)
@@ -125,3 +127,19 @@ def test_recurrence_near_zero_row_step(pc, fs, fc, fo, prec):
         assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="near-zero step F64")
     else:
         assert_spectra(C, Co, what="near-zero step prec %d" % prec)
+
+
+def test_table_single_fp16_variant(pc):
+    """The literal mixed variant of the table form (PCAL_PREC_F16: single FP16 entries, no gain
+    correction) runs and reports its form; its table rounding (2^-11 per entry) is what separates it
+    from the FP64 oracle, within a few times that rounding."""
+    spec = synth.WORKLOADS["wide8_1024M_510k"]["spec"]
+    L = 1 << 22
+    packed = synth.make_stream(spec, L)
+    with pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 8, method=pc.METHOD_LUT, precision=pc.PREC_F16) as h:
+        assert h.info()["precision"] == pc.PREC_F16
+    C, _ = _extract(pc, spec, packed, L, pc.METHOD_LUT, prec=pc.PREC_F16)
+    Co = oracle.correlate(packed, 8, L, spec.fs, spec.f_comb, spec.f_offset)
+    a, p, w = compare_spectra(C, Co)
+    say("wide8 table single-FP16: amp %.2e phase %.2e" % (a, p))
+    assert a < 2e-3 and p < 2e-3

@@ -63,7 +63,8 @@ def _walk_loop(lines):
 
 def _fold_kernels(funcs):
     names = [n for n in funcs if "fold_kernel" in n or "fold_batch_kernel" in n]
-    assert len(names) == 18, names  # {2,8}-bit x 3 precisions: plain, batched (device or inline work-list)
+    # {2,8}-bit x 3 precisions: plain, batched (device or inline work-list); plus the plain fixed-point form
+    assert len(names) == 20, names
     return names
 
 

@@ -2,7 +2,7 @@
 
 orc_fold_table_int sums x[n] * T[n mod R] into bin n mod N exactly in
 integers; fixed_rotator gives the rotator of Eq. 3 over one period (Eq. 4)
-scaled by 2^15 and rounded.  Pinned to a plain Python loop on tiny inputs,
+scaled by 2^17 and rounded.  Pinned to a plain Python loop on tiny inputs,
 to the integer fold of Eq. 2 for the unit table, to the exact rotator at
 the quarter-rate offset, to the rounding bound of every entry and of the
 bins against the FP64 rotated fold, and to chunking with a global index.
@@ -49,17 +49,17 @@ def test_unit_table_is_integer_fold(oracle_lib):
 
 
 def test_fixed_rotator_entries():
-    """Integers within 2^-16 sqrt(2) (times 2^15) of the exact rotator; exact at the quarter rate."""
+    """Integers within 2^-18 sqrt(2) (times 2^17) of the exact rotator; exact at the quarter rate."""
     T = core.fixed_rotator(16_000_000, 4_000_000)
-    assert np.array_equal(T, np.array([32768, -32768j, -32768, 32768j]))
+    assert np.array_equal(T, np.array([131072, -131072j, -131072, 131072j]))
     for fs, fo in ((64_000_000, 10_000), (1_024_000_000, 510_000), (64_000_000, 10_008)):
         T = core.fixed_rotator(fs, fo)
         R = fs // np.gcd(fs, fo)
-        assert T.size == R and T[0] == 32768
+        assert T.size == R and T[0] == 131072
         assert np.array_equal(T.real, np.round(T.real)) and np.array_equal(T.imag, np.round(T.imag))
         r = np.arange(R)
         exact = np.exp(-2j * np.pi * ((fo * r) % fs) / fs)
-        assert np.abs(T / 32768.0 - exact).max() <= 2 ** -16 * np.sqrt(2) + 1e-15
+        assert np.abs(T / 131072.0 - exact).max() <= 2 ** -18 * np.sqrt(2) + 1e-15
 
 
 @pytest.mark.parametrize("fs,fo,nbits,N,L,n0", [(64_000_000, 10_000, 2, 64, 6400 * 5 + 44, 3),
@@ -71,8 +71,8 @@ def test_fixed_bins_within_rounding_of_fp64_fold(oracle_lib, fs, fo, nbits, N, L
     re, im = oracle_lib.fold_table_int(packed, nbits, L, N, T, n0=n0)
     P = oracle_lib.fold_rot(packed, nbits, L, fs, fo, N, n0=n0)
     lv = np.abs(_np_levels(packed, nbits, L))
-    bound = np.bincount((n0 + np.arange(L)) % N, weights=lv, minlength=N) * 2 ** -16 * np.sqrt(2)
-    assert np.all(np.abs((re + 1j * im) / 32768.0 - P) <= bound + 1e-9)
+    bound = np.bincount((n0 + np.arange(L)) % N, weights=lv, minlength=N) * 2 ** -18 * np.sqrt(2)
+    assert np.all(np.abs((re + 1j * im) / 131072.0 - P) <= bound + 1e-9)
 
 
 def test_fixed_chunking(oracle_lib):
