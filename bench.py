@@ -134,7 +134,7 @@ def cpu_baseline_configs(torch, synth, target_s=4.0):
     return out
 
 
-SERVED_POOL = 1 << 24  # samples of the pre-staged device pool per stream configuration
+SERVED_POOL = 1 << 25  # samples of the pre-staged device pool per stream configuration (~0.8 GB in all)
 
 
 def _served_setup(torch, synth, seconds):
@@ -163,8 +163,10 @@ def _pieces(sp, pool, pos, n):
     return out
 
 
-def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False):
-    """Replay the arrival trace through the served form or through plain per-chunk extraction.
+def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None, workgroups=64):
+    """Replay the arrival trace through the served form (mode "served": host-stepped; "resident": the
+    device-resident loop of `workgroups` workgroups) or through plain per-chunk extraction ("plain"),
+    all in precision form `prec` (default: mixed).
 
     Latency of an integration = host time its results are seen - arrival time of its last chunk.
     flat_out: every chunk is available at once (capacity: the sustained rate is the result; latencies
@@ -173,6 +175,8 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False):
     from collections import deque
 
     specs, (t, sid, ns), pools = setup
+    if prec is None:
+        prec = pcal.PREC_MIXED
     if flat_out:
         t = np.zeros_like(t)
         drain_s = 120.0
@@ -181,13 +185,17 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False):
     last_arrival = {}
     lat = []
     done_samples = 0
-    if mode == "served":
-        srv = pcal.PCalServer(mem_budget_bytes=16 << 30, max_streams=S)
+    served = mode in ("served", "resident")
+    if served:
+        srv = pcal.PCalServer(mem_budget_bytes=16 << 30, max_streams=S, precision=prec)
         ids = [srv.open(sp.fs, sp.f_comb, sp.f_offset, sp.nbits, sp.fs) for sp in specs]
         rev = {v: k for k, v in enumerate(ids)}
+        if mode == "resident":
+            srv.start(workgroups=workgroups)
     else:
         K = 4
-        hs = [pcal.PCal(sp.fs, sp.f_comb, sp.f_offset, sp.nbits, method=pcal.METHOD_PERIOD_FOLD) for sp in specs]
+        hs = [pcal.PCal(sp.fs, sp.f_comb, sp.f_offset, sp.nbits, method=pcal.METHOD_PERIOD_FOLD, precision=prec)
+              for sp in specs]
         streams = [torch.cuda.Stream() for _ in range(K)]
         slots = [torch.zeros((8, 4 * sp.ntones + 1), dtype=torch.float64, pin_memory=True) for sp in specs]
         in_integ = [0] * S
@@ -209,7 +217,7 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False):
                 for k in range(p0 // sp.fs, (p0 + n_) // sp.fs):
                     last_arrival[(s_, k)] = t[a]
                 for ptr, m in _pieces(sp, pools[(sp.fs, sp.f_offset, sp.nbits)], p0, n_):
-                    if mode == "served":
+                    if served:
                         sub_s.append(ids[s_])
                         sub_p.append(ptr)
                         sub_n.append(m)
@@ -232,10 +240,10 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False):
                                 integ_no[s_] += 1
                                 in_integ[s_] = 0
                 pos[s_] += n_
-            if mode == "served":
+            if served:
                 srv.submit(sub_s, np.asarray(sub_p, dtype=np.uint64), sub_n)
             i = j
-        if mode == "served":
+        if served:
             srv.step()
             for sv, k in srv.poll():
                 s_ = rev[sv]
@@ -252,8 +260,10 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False):
         if i >= n_arr and (idle or now > t[-1] + drain_s):
             break
     wall = time.perf_counter() - t0
+    if mode == "resident":
+        srv.stop()
     torch.cuda.synchronize()
-    if mode == "served":
+    if served:
         srv.close()
     else:
         for h in hs:
@@ -588,7 +598,7 @@ def main():
                     help="skip the 64-stream batched-form measurement")
     ap.add_argument("--no-rotator-study", action="store_true",
                     help="skip the 8-bit wide-workload comparison of the rotator forms")
-    ap.add_argument("--served-seconds", type=float, default=8.0,
+    ap.add_argument("--served-seconds", type=float, default=30.0,
                     help="length of the serving-study arrival trace (0: skip the serving study)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (10 times): the known-size reference that "
@@ -749,20 +759,34 @@ def main():
     if args.served_seconds > 0:
         print("[bench] serving study: %.0f s trace, 256 streams" % args.served_seconds, file=sys.stderr, flush=True)
         setup = _served_setup(torch, synth, args.served_seconds)
+        pool_bytes = sum(int(v.numel()) for v in setup[2].values())
+        resident = served_run(pcal, torch, setup, "resident")
+        print("[bench] device-resident served form done", file=sys.stderr, flush=True)
         served = served_run(pcal, torch, setup, "served")
-        print("[bench] served form done", file=sys.stderr, flush=True)
+        print("[bench] host-step served form done", file=sys.stderr, flush=True)
         plain = served_run(pcal, torch, setup, "plain")
         print("[bench] serving capacity: the same trace with every chunk available at once",
               file=sys.stderr, flush=True)
+        cap_res = served_run(pcal, torch, setup, "resident", flat_out=True, workgroups=256)
         cap_served = served_run(pcal, torch, setup, "served", flat_out=True)
         cap_plain = served_run(pcal, torch, setup, "plain", flat_out=True)
+        # bytes per sample of the mix (2-bit 0.25 B, 8-bit 1 B), for the HBM fraction of the capacity
+        specs, (tt, sid_, ns_), _ = setup
+        bps = float(np.sum(ns_ * np.array([specs[int(k)].nbits / 8.0 for k in sid_])) / np.sum(ns_))
+        for c in (cap_res, cap_served, cap_plain):
+            c["hbm_frac"] = round(c["sustained_gsps"] * 1e9 * bps / (HBM_PEAK_GBS * 1e9), 4)
         out["served"] = {"workload": "256 streams (2-/8-bit, fs 32-512 MHz, f_offset 0-510 kHz), Poisson "
                                      "chunks of 2^20-2^24 samples at 200 Gsamples/s offered, 1 s integrations, "
-                                     "%.0f s trace" % args.served_seconds,
-                         "served": served, "plain_per_chunk": plain,
+                                     "%.0f s trace, mixed precision form; chunks drawn from device pools of "
+                                     "%.0f MB in all" % (args.served_seconds, pool_bytes / 1e6),
+                         "resident": resident, "served": served, "plain_per_chunk": plain,
+                         "notes": "resident: one persistent kernel of 64 workgroups fed through a work ring; "
+                                  "served: host-stepped batched launches; plain: one pcal_extract per chunk "
+                                  "on 4 HIP streams",
                          "capacity": {"note": "the same trace with every chunk available at once; sustained "
-                                              "Gsamples/s until every integration's results are in",
-                                      "served": cap_served, "plain_per_chunk": cap_plain}}
+                                              "Gsamples/s until every integration's results are in "
+                                              "(resident: 256 workgroups); hbm_frac at %.3f B per sample" % bps,
+                                      "resident": cap_res, "served": cap_served, "plain_per_chunk": cap_plain}}
     print(json.dumps(out), flush=True)
 
 

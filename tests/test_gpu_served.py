@@ -69,8 +69,12 @@ def _plain_integrations(buf, fs, fc, fo, nbits, integ, prec=0):
 ALONE_TOL = {0: F64_RTOL, 1: 1e-6, 2: 1e-5}
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
-def test_served_matches_plain_per_integration(prec):
+@pytest.mark.parametrize("prec,resident", [(0, False), (1, False), (2, False), (0, True), (1, True)])
+def test_served_matches_plain_per_integration(prec, resident):
+    """Host-step form, and the device-resident form (one persistent kernel fed through the work
+    ring: 24 workgroups, fewer than a chunk's 32 tasks, so chunks also run one task after another)."""
+    import time
+
     from paper_2501_05993_amd import pcal
 
     bufs = _streams_on_device()
@@ -79,6 +83,8 @@ def test_served_matches_plain_per_integration(prec):
     sids = []
     for fs, fc, fo, nbits, integ in STREAMS:
         sids.append(srv.open(fs, fc, fo, nbits, integ))
+    if resident:
+        srv.start(workgroups=24)
     # interleave the streams' chunks in a random order of arrival
     queue = []
     for i, (fs, fc, fo, nbits, integ) in enumerate(STREAMS):
@@ -95,7 +101,8 @@ def test_served_matches_plain_per_integration(prec):
         i = queue[j][0]
         arrivals.append(per[i][pos[i]])
         pos[i] += 1
-    say("served (precision form %d): %d streams, %d chunks" % (prec, len(STREAMS), len(arrivals)))
+    say("served (precision form %d, resident %s): %d streams, %d chunks" % (prec, resident, len(STREAMS),
+                                                                          len(arrivals)))
     got = {}
     k = 0
     while k < len(arrivals) or srv.stats()["queued_samples"] > 0:
@@ -110,6 +117,18 @@ def test_served_matches_plain_per_integration(prec):
             got[(sid, integ)] = srv.spectrum(sid, integ)
     import torch
 
+    if resident:
+        t_end = time.time() + 60.0
+        while time.time() < t_end:
+            srv.step()
+            for sid, integ in srv.poll():
+                got[(sid, integ)] = srv.spectrum(sid, integ)
+            st = srv.stats()
+            if st["queued_samples"] == 0 and st["inflight_finalizes"] == 0:
+                break
+        srv.stop()
+        for sid, integ in srv.poll():
+            got[(sid, integ)] = srv.spectrum(sid, integ)
     torch.cuda.synchronize()
     for _ in range(100):
         for sid, integ in srv.poll():
@@ -185,5 +204,31 @@ def test_served_admission_refuses_before_allocating():
     assert torch.cuda.mem_get_info()[0] == free0
     a = srv.open(32_000_000, 1_000_000, 0, 2, 1 << 20)
     assert srv.stats()["device_bytes"] == small
+    srv.close_stream(a)
+    srv.close()
+
+
+def test_served_resident_states_and_limits():
+    """Start twice / stop when not started: PCAL_ESTATE; a stream of more than 1792 tones is refused in the
+    device-resident form (PCAL_ENOTSUP) but admitted by the host-step form; a started loop with no work
+    stops at once and every workgroup leaves."""
+    from paper_2501_05993_amd import pcal
+
+    srv = pcal.PCalServer(mem_budget_bytes=1 << 30, max_streams=4)
+    with pytest.raises(pcal.PcalError) as e:
+        srv.stop()
+    assert e.value.code == pcal.ESTATE
+    srv.start(workgroups=8)
+    with pytest.raises(pcal.PcalError) as e:
+        srv.start(workgroups=8)
+    assert e.value.code == pcal.ESTATE
+    with pytest.raises(pcal.PcalError) as e:
+        srv.open(4_096_000_000, 1_000_000, 0, 2, 1 << 20)  # N = 4096
+    assert e.value.code == pcal.ENOTSUP
+    srv.stop()
+    a = srv.open(4_096_000_000, 1_000_000, 0, 2, 1 << 20)
+    with pytest.raises(pcal.PcalError) as e:
+        srv.start(workgroups=8)  # an open stream does not fit the resident form
+    assert e.value.code == pcal.ENOTSUP
     srv.close_stream(a)
     srv.close()
