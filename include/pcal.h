@@ -472,6 +472,37 @@ int pcal_server_stop(pcal_server_t s);
 int pcal_read_probe(const void *dev_ptr, int64_t bytes, int blocks, int threads, uint64_t *out,
                     pcal_stream_t stream, void *start_event, void *stop_event);
 
+/* ---- Allocation-free extraction -------------------------------------------
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  One call is
+ * one integration of the period-fold FP64 form, what pcal_create +
+ * pcal_extract + pcal_results_async + pcal_destroy compute for the same
+ * arguments, with no allocation and no host-to-device copy: the rotator
+ * tables, accumulators and counters live in a fixed device array of
+ * PCAL_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from its first
+ * use on that GPU until the process ends, and the tables are computed on the
+ * device.
+ *   Parameters as pcal_create; the global sample index of dev_ptr's first
+ *   sample is 0.  nsamples as pcal_extract (0 gives an empty integration).
+ *   dev_out: device memory of 4N + 1 doubles, owned by the caller, that
+ *   receives amp[0..N), phase[N..2N), Re C[2N..3N), Im C[3N..4N), delay[4N]
+ *   (the layout of pcal_results_async's host_out).
+ * Asynchronous on stream: dev_ptr and dev_out must stay valid until the
+ * stream has passed the call.  Every call on one GPU uses that GPU's one
+ * array and leaves its contents there (each call clears what must start at
+ * zero): calls that overlap on one GPU (on different streams or from several
+ * host threads) race and give wrong results; calls ordered on one stream do
+ * not.
+ * Errors: PCAL_EINVAL (parameters as pcal_create; null dev_out; nsamples
+ * negative or not a multiple of the samples per byte; tables and
+ * accumulators larger than the array, with the sizes in pcal_last_error()),
+ * PCAL_ENOTSUP (the stream needs a per-sample form: fold period over 2^22
+ * samples, or fs >= 2^32 Hz), PCAL_EHIP. */
+#define PCAL_NOALLOC_SCRATCH_BYTES (4 << 20)
+int pcal_extract_noalloc(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband,
+                         const void *dev_ptr, int64_t nsamples, double *dev_out, pcal_stream_t stream);
+
 /* Text of a status code. */
 const char *pcal_strerror(int code);
 

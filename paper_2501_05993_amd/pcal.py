@@ -113,6 +113,8 @@ _SIGS = {
     "pcal_read_probe": ([ctypes.c_void_p, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "pcal_last_error": ([], ctypes.c_char_p),
+    "pcal_extract_noalloc": ([_i64, _i64, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, _i64, ctypes.c_void_p,
+                              ctypes.c_void_p], ctypes.c_int),
 }
 
 
@@ -161,6 +163,23 @@ def read_probe(data, out, blocks: int, threads: int, stream=None, events=None) -
     _check(lib().pcal_read_probe(ctypes.c_void_p(data.data_ptr()), data.numel() * data.element_size(), blocks,
                                  threads, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream_handle(stream)),
                                  e0, e1), "pcal_read_probe")
+
+
+def extract_noalloc(fs: int, f_comb: int, f_offset: int, nbits: int, data, nsamples: int, out,
+                    sideband: int = 1, stream=None) -> None:
+    """One integration without any allocation (pcal_extract_noalloc): data is a device tensor (or a raw
+    device address) of packed samples, out a float64 device tensor of 4N + 1 elements receiving
+    amp, phase, Re C, Im C and the delay.  Asynchronous on stream."""
+    N = fs // f_comb if f_comb > 0 else 0
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+            and out.numel() >= 4 * N + 1):
+        raise ValueError("out needs 4N + 1 contiguous float64 elements on the device")
+    ptr = data.data_ptr() if isinstance(data, torch.Tensor) else int(data)
+    if isinstance(data, torch.Tensor) and nsamples * nbits > data.numel() * data.element_size() * 8:
+        raise ValueError("tensor holds fewer than nsamples samples")
+    _check(lib().pcal_extract_noalloc(fs, f_comb, f_offset, nbits, sideband, ctypes.c_void_p(ptr), nsamples,
+                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream_handle(stream))),
+           "pcal_extract_noalloc")
 
 
 def plan(fs: int, f_comb: int, f_offset: int, nbits: int, method: int = METHOD_AUTO,

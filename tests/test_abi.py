@@ -108,3 +108,21 @@ def test_plan_device_bytes():
     osc = pcal.plan(1_024_000_000, 1_000_000, 510_000, 8, method=pcal.METHOD_OSC)["device_bytes"]
     assert lut[pcal.PREC_F64] - osc == 16 * R
 
+
+@pytest.mark.parametrize("args,code", [
+    ((64_000_000, 1_000_000, 10_007, 2, 1, 4096), -6),      # per-sample form needed: PCAL_ENOTSUP
+    ((1 << 24, 1 << 20, 4, 2, 1, 4096), -1),                 # tables beyond the array: PCAL_EINVAL
+    ((64_000_000, 1_000_000, 10_000, 2, 1, 4097), -1),       # not a multiple of the samples per byte
+    ((64_000_000, 1_000_000, 10_000, 3, 1, 4096), -1),       # bad width
+    ((64_000_000, 1_000_000, 10_000, 2, 0, 4096), -1),       # bad sideband
+])
+def test_noalloc_refused_on_the_host(args, code):
+    """Refusals come from the host planner before any HIP call (no GPU needed)."""
+    import ctypes
+
+    from paper_2501_05993_amd import pcal
+
+    fs, fc, fo, nbits, sb, ns = args
+    dummy = ctypes.c_void_p(16)  # never dereferenced: the call is refused first
+    assert pcal.lib().pcal_extract_noalloc(fs, fc, fo, nbits, sb, dummy, ns, dummy, None) == code
+
