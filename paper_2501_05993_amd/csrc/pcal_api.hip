@@ -39,16 +39,28 @@ int64_t lcm_capped(int64_t a, int64_t b, int64_t limit) {
     return q * b;
 }
 
-// exp(-j 2 pi num / den) for 0 <= num < den, argument reduced to [-pi, pi].
+// exp(-j 2 pi num / den) for 0 <= num < den.  The angle a = 2 pi num / den is
+// split exactly in integers as a = k pi/2 + x with |x| <= pi/4 (k the nearest
+// quarter turn: 8 num = q den + r gives the octant q and the remainder r), so
+// libm sees only |x| <= pi/4, quarter turns come out exact, and cos a, sin a
+// follow from cos x, sin x by the quadrant k mod 4.
 void phasor(int64_t num, int64_t den, double *re, double *im) {
-    const double two_pi = 6.283185307179586476925286766559;
-    double ang;
-    if (2 * num <= den)
-        ang = two_pi * static_cast<double>(num) / static_cast<double>(den);
-    else
-        ang = -two_pi * static_cast<double>(den - num) / static_cast<double>(den);
-    *re = cos(ang);
-    *im = -sin(ang);
+    const unsigned __int128 n8 = static_cast<unsigned __int128>(num) * 8u;
+    const int q = static_cast<int>(n8 / static_cast<uint64_t>(den));
+    const int64_t r = static_cast<int64_t>(n8 % static_cast<uint64_t>(den));
+    const double quarter_pi = 0.78539816339744830961566084581988;
+    const double x = (q & 1) ? -quarter_pi * (static_cast<double>(den - r) / static_cast<double>(den))
+                             : quarter_pi * (static_cast<double>(r) / static_cast<double>(den));
+    const double cx = cos(x), sx = sin(x);
+    double ca, sa;
+    switch (((q + 1) / 2) & 3) {
+        case 0: ca = cx; sa = sx; break;
+        case 1: ca = -sx; sa = cx; break;
+        case 2: ca = -cx; sa = -sx; break;
+        default: ca = sx; sa = -cx; break;
+    }
+    *re = ca;
+    *im = -sa;
 }
 
 // Tuning knobs (defaults chosen by measurement; environment overrides for sweeps).
