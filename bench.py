@@ -27,13 +27,17 @@ METRIC = "Gsamples/s and % HBM peak, 2-bit fold @1e-4 rad; p99 latency per integ
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "fold2_64M_10k"
 STAMPED_STEPS = 30  # kernel-stamped steps after the timed region (the kernel's duration)
-KERNEL_SRC = os.path.join(ROOT, "paper_2501_05993_amd", "csrc", "pcal_kernels.hip")
+# the fold kernel's source: its body (pcal_fold.h) and its kernels and launchers (pcal_kernels.hip)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2501_05993_amd", "csrc", f) for f in ("pcal_fold.h", "pcal_kernels.hip")]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "fold_kernel_fold2_64M_10k_pmc.md")
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def pmc_traffic():
@@ -190,8 +194,6 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None,
         srv = pcal.PCalServer(mem_budget_bytes=16 << 30, max_streams=S, precision=prec)
         ids = [srv.open(sp.fs, sp.f_comb, sp.f_offset, sp.nbits, sp.fs) for sp in specs]
         rev = {v: k for k, v in enumerate(ids)}
-        if mode == "resident":
-            srv.start(workgroups=workgroups)
     else:
         K = 4
         hs = [pcal.PCal(sp.fs, sp.f_comb, sp.f_offset, sp.nbits, method=pcal.METHOD_PERIOD_FOLD, precision=prec)
@@ -202,6 +204,8 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None,
         integ_no = [0] * S
         pending = deque()
     torch.cuda.synchronize()
+    if mode == "resident":  # after the device-wide synchronisation: that would wait for the persistent kernel
+        srv.start(workgroups=workgroups)
     t0 = time.perf_counter()
     i = 0
     n_arr = len(t)

@@ -443,11 +443,16 @@ int pcal_server_destroy(pcal_server_t s);
  * finalize, writes the results into the stream's pinned result slot and
  * appends a completion record that pcal_server_poll reads.  A piece that
  * completes an integration is published only after the stream's previous
- * integration has been reported.  A workgroup waits only for the host to
- * publish: it leaves when pcal_server_stop sets the quit flag, or after about
- * 9 s without work, so the kernel always ends.  pcal_server_stop waits (up
- * to 30 s) for the published work, sets the quit flag and waits for the
- * kernel; the server continues in the host-step form.  pcal_server_close
+ * integration has been reported.  A workgroup claims a task only once it is
+ * published and waits only for the host to publish: it leaves when
+ * pcal_server_stop sets the quit flag, or after about 4-9 s without work, so
+ * the kernel always ends; pcal_server_step launches it again when every
+ * workgroup has left and work comes.  The kernel runs on a non-blocking
+ * stream of the server's own (after the work already enqueued on `stream`):
+ * a device-wide synchronisation (hipDeviceSynchronize) waits for it, so call
+ * pcal_server_stop first.  pcal_server_stop waits (up to 30 s) for the
+ * published work, sets the quit flag and waits for the kernel; the server
+ * continues in the host-step form.  pcal_server_close
  * and pcal_server_destroy wait for published work first.  Streams need at
  * most 1792 tones and a fold period of at most 32 column tiles in this form
  * (PCAL_ENOTSUP otherwise, at start or open), and the batch workgroup size

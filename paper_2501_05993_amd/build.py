@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpcal.so")
-SOURCES = ["pcal_api.hip", "pcal_kernels.hip", "pcal_rotate.hip", "pcal_batch.hip", "pcal_server.hip",
+SOURCES = ["pcal_api.hip", "pcal_kernels.hip", "pcal_served.hip", "pcal_rotate.hip", "pcal_batch.hip", "pcal_server.hip",
            "pcal_pulse.hip", "pcal_probe.hip", "pcal_noalloc.hip"]
 
 HIPCC_FLAGS = [

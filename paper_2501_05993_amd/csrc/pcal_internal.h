@@ -209,7 +209,7 @@ int fold_blocks_per_cu(int nbits, int prec, int threads, size_t lds);
 // One chunk of a served stream as the host publishes it in the work ring
 // (pinned, coherent host memory): the chunk's fold, planned for at most
 // `tasks` workgroups, and, when the chunk completes an integration, that
-// integration's finalize.  seq (chunk index + 1) is written last.
+// integration's finalize.  The host then raises the count of published tasks.
 struct ServedDesc {
     FoldArgs fold;
     FinArgs fin;
@@ -218,7 +218,6 @@ struct ServedDesc {
     int ntasks;       // fold workgroups of the chunk (<= the kernel's tasks per chunk)
     int fin_total;    // tasks of the whole integration if this chunk completes it, else 0
     long long integ;  // integration index (completion record)
-    unsigned long long seq;
 };
 
 // A finished integration, written by the device into the completion ring;
@@ -235,6 +234,7 @@ struct ServedArgs {
     const ServedDesc *ring;      // [cap] work ring (host memory, device address)
     unsigned long long *slot_free;  // [cap] host memory: chunk index + 1 of the last chunk whose tasks all ended
     ServedDone *done;            // [done_cap] completion ring (host memory)
+    const unsigned long long *published;  // host memory: tasks published (chunks published x tasks)
     const int *quit;             // host memory: nonzero asks every workgroup to leave once its wait finds no work
     int *status;                 // host memory: [0] workgroups that left, [1] workgroups that left on the spin limit
     unsigned long long *cursor;  // device: next task index to claim
@@ -243,7 +243,7 @@ struct ServedArgs {
     unsigned *task_done;         // device [streams][2]: tasks of the integration in the bank that ended
     unsigned *fin_total;         // device [streams][2]: tasks of that integration, once its last chunk is known
     int cap, done_cap, tasks;    // ring slots, completion records, tasks (workgroups) per chunk
-    unsigned long long spin_limit;  // polls of an empty ring slot before a workgroup leaves
+    unsigned long long spin_limit;  // idle polls (no published task left) before a workgroup leaves
 };
 
 void launch_served(const ServedArgs &a, int prec, int grid, int threads, size_t lds, hipStream_t s);

@@ -87,6 +87,8 @@ struct pcal_server_ctx {
     unsigned long long *slot_free = nullptr;  // coherent host memory, written by the device
     ServedDone *dn = nullptr;
     int *ctl = nullptr;                      // [0] quit, [1] workgroups that left, [2] of them on the spin limit
+    unsigned long long *pub = nullptr;       // tasks published (coherent host memory, read by the device)
+    int relaunches = 0;                      // kernels launched again after every workgroup had left
     ServedArgs args{};
     void *dmem = nullptr;                    // device counters
     unsigned long long published = 0;        // chunks published
@@ -113,9 +115,10 @@ bool valid_sid(const pcal_server_ctx *s, int sid) {
 constexpr int kRingSlots = 256;        // chunks in the work ring
 constexpr int kDoneSlots = 4096;       // completion records
 constexpr int kTasksPerChunk = 32;     // workgroups per chunk (PCAL_SERVED_TASKS)
-// Polls of an unpublished ring slot before a workgroup leaves (about 9 s: each
-// poll sleeps about 3.4 us and reads host memory), so that the kernel ends even
-// if the host never sets quit.
+// Idle polls (no published task to claim) before a workgroup leaves (about
+// 4-9 s: each poll sleeps about 1 us and reads host memory), so that the
+// kernel ends even if the host never sets quit; the host launches it again
+// when work comes (keep_alive).
 constexpr unsigned long long kSpinLimit = 2000000ull;
 
 template <class T>
@@ -158,6 +161,21 @@ void drain_done(pcal_server_ctx *s) {
     }
 }
 
+// Resident form: when every workgroup of the loop has left (each leaves after
+// about 4-9 s without work), launch it again; its state lives in device and
+// host memory, and no workgroup held a claim when it left, so the new launch
+// continues where the old one stopped.
+int keep_alive(pcal_server_ctx *s) {
+    if (__atomic_load_n(s->ctl + 1, __ATOMIC_ACQUIRE) < s->rgrid) return PCAL_OK;
+    PCAL_HIP(hipStreamSynchronize(s->rstream));
+    __atomic_store_n(s->ctl + 1, 0, __ATOMIC_RELAXED);
+    __atomic_store_n(s->ctl + 2, 0, __ATOMIC_RELAXED);
+    launch_served(s->args, kernel_prec(s->prec), s->rgrid, kServedThreads, kServedLds, s->rstream);
+    PCAL_HIP(hipGetLastError());
+    s->relaunches += 1;
+    return PCAL_OK;
+}
+
 // Resident form: every published chunk's tasks have ended.
 bool ring_idle(const pcal_server_ctx *s) {
     const unsigned long long lo = s->published > static_cast<unsigned long long>(s->cap)
@@ -172,6 +190,8 @@ bool ring_idle(const pcal_server_ctx *s) {
 int wait_idle(pcal_server_ctx *s, double seconds) {
     const auto t0 = std::chrono::steady_clock::now();
     for (;;) {
+        const int rc = keep_alive(s);
+        if (rc) return rc;
         drain_done(s);
         bool fin = false;
         for (const SrvStream &st : s->streams) fin = fin || (st.open && st.fin_inflight);
@@ -184,11 +204,18 @@ int wait_idle(pcal_server_ctx *s, double seconds) {
 }
 
 void free_resident(pcal_server_ctx *s) {
+    if (s->rstream) {
+        (void)hipStreamSynchronize(s->rstream);
+        (void)hipStreamDestroy(s->rstream);
+        s->rstream = nullptr;
+    }
     if (s->ring) (void)hipHostFree(s->ring);
     if (s->slot_free) (void)hipHostFree(s->slot_free);
     if (s->dn) (void)hipHostFree(s->dn);
     if (s->ctl) (void)hipHostFree(s->ctl);
+    if (s->pub) (void)hipHostFree(s->pub);
     if (s->dmem) (void)hipFree(s->dmem);
+    s->pub = nullptr;
     s->ring = nullptr;
     s->slot_free = nullptr;
     s->dn = nullptr;
@@ -257,8 +284,9 @@ int publish(pcal_server_ctx *s, int64_t *samples) {
                 st.slot_ready[k] = false;
                 st.fin_inflight = true;
             }
-            __atomic_store_n(&d.seq, c + 1, __ATOMIC_RELEASE);  // the descriptor is complete: publish it
             s->published = c + 1;
+            // the descriptor is complete: publish its tasks
+            __atomic_store_n(s->pub, s->published * static_cast<unsigned long long>(s->tasks), __ATOMIC_RELEASE);
             if (samples) *samples += take;
             h->n_total += take;
             pc.ptr += take / st.spb;
@@ -405,6 +433,8 @@ int pcal_server_step(pcal_server_t s, pcal_stream_t stream, int64_t *samples_dis
     if (!s) return PCAL_EINVAL;
     if (samples_dispatched) *samples_dispatched = 0;
     if (s->resident) {
+        const int rc = keep_alive(s);
+        if (rc) return rc;
         drain_done(s);
         return publish(s, samples_dispatched);
     }
@@ -563,7 +593,8 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
     s->cap = kRingSlots;
     s->done_cap = kDoneSlots;
     if ((rc = coherent_alloc(&s->ring, s->cap)) || (rc = coherent_alloc(&s->slot_free, s->cap)) ||
-        (rc = coherent_alloc(&s->dn, s->done_cap)) || (rc = coherent_alloc(&s->ctl, 4))) {
+        (rc = coherent_alloc(&s->dn, s->done_cap)) || (rc = coherent_alloc(&s->ctl, 4)) ||
+        (rc = coherent_alloc(&s->pub, 1))) {
         free_resident(s);
         return rc;
     }
@@ -577,7 +608,31 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
             return e == hipErrorOutOfMemory ? PCAL_ENOMEM : PCAL_EHIP;
         }
     }
-    hipStream_t hs = static_cast<hipStream_t>(stream);
+    // The loop runs on a stream of its own that does not synchronise with the
+    // null stream (default priority): synchronous copies elsewhere (tables of
+    // streams opened later) must not wait for the persistent kernel.  It
+    // starts after the work already enqueued on the caller's stream.
+    hipStream_t hs = nullptr;
+    {
+        hipError_t e = hipStreamCreateWithFlags(&hs, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            set_error("hipStreamCreateWithFlags", e);
+            free_resident(s);
+            return PCAL_EHIP;
+        }
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, static_cast<hipStream_t>(stream));
+        if (e == hipSuccess) e = hipStreamWaitEvent(hs, ev, 0);
+        if (ev) (void)hipEventDestroy(ev);
+        if (e != hipSuccess) {
+            set_error("ordering the served loop after the caller's stream", e);
+            (void)hipStreamDestroy(hs);
+            free_resident(s);
+            return PCAL_EHIP;
+        }
+    }
+    s->rstream = hs;
     launch_zero(s->dmem, dbytes, hs);
     ServedArgs &a = s->args;
     a = ServedArgs{};
@@ -589,7 +644,8 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
     a.fin_total = a.task_done + nsb;
     if ((rc = device_address(s->ring, const_cast<ServedDesc **>(&a.ring))) ||
         (rc = device_address(s->slot_free, &a.slot_free)) || (rc = device_address(s->dn, &a.done)) ||
-        (rc = device_address(s->ctl, &a.status))) {
+        (rc = device_address(s->ctl, &a.status)) ||
+        (rc = device_address(s->pub, const_cast<unsigned long long **>(&a.published)))) {
         free_resident(s);
         return rc;
     }
@@ -601,8 +657,8 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
     a.spin_limit = kSpinLimit;
     s->published = 0;
     s->done_next = 0;
+    s->relaunches = 0;
     s->rgrid = workgroups;
-    s->rstream = hs;
     launch_served(a, kernel_prec(s->prec), workgroups, kServedThreads, kServedLds, hs);
     {
         const hipError_t e = hipGetLastError();

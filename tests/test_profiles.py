@@ -19,8 +19,12 @@ def _recorded(name):
 
 
 def test_fold_profiles_match_kernel_source():
-    with open(os.path.join(ROOT, "paper_2501_05993_amd", "csrc", "pcal_kernels.hip"), "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    """The fold kernel's source is its body (pcal_fold.h) and its kernels (pcal_kernels.hip)."""
+    h = hashlib.sha256()
+    for f in ("pcal_fold.h", "pcal_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2501_05993_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()[:16]
     assert _recorded("fold_kernel_fold2_64M_10k_pmc.md") == sha
     assert _recorded("fold_kernel_fold2_64M_10k_trace.md") == sha
 
