@@ -167,7 +167,7 @@ def _pieces(sp, pool, pos, n):
     return out
 
 
-def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None, workgroups=64):
+def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None, workgroups=256):
     """Replay the arrival trace through the served form (mode "served": host-stepped; "resident": the
     device-resident loop of `workgroups` workgroups) or through plain per-chunk extraction ("plain"),
     all in precision form `prec` (default: mixed).
@@ -253,8 +253,10 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None,
                 s_ = rev[sv]
                 lat.append(time.perf_counter() - t0 - last_arrival[(s_, k)])
                 done_samples += specs[s_].fs
-            st_ = srv.stats()
-            idle = st_["queued_samples"] == 0 and st_["inflight_finalizes"] == 0
+            idle = False
+            if i >= n_arr:  # every chunk submitted: has all of it been reported?
+                st_ = srv.stats()
+                idle = st_["queued_samples"] == 0 and st_["inflight_finalizes"] == 0
         else:
             while pending and pending[0][0].query():
                 _, s_, k = pending.popleft()
@@ -264,8 +266,10 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None,
         if i >= n_arr and (idle or now > t[-1] + drain_s):
             break
     wall = time.perf_counter() - t0
+    loop = None
     if mode == "resident":
         srv.stop()
+        loop = srv.loop_stats()
     torch.cuda.synchronize()
     if served:
         srv.close()
@@ -274,14 +278,20 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None,
             h.close()
     offered = float(ns.sum())
     if flat_out:
-        return {"samples": offered, "sustained_gsps": round(offered / wall / 1e9, 1), "wall_s": round(wall, 3),
-                "integrations": len(lat)}
-    return {"integrations": len(lat),
+        r = {"samples": offered, "sustained_gsps": round(offered / wall / 1e9, 1), "wall_s": round(wall, 3),
+             "integrations": len(lat)}
+        if loop:
+            r["loop"] = loop
+        return r
+    r = {"integrations": len(lat),
             "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3) if lat else None,
             "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3) if lat else None,
             "sustained_gsps": round(offered / wall / 1e9, 2),
             "completed_integration_gsps": round(done_samples / wall / 1e9, 2),
             "wall_s": round(wall, 2)}
+    if loop:
+        r["loop"] = loop
+    return r
 
 
 def precision_report(pcal, torch, synth, oracle=None):
@@ -668,7 +678,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(i)
-    h.sync()
+    h.flush()  # the last integration's finalize, enqueued now (no later fold to carry it)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     last = ring[(args.steps - 1) % 8].numpy().copy()
@@ -771,7 +781,7 @@ def main():
         plain = served_run(pcal, torch, setup, "plain")
         print("[bench] serving capacity: the same trace with every chunk available at once",
               file=sys.stderr, flush=True)
-        cap_res = served_run(pcal, torch, setup, "resident", flat_out=True, workgroups=256)
+        cap_res = served_run(pcal, torch, setup, "resident", flat_out=True)
         cap_served = served_run(pcal, torch, setup, "served", flat_out=True)
         cap_plain = served_run(pcal, torch, setup, "plain", flat_out=True)
         # bytes per sample of the mix (2-bit 0.25 B, 8-bit 1 B), for the HBM fraction of the capacity
@@ -784,12 +794,12 @@ def main():
                                      "%.0f s trace, mixed precision form; chunks drawn from device pools of "
                                      "%.0f MB in all" % (args.served_seconds, pool_bytes / 1e6),
                          "resident": resident, "served": served, "plain_per_chunk": plain,
-                         "notes": "resident: one persistent kernel of 64 workgroups fed through a work ring; "
+                         "notes": "resident: one persistent kernel of 256 workgroups fed through a work ring; "
                                   "served: host-stepped batched launches; plain: one pcal_extract per chunk "
                                   "on 4 HIP streams",
                          "capacity": {"note": "the same trace with every chunk available at once; sustained "
-                                              "Gsamples/s until every integration's results are in "
-                                              "(resident: 256 workgroups); hbm_frac at %.3f B per sample" % bps,
+                                              "Gsamples/s until every integration's results are in; "
+                                              "hbm_frac at %.3f B per sample" % bps,
                                       "resident": cap_res, "served": cap_served, "plain_per_chunk": cap_plain}}
     print(json.dumps(out), flush=True)
 

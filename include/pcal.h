@@ -432,36 +432,59 @@ int pcal_server_stats(pcal_server_t s, int64_t *queued_samples, int *inflight_fi
 int pcal_server_destroy(pcal_server_t s);
 
 /* Device-resident form of the served loop.  pcal_server_start launches one
- * persistent kernel of `workgroups` workgroups on `stream`; from then on
- * pcal_server_step launches nothing: it publishes the queued pieces (split at
- * integration boundaries, every queued piece that fits, not one per stream)
- * as descriptors in a work ring in pinned, coherent host memory and returns.
- * The kernel's workgroups claim the pieces' tasks in order (a piece is up to
- * 32 fold workgroups' worth, PCAL_SERVED_TASKS), fold them into the stream's
- * accumulator bank in HBM (two banks per stream, alternating by
- * integration), and the task that completes an integration runs its FP64
+ * persistent kernel of `workgroups` workgroups (2 to 2048; at most as many as
+ * are resident at once on the device is the useful range) on `stream`; from
+ * then on pcal_server_step launches nothing: it publishes the queued pieces
+ * (split at integration boundaries, every queued piece that fits, not one per
+ * stream) as descriptors in a work ring of 256 chunks in pinned, coherent
+ * host memory and returns.  Workgroup 0 of the kernel schedules: it reads the
+ * count of published chunks, copies each new descriptor into device memory
+ * and hands the chunks' fold tasks (one per 128 KiB of the chunk,
+ * PCAL_SERVED_TASK_KIB, at least its column tiles, at most 32,
+ * PCAL_SERVED_TASKS) in order to idle workgroups through per-workgroup
+ * mailboxes in device memory.  The other workgroups fold their task into the
+ * stream's accumulator bank in HBM (two banks per stream, alternating by
+ * integration); the task that completes an integration runs its FP64
  * finalize, writes the results into the stream's pinned result slot and
  * appends a completion record that pcal_server_poll reads.  A piece that
  * completes an integration is published only after the stream's previous
- * integration has been reported.  A workgroup claims a task only once it is
- * published and waits only for the host to publish: it leaves when
- * pcal_server_stop sets the quit flag, or after about 4-9 s without work, so
- * the kernel always ends; pcal_server_step launches it again when every
- * workgroup has left and work comes.  The kernel runs on a non-blocking
- * stream of the server's own (after the work already enqueued on `stream`):
- * a device-wide synchronisation (hipDeviceSynchronize) waits for it, so call
- * pcal_server_stop first.  pcal_server_stop waits (up to 30 s) for the
- * published work, sets the quit flag and waits for the kernel; the server
- * continues in the host-step form.  pcal_server_close
- * and pcal_server_destroy wait for published work first.  Streams need at
- * most 1792 tones and a fold period of at most 32 column tiles in this form
- * (PCAL_ENOTSUP otherwise, at start or open), and the batch workgroup size
- * of 512 threads (PCAL_BATCH_THREADS unset).
- * Errors: PCAL_EINVAL, PCAL_ESTATE (already started / not started),
- * PCAL_ENOTSUP, PCAL_ENOMEM, PCAL_EHIP (a launch failed, or the published
- * work did not end in time). */
+ * integration has been reported.  The loop leaves when pcal_server_stop sets
+ * the quit flag, or about 4 s after its last work (PCAL_SERVED_IDLE_MS),
+ * each time only with every published task ended, so the kernel always ends;
+ * pcal_server_step launches it again when every workgroup has left and work
+ * comes.  The kernel runs on a non-blocking stream of the server's own (after
+ * the work already enqueued on `stream`): a device-wide synchronisation
+ * (hipDeviceSynchronize) waits for it, so call pcal_server_stop first.
+ * pcal_server_stop waits (up to 30 s) for the published work, sets the quit
+ * flag and waits for the kernel; the server continues in the host-step form.
+ * pcal_server_close and pcal_server_destroy wait for published work first.
+ * Streams need at most 1792 tones and a fold period of at most 32 column
+ * tiles in this form (PCAL_ENOTSUP otherwise, at start or open), and the
+ * batch workgroup size of 512 threads (PCAL_BATCH_THREADS unset).
+ * Errors: PCAL_EINVAL (workgroups outside 2..2048), PCAL_ESTATE (already
+ * started / not started), PCAL_ENOTSUP, PCAL_ENOMEM, PCAL_EHIP (a launch
+ * failed, or the published work did not end in time). */
 int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream);
 int pcal_server_stop(pcal_server_t s);
+
+/* Counters of the device-resident loop since pcal_server_start (observability
+ * of the loop, not part of the extraction).  Writes min(n, PCAL_LOOP_STATS)
+ * values to out (host memory of the caller), in this order:
+ *   [0] chunks published, [1] fold tasks run, [2] fold tasks published
+ *   (equal to [1] once the published work has ended), [3] descriptors
+ *   the scheduler copied into device memory, [4] scheduler rounds (each reads
+ *   the host's count once), [5] integrations finalized, [6] relaunches of the
+ *   kernel, [7] scheduler rounds that handed out nothing, then worker time
+ *   summed over tasks, in ns: [8] waiting for the task (from the end of the
+ *   previous one), [9] reading the descriptor, [10] folding, [11] counting
+ *   and finalizing.
+ * The scheduler adds its counts ([3], [4], [7]) when the loop leaves; the
+ * others are read while the kernel runs, each value on its own, so the set is
+ * a consistent snapshot only after pcal_server_stop; it is kept until the
+ * next pcal_server_start.
+ * Errors: PCAL_EINVAL (null s or out, n < 0), PCAL_ESTATE (never started). */
+#define PCAL_LOOP_STATS 12
+int pcal_server_loop_stats(pcal_server_t s, int64_t *out, int n);
 
 /* Streaming-read reference (not part of the extraction): reads `bytes`
  * bytes at dev_ptr once with 16-byte non-temporal loads, as the fold kernel

@@ -215,8 +215,8 @@ struct ServedDesc {
     FinArgs fin;
     int sid;          // stream slot of the server
     int bank;         // accumulator bank of the integration
-    int ntasks;       // fold workgroups of the chunk (<= the kernel's tasks per chunk)
-    int fin_total;    // tasks of the whole integration if this chunk completes it, else 0
+    int ntasks;       // fold tasks of the chunk (1 <= ntasks <= the task indices per chunk)
+    int fin_total;    // fold tasks of the whole integration if this chunk completes it, else 0
     long long integ;  // integration index (completion record)
 };
 
@@ -229,26 +229,46 @@ struct ServedDone {
     unsigned long long seq;
 };
 
-// Arguments of the persistent served kernel.
+// Arguments of the persistent served kernel.  Workgroup 0 schedules, the
+// others fold.  The scheduler alone reads host memory: the count of published
+// tasks, the quit flag and each new chunk's descriptor, which it copies into
+// device memory (dring).  It hands tasks to idle workers through per-worker
+// mailbox lines (mail_assigned, written by the scheduler; mail_done, written
+// by the worker), so that no line in device memory is polled by more than two
+// workgroups: lines that many workgroups poll with coherent loads serialise at
+// the memory.
 struct ServedArgs {
     const ServedDesc *ring;      // [cap] work ring (host memory, device address)
     unsigned long long *slot_free;  // [cap] host memory: chunk index + 1 of the last chunk whose tasks all ended
     ServedDone *done;            // [done_cap] completion ring (host memory)
     const unsigned long long *published;  // host memory: tasks published (chunks published x tasks)
-    const int *quit;             // host memory: nonzero asks every workgroup to leave once its wait finds no work
-    int *status;                 // host memory: [0] workgroups that left, [1] workgroups that left on the spin limit
-    unsigned long long *cursor;  // device: next task index to claim
+    const int *quit;             // host memory: nonzero asks the loop to leave once every published task ended
+    int *status;                 // host memory: [0] workgroups that left, [1] of them after the idle limit
+    unsigned long long *sched;   // device: [0] next chunk to hand out (kept across launches)
     unsigned long long *done_cursor;  // device: next completion record
     unsigned *slot_cnt;          // device [cap]: tasks of the chunk in the slot that ended
     unsigned *task_done;         // device [streams][2]: tasks of the integration in the bank that ended
     unsigned *fin_total;         // device [streams][2]: tasks of that integration, once its last chunk is known
-    int cap, done_cap, tasks;    // ring slots, completion records, tasks (workgroups) per chunk
-    unsigned long long spin_limit;  // idle polls (no published task left) before a workgroup leaves
+    FinArgs *fin_args;           // device [streams][2]: that integration's finalize, from its last chunk
+    ServedDesc *dring;           // device [cap]: the scheduler's copy of each slot's descriptor
+    unsigned long long *mail_assigned;  // device [grid][kMailStride]: task + 2 handed to the worker; 1: leave
+    unsigned long long *mail_done;      // device [grid][kMailStride]: task + 2 the worker finished; 1: started
+    int cap, done_cap, tasks;    // ring slots, completion records, task indices per chunk
+    int grid;                    // workgroups of the launch (the scheduler and grid - 1 workers)
+    unsigned long long idle_ticks;    // wall-clock ticks without work before the loop leaves
+    unsigned long long worker_ticks;  // ticks a worker waits for its scheduler before it leaves anyway
+    unsigned long long *stat;    // device [kServedStats]: loop counters (pcal_server_loop_stats order from [1])
 };
+constexpr int kServedStats = 12;
+constexpr int kMailStride = 32;            // u64 words per mailbox (256 B: a line of its own)
+constexpr int kServedMaxWorkgroups = 2048;
+constexpr int kServedMaxRing = 256;        // ring slots the scheduler can look ahead over (<= its threads)
 
 void launch_served(const ServedArgs &a, int prec, int grid, int threads, size_t lds, hipStream_t s);
 constexpr int kServedThreads = 512;          // the batched form's member workgroup size
 constexpr size_t kServedLds = 61440;         // fold geometries up to 12800 positions, finalize up to 1792 tones
+static_assert(kServedLds >= 8 * kServedMaxWorkgroups + 4 * (2 * kServedMaxRing + 17), "scheduler state");
+static_assert(kServedMaxRing <= kServedThreads, "one scheduler thread per pending chunk");
 constexpr int kServedMaxTones = 1792;
 
 // Work-lists of the batched kernels: item i owns workgroups [first[i],

@@ -1,104 +1,309 @@
 // The device-resident served loop (pcal_server_start): one persistent kernel
-// that claims published chunk tasks, folds them with the fold body of
-// pcal_fold.h and finalizes each integration in the task that completes it.
+// whose workgroup 0 schedules and whose other workgroups fold published chunk
+// tasks with the fold body of pcal_fold.h, each integration finalized by the
+// task that completes it.
+#include <stddef.h>
+
 #include "pcal_fold.h"
 
 namespace pcal {
 namespace {
 
-// ---------------------------------------------------------------- served loop
+// Memory ordering.  An acquire or release at agent or system scope makes
+// gfx950 invalidate or write back a whole L2 (one per XCD), so the loop keeps
+// them out of everything done per poll or per task: it polls, hands out and
+// counts with relaxed atomics, which are coherent per location, and orders
+// them by waiting for its outstanding memory operations (s_waitcnt) where one
+// must be complete before the next is issued.  Host memory is read with
+// system-scope loads, which no GPU cache keeps; the device copies of the
+// descriptors are written and read with agent-scope atomics.  The one acquire
+// (before a finalize reads the bank that other workgroups' atomics filled)
+// and the one release (after it clears that bank with plain stores) come once
+// per integration.
 
-// Copy n 32-bit words from coherent host memory with system-scope loads (the
-// host may have written them after this kernel started).
-__device__ __forceinline__ void copy_from_host(uint32_t *dst, const uint32_t *src, int n) {
-    for (int i = static_cast<int>(threadIdx.x); i < n; i += blockDim.x)
-        dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+__device__ __forceinline__ unsigned long long ld_agent(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void st_agent(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void add_stat(const ServedArgs &sa, int k, unsigned long long v) {
+    if (v) __hip_atomic_fetch_add(sa.stat + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Persistent kernel of the served form: every workgroup claims published
-// tasks in increasing order (task t is workgroup t mod tasks of chunk
-// t / tasks; a task is claimed only once the host has published it, by a
-// compare-and-swap on the claim cursor, so a workgroup never holds a claim on
-// unpublished work), runs its share of the chunk's fold into the stream's
-// accumulator bank, and counts the task.  The task that completes an
-// integration (its count reaches the integration's total, which the
-// integration's last chunk records before counting) runs that integration's
-// finalize alone, then writes a completion record.  No workgroup ever waits
-// for another: a wait is only for the host to publish, and it ends when the
-// host sets quit or after spin_limit idle polls (the host relaunches the
-// kernel when every workgroup has left and work is published).
-template <int PREC>
-__global__ void __launch_bounds__(kServedThreads) served_kernel(ServedArgs sa) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ __align__(16) ServedDesc d;
-    __shared__ unsigned long long s_task;
-    __shared__ int s_go, s_fin;
-    const int t = static_cast<int>(threadIdx.x);
+constexpr int kWords = static_cast<int>(sizeof(ServedDesc) / 4);
+constexpr int kFinWords = static_cast<int>(sizeof(FinArgs) / 4);
+static_assert(sizeof(FinArgs) % 4 == 0, "finalize arguments are copied as words");
+constexpr int kNtasksWord = static_cast<int>(offsetof(ServedDesc, ntasks) / 4);
+constexpr unsigned long long kLeave = 1ull;  // mailbox value: leave the loop (tasks are handed out as task + 2)
+
+// Workgroup 0: hand the published tasks out, chunk after chunk and in task
+// order within a chunk, to the workers whose mailbox shows them idle.  Each
+// round: read the host's count of published tasks and its quit flag; copy the
+// descriptors of newly published chunks into device memory (complete before
+// any of their tasks is handed out); read every worker's mailbox; give the
+// k-th idle worker (in worker order) the k-th pending task.  It leaves, and
+// tells every worker to leave, when quit is set or idle_ticks pass without
+// work, in both cases only with no task pending and no worker busy.
+//
+// The host publishes chunk c only after chunk c - cap has ended, so at most
+// cap chunks are pending and a slot's descriptor is replaced only after every
+// task of its previous chunk has read it.
+__device__ void schedule(const ServedArgs &sa, unsigned char *lds) {
+    const int t = static_cast<int>(threadIdx.x), nt = static_cast<int>(blockDim.x);
+    const int lane = t & 63, wave = t >> 6, nwaves = (nt + 63) / 64;
+    const int G = sa.grid;
+    unsigned long long *s_assigned = reinterpret_cast<unsigned long long *>(lds);  // [G]: last value handed out
+    int *s_ntasks = reinterpret_cast<int *>(s_assigned + kServedMaxWorkgroups);      // [kServedMaxRing]
+    int *s_pref = s_ntasks + kServedMaxRing;  // [kServedMaxRing + 1]: exclusive prefix of the pending tasks
+    int *s_wave = s_pref + kServedMaxRing + 1;  // [16]: per-wave totals
+    __shared__ unsigned long long s_chunks, s_copied, s_next;
+    __shared__ int s_next_wg, s_quit, s_pending, s_busy, s_handed;
+    for (int w = t; w < G; w += nt) s_assigned[w] = 1ull;  // a started, idle worker's mailbox reads 1
+    if (t == 0) {
+        // every chunk before s_next was handed out, and has ended, in an earlier launch
+        s_next = ld_agent(sa.sched);
+        s_copied = s_next;
+        s_next_wg = 0;
+    }
+    __syncthreads();
+    unsigned long long polls = 0, rounds_idle = 0, copies = 0;
+    unsigned long long t_work = wall_clock64();
     for (;;) {
         if (t == 0) {
-            int go = 0;
-            unsigned long long task = 0;
-            for (unsigned long long idle = 0; idle < sa.spin_limit;) {
-                const unsigned long long pub =
-                    __hip_atomic_load(sa.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-                unsigned long long c = __hip_atomic_load(sa.cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (c < pub) {
-                    if (__hip_atomic_compare_exchange_strong(sa.cursor, &c, c + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT)) {
-                        task = c;
-                        go = 1;
-                        break;
-                    }
-                    continue;  // another workgroup took it: look again at once
-                }
-                if (__hip_atomic_load(sa.quit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
-                    go = -1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(32);
-                ++idle;
-            }
-            s_task = task;
-            s_go = go;
+            const unsigned long long pub =
+                __hip_atomic_load(sa.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            s_quit = __hip_atomic_load(sa.quit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            s_chunks = pub / static_cast<unsigned>(sa.tasks);
+            ++polls;
         }
         __syncthreads();
-        if (s_go != 1) {
+        const unsigned long long chunks = s_chunks, copied = s_copied, next = s_next;
+        // copy the new descriptors (the host wrote each before raising the
+        // count): word w of chunk copied + c, all threads
+        const int ncopy = static_cast<int>(chunks - copied);
+        for (int i = t; i < ncopy * kWords; i += nt) {
+            const int c = i / kWords, w = i - c * kWords;
+            const int slot = static_cast<int>((copied + c) % static_cast<unsigned>(sa.cap));
+            const uint32_t v = __hip_atomic_load(reinterpret_cast<const uint32_t *>(sa.ring + slot) + w,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(reinterpret_cast<uint32_t *>(sa.dring + slot) + w, v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            if (w == kNtasksWord) s_ntasks[slot] = static_cast<int>(v);
+        }
+        wait_memory();  // the copies are complete before any of their tasks is handed out
+        copies += static_cast<unsigned long long>(ncopy);
+        __syncthreads();
+        if (t == 0) s_copied = chunks;
+        // pending tasks: chunks [next, chunks), the first one from task s_next_wg
+        const int P = static_cast<int>(chunks - next);  // <= cap <= kServedMaxRing <= nt
+        int rem = 0;
+        if (t < P) {
+            const int slot = static_cast<int>((next + t) % static_cast<unsigned>(sa.cap));
+            rem = s_ntasks[slot] - (t == 0 ? s_next_wg : 0);
+        }
+        int incl = rem;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) s_wave[wave] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            if (w < wave) before += s_wave[w];
+            total += s_wave[w];
+        }
+        if (t < P) s_pref[t + 1] = before + incl;
+        if (t == 0) s_pref[0] = 0;
+        __syncthreads();
+        // idle workers ranked in worker order: the k-th gets pending task k
+        int rank_base = 0, busy = 0, handed = 0;
+        for (int w0 = 1; w0 < G; w0 += nt) {
+            const int w = w0 + t;
+            bool idle = false;
+            if (w < G) {
+                const unsigned long long dv = ld_agent(sa.mail_done + static_cast<size_t>(w) * kMailStride);
+                idle = dv == s_assigned[w];
+                // not started yet (its mailbox still zero, nothing handed to it): neither idle nor busy
+                busy += (idle || (dv == 0ull && s_assigned[w] == 1ull)) ? 0 : 1;
+            }
+            const unsigned long long mask = __ballot(idle);
+            __syncthreads();  // every read of s_wave above is done
+            if (lane == 0) s_wave[wave] = __popcll(mask);
+            __syncthreads();
+            int wb = 0, wt = 0;
+            for (int v = 0; v < nwaves; ++v) {
+                wt += s_wave[v];
+                if (v < wave) wb += s_wave[v];
+            }
+            const int r = rank_base + wb + __popcll(mask & ((1ull << lane) - 1ull));
+            if (idle && r < total) {
+                // pending task r: chunk j with s_pref[j] <= r < s_pref[j + 1]
+                int lo = 0, hi = P - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pref[mid] <= r)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                const int wg = (lo == 0 ? s_next_wg : 0) + (r - s_pref[lo]);
+                const unsigned long long task = (next + lo) * static_cast<unsigned>(sa.tasks) + wg;
+                s_assigned[w] = task + 2;
+                st_agent(sa.mail_assigned + static_cast<size_t>(w) * kMailStride, task + 2);
+                ++handed;
+            }
+            rank_base += wt;
+        }
+        // tasks handed out and workers busy, summed over the workgroup
+        int h = handed, b = busy;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            h += __shfl_xor(h, d, 64);
+            b += __shfl_xor(b, d, 64);
+        }
+        if (t == 0) {
+            s_handed = 0;
+            s_busy = 0;
+        }
+        __syncthreads();
+        if (lane == 0) {
+            atomicAdd(&s_handed, h);
+            atomicAdd(&s_busy, b);
+        }
+        __syncthreads();
+        const int nh = s_handed;
+        if (t == 0) {
+            // move past the tasks handed out
+            if (nh >= total) {
+                s_next = chunks;
+                s_next_wg = 0;
+            } else if (nh > 0) {
+                int lo = 0, hi = P - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pref[mid] <= nh)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                s_next_wg = (lo == 0 ? s_next_wg : 0) + (nh - s_pref[lo]);
+                s_next = next + lo;
+            }
+            s_pending = total - nh;
+        }
+        __syncthreads();
+        const bool quiet = s_pending == 0 && s_busy == 0 && nh == 0;
+        const unsigned long long now = wall_clock64();
+        if (!quiet) t_work = now;
+        if (quiet && (s_quit || now - t_work > sa.idle_ticks)) {
+            for (int w = 1 + t; w < G; w += nt)
+                st_agent(sa.mail_assigned + static_cast<size_t>(w) * kMailStride, kLeave);
             if (t == 0) {
-                __hip_atomic_fetch_add(sa.status, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-                if (s_go == 0) __hip_atomic_fetch_add(sa.status + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                st_agent(sa.sched, s_next);
+                add_stat(sa, 3, copies);
+                add_stat(sa, 4, polls);
+                add_stat(sa, 7, rounds_idle);
+                wait_memory();
+                __hip_atomic_fetch_add(sa.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (!s_quit) __hip_atomic_fetch_add(sa.status + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             }
             return;
         }
-        const unsigned long long task = s_task;
+        if (nh == 0) {
+            ++rounds_idle;
+            __builtin_amdgcn_s_sleep(4);
+        }
+    }
+}
+
+// Workgroups 1 .. grid - 1: wait on the own mailbox for a task (or the word to
+// leave), fold the task into the stream's accumulator bank and count it; the
+// task whose count completes an integration finalizes it and writes its
+// completion record.  That task may belong to any chunk of the integration,
+// and only the last chunk's descriptor carries the finalize: its tasks leave
+// a copy per stream and bank in device memory before they count.  The wait is
+// bounded: worker_ticks is far beyond the scheduler's own idle limit, after
+// which the scheduler always sends the word to leave.
+template <int PREC>
+__device__ void work(const ServedArgs &sa, unsigned char *lds) {
+    __shared__ __align__(16) ServedDesc d;
+    __shared__ __align__(16) FinArgs fa;
+    __shared__ unsigned long long s_val;
+    __shared__ int s_fin;
+    const int t = static_cast<int>(threadIdx.x);
+    const size_t me = static_cast<size_t>(blockIdx.x) * kMailStride;
+    unsigned long long last = 0ull, t_prev = wall_clock64();
+    if (t == 0) st_agent(sa.mail_done + me, 1ull);  // started and idle
+    for (;;) {
+        if (t == 0) {
+            unsigned long long v = ld_agent(sa.mail_assigned + me);
+            const unsigned long long t0 = wall_clock64();
+            while (v == last || v == 0ull) {
+                if (wall_clock64() - t0 > sa.worker_ticks) {
+                    v = kLeave;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+                v = ld_agent(sa.mail_assigned + me);
+            }
+            s_val = v;
+        }
+        __syncthreads();
+        const unsigned long long val = s_val;
+        if (val == kLeave) {
+            if (t == 0) __hip_atomic_fetch_add(sa.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            return;
+        }
+        const unsigned long long t_claim = wall_clock64();
+        const unsigned long long task = val - 2;
         const unsigned long long chunk = task / static_cast<unsigned>(sa.tasks);
         const int wg = static_cast<int>(task % static_cast<unsigned>(sa.tasks));
         const int slot = static_cast<int>(chunk % static_cast<unsigned>(sa.cap));
-        copy_from_host(reinterpret_cast<uint32_t *>(&d), reinterpret_cast<const uint32_t *>(sa.ring + slot),
-                       static_cast<int>(sizeof(ServedDesc) / 4));
+        uint32_t *dw = reinterpret_cast<uint32_t *>(&d);
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(sa.dring + slot);
+        for (int i = t; i < kWords; i += static_cast<int>(blockDim.x))
+            dw[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        if (wg < d.ntasks) {
-            if (d.fold.nbits == 2)
-                fold_body<2, PREC>(d.fold, wg, lds);
-            else
-                fold_body<8, PREC>(d.fold, wg, lds);
+        const unsigned long long t_desc = wall_clock64();
+        if (d.fold.nbits == 2)
+            fold_body<2, PREC>(d.fold, wg, lds);
+        else
+            fold_body<8, PREC>(d.fold, wg, lds);
+        const int bank_ix = 2 * d.sid + d.bank;
+        if (d.fin_total > 0) {  // the integration's last chunk: its finalize, for whichever task completes it
+            uint32_t *dst = reinterpret_cast<uint32_t *>(sa.fin_args + bank_ix);
+            const uint32_t *fw = reinterpret_cast<const uint32_t *>(&d.fin);
+            for (int i = t; i < kFinWords; i += static_cast<int>(blockDim.x))
+                __hip_atomic_store(dst + i, fw[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        // every wave's atomics are acknowledged before the task is counted
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        // every wave's atomics (and the copy above) are acknowledged before the task is counted
+        wait_memory();
         __syncthreads();
+        const unsigned long long t_fold = wall_clock64();
         if (t == 0) {
-            unsigned *done = sa.task_done + 2 * d.sid + d.bank;
-            unsigned *total = sa.fin_total + 2 * d.sid + d.bank;
-            if (d.fin_total > 0) __hip_atomic_store(total, static_cast<unsigned>(d.fin_total), __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned v = __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-            const unsigned want = __hip_atomic_load(total, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned *done = sa.task_done + bank_ix;
+            unsigned *total = sa.fin_total + bank_ix;
+            if (d.fin_total > 0) {
+                __hip_atomic_store(total, static_cast<unsigned>(d.fin_total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                wait_memory();  // the total is in place before the count
+            }
+            const unsigned v = __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            wait_memory();  // the count has landed before the total is read
+            const unsigned want = __hip_atomic_load(total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s_fin = (want != 0u && v == want) ? 1 : 0;
-            // the ring slot is free for the host once every task of its chunk ended
-            const unsigned c = __hip_atomic_fetch_add(sa.slot_cnt + slot, 1u, __ATOMIC_ACQ_REL,
+            // the ring slot is free for the host once every task of its chunk
+            // ended (their reads of the slot are complete: the waits above)
+            const unsigned c = __hip_atomic_fetch_add(sa.slot_cnt + slot, 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT) + 1u;
-            if (c == static_cast<unsigned>(sa.tasks)) {
+            if (c == static_cast<unsigned>(d.ntasks)) {
                 __hip_atomic_store(sa.slot_cnt + slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(sa.slot_free + slot, chunk + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                wait_memory();
+                __hip_atomic_store(sa.slot_free + slot, chunk + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }
         __syncthreads();
@@ -106,27 +311,56 @@ __global__ void __launch_bounds__(kServedThreads) served_kernel(ServedArgs sa) {
             // the whole integration is in the bank: finalize it here, every
             // part in turn (read, DFT, results into the stream's pinned slot,
             // clear the bank), then report it
+            {
+                const uint32_t *src_f = reinterpret_cast<const uint32_t *>(sa.fin_args + bank_ix);
+                uint32_t *fw = reinterpret_cast<uint32_t *>(&fa);
+                for (int i = t; i < kFinWords; i += static_cast<int>(blockDim.x))
+                    fw[i] = __hip_atomic_load(src_f + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const int nwg = (d.fin.N + 63) / 64;
+            __syncthreads();
+            const int nwg = (fa.N + 63) / 64;
             for (int part = 0; part < nwg; ++part) {
-                finalize_body(d.fin, part, nwg, lds);
+                finalize_body(fa, part, nwg, lds);
                 __syncthreads();
             }
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            wait_memory();
             __syncthreads();
             if (t == 0) {
-                __hip_atomic_store(sa.task_done + 2 * d.sid + d.bank, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(sa.fin_total + 2 * d.sid + d.bank, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(sa.task_done + bank_ix, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(sa.fin_total + bank_ix, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
                 const unsigned long long k = atomicAdd(sa.done_cursor, 1ull);
                 ServedDone *r = sa.done + k % static_cast<unsigned>(sa.done_cap);
                 __hip_atomic_store(&r->sid, d.sid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 __hip_atomic_store(&r->integ, d.integ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 __hip_atomic_store(&r->seq, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                add_stat(sa, 5, 1ull);
             }
             __syncthreads();
         }
+        if (t == 0) {
+            wait_memory();
+            st_agent(sa.mail_done + me, val);  // idle again
+            const unsigned long long t_end = wall_clock64();
+            add_stat(sa, 1, 1ull);
+            add_stat(sa, 8, t_claim - t_prev);
+            add_stat(sa, 9, t_desc - t_claim);
+            add_stat(sa, 10, t_fold - t_desc);
+            add_stat(sa, 11, t_end - t_fold);
+            t_prev = t_end;
+        }
+        last = val;
     }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(kServedThreads) served_kernel(ServedArgs sa) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    if (blockIdx.x == 0)
+        schedule(sa, lds);
+    else
+        work<PREC>(sa, lds);
 }
 
 }  // namespace

@@ -46,7 +46,7 @@ struct SrvStream {
     int64_t slot_integ[kResultDepth];  // integration held by each slot (-1: none)
     bool slot_ready[kResultDepth];
     // device-resident form
-    int64_t integ_chunks = 0;        // chunks published in the current integration
+    int64_t integ_tasks = 0;         // fold tasks published in the current integration
     bool fin_inflight = false;       // an integration's last chunk is published, its completion not yet seen
 };
 
@@ -83,10 +83,16 @@ struct pcal_server_ctx {
     bool resident = false;
     hipStream_t rstream = nullptr;
     int rgrid = 0, tasks = 0, cap = 0, done_cap = 0;
+    int64_t task_bytes = 0;   // chunk bytes per fold task
+    size_t mail_bytes = 0;    // both mailbox arrays (cleared before a relaunch)
+    unsigned long long tasks_published = 0;  // fold tasks of the chunks published
+    hipStream_t sstream = nullptr;           // reads of the loop counters while the kernel runs
+    unsigned long long last_stat[kServedStats] = {};  // the loop counters at the last stop
+    bool have_stat = false;
     ServedDesc *ring = nullptr;              // coherent host memory, written by the host
     unsigned long long *slot_free = nullptr;  // coherent host memory, written by the device
     ServedDone *dn = nullptr;
-    int *ctl = nullptr;                      // [0] quit, [1] workgroups that left, [2] of them on the spin limit
+    int *ctl = nullptr;                      // [0] quit, [1] workgroups that left, [2] 1 if they left when idle
     unsigned long long *pub = nullptr;       // tasks published (coherent host memory, read by the device)
     int relaunches = 0;                      // kernels launched again after every workgroup had left
     ServedArgs args{};
@@ -114,12 +120,18 @@ bool valid_sid(const pcal_server_ctx *s, int sid) {
 
 constexpr int kRingSlots = 256;        // chunks in the work ring
 constexpr int kDoneSlots = 4096;       // completion records
-constexpr int kTasksPerChunk = 32;     // workgroups per chunk (PCAL_SERVED_TASKS)
-// Idle polls (no published task to claim) before a workgroup leaves (about
-// 4-9 s: each poll sleeps about 1 us and reads host memory), so that the
-// kernel ends even if the host never sets quit; the host launches it again
-// when work comes (keep_alive).
-constexpr unsigned long long kSpinLimit = 2000000ull;
+constexpr int kTasksPerChunk = 32;     // largest number of fold tasks per chunk (PCAL_SERVED_TASKS)
+static_assert(kRingSlots <= kServedMaxRing, "the scheduler looks ahead over the whole ring");
+// Time without work before the loop leaves (PCAL_SERVED_IDLE_MS), so that the
+// kernel ends even if the host never sets quit (the host launches it again
+// when work comes: keep_alive); a worker leaves on its own only after far
+// longer (the scheduler always tells it to leave first).
+constexpr int kIdleMs = 4000;
+constexpr double kWorkerSeconds = 60.0;
+// Bytes of a chunk per fold task of the resident loop (PCAL_SERVED_TASK_KIB):
+// a chunk gets ceil(bytes / this) tasks, at least its column tiles, at most
+// the tasks per chunk.
+constexpr int kTaskKib = 128;
 
 template <class T>
 int coherent_alloc(T **host, size_t count) {
@@ -161,15 +173,17 @@ void drain_done(pcal_server_ctx *s) {
     }
 }
 
-// Resident form: when every workgroup of the loop has left (each leaves after
-// about 4-9 s without work), launch it again; its state lives in device and
-// host memory, and no workgroup held a claim when it left, so the new launch
-// continues where the old one stopped.
+// Resident form: when every workgroup of the loop has left (they leave
+// together, about 4 s after the last work), launch it again with clear
+// mailboxes; the loop leaves only with every handed-out task ended, and the
+// next chunk to hand out is kept in device memory, so the new launch continues
+// where the old one stopped.
 int keep_alive(pcal_server_ctx *s) {
     if (__atomic_load_n(s->ctl + 1, __ATOMIC_ACQUIRE) < s->rgrid) return PCAL_OK;
     PCAL_HIP(hipStreamSynchronize(s->rstream));
     __atomic_store_n(s->ctl + 1, 0, __ATOMIC_RELAXED);
     __atomic_store_n(s->ctl + 2, 0, __ATOMIC_RELAXED);
+    launch_zero(s->args.mail_assigned, s->mail_bytes, s->rstream);
     launch_served(s->args, kernel_prec(s->prec), s->rgrid, kServedThreads, kServedLds, s->rstream);
     PCAL_HIP(hipGetLastError());
     s->relaunches += 1;
@@ -209,6 +223,15 @@ void free_resident(pcal_server_ctx *s) {
         (void)hipStreamDestroy(s->rstream);
         s->rstream = nullptr;
     }
+    if (s->sstream) {
+        (void)hipStreamDestroy(s->sstream);
+        s->sstream = nullptr;
+    }
+    if (s->dmem && s->args.stat &&
+        hipMemcpy(s->last_stat, s->args.stat, sizeof(s->last_stat), hipMemcpyDeviceToHost) == hipSuccess)
+        s->have_stat = true;
+    (void)hipGetLastError();
+    s->args.stat = nullptr;
     if (s->ring) (void)hipHostFree(s->ring);
     if (s->slot_free) (void)hipHostFree(s->slot_free);
     if (s->dn) (void)hipHostFree(s->dn);
@@ -257,7 +280,9 @@ int publish(pcal_server_ctx *s, int64_t *samples) {
             const int bank = static_cast<int>(st.integ & 1);
             const size_t NS = static_cast<size_t>(kAccSlots) * static_cast<size_t>(p.N);
             ServedDesc &d = s->ring[slot];
-            const pcal_launch_t L = plan_launch(p, reinterpret_cast<uintptr_t>(pc.ptr), h->n_total, take, s->tasks);
+            const int64_t want = (take / st.spb + s->task_bytes - 1) / s->task_bytes;
+            const int target = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, s->tasks)));
+            const pcal_launch_t L = plan_launch(p, reinterpret_cast<uintptr_t>(pc.ptr), h->n_total, take, target);
             d.fold = fold_args(h, L, pc.ptr);
             d.fold.acc = h->acc_mem + bank * NS;
             d.fold.acc_int = h->acc_int_mem + bank * NS;
@@ -279,7 +304,7 @@ int publish(pcal_server_ctx *s, int64_t *samples) {
                 f.inv_L = 1.0 / static_cast<double>(st.integ_samples);
                 f.clear = 1;
                 d.fin = f;
-                d.fin_total = s->tasks * static_cast<int>(st.integ_chunks + 1);
+                d.fin_total = static_cast<int>(st.integ_tasks + d.ntasks);
                 st.slot_integ[k] = st.integ;
                 st.slot_ready[k] = false;
                 st.fin_inflight = true;
@@ -293,11 +318,12 @@ int publish(pcal_server_ctx *s, int64_t *samples) {
             pc.n -= take;
             if (pc.n == 0) st.queue.pop_front();
             st.in_integ += take;
-            st.integ_chunks += 1;
+            st.integ_tasks += d.ntasks;
+            s->tasks_published += static_cast<unsigned long long>(d.ntasks);
             if (completes) {
                 st.integ += 1;
                 st.in_integ = 0;
-                st.integ_chunks = 0;
+                st.integ_tasks = 0;
             }
             progress = true;
         }
@@ -385,7 +411,7 @@ int pcal_server_open(pcal_server_t s, int64_t fs_hz, int64_t f_comb_hz, int64_t 
     st.in_integ = 0;
     st.device_bytes = h->device_bytes;
     st.queue.clear();
-    st.integ_chunks = 0;
+    st.integ_tasks = 0;
     st.fin_inflight = false;
     for (int i = 0; i < kResultDepth; ++i) {
         st.slot_integ[i] = -1;
@@ -576,10 +602,12 @@ int pcal_server_stats(pcal_server_t s, int64_t *queued_samples, int *inflight_fi
 }
 
 int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
-    if (!s || workgroups < 1) return PCAL_EINVAL;
+    if (!s || workgroups < 2 || workgroups > kServedMaxWorkgroups) return PCAL_EINVAL;
     if (s->resident) return PCAL_ESTATE;
     if (batch_threads(s->batch) != kServedThreads) return PCAL_ENOTSUP;
+    s->args = ServedArgs{};
     s->tasks = std::max(1, env_int("PCAL_SERVED_TASKS", kTasksPerChunk));
+    s->task_bytes = static_cast<int64_t>(std::max(1, env_int("PCAL_SERVED_TASK_KIB", kTaskKib))) << 10;
     for (int i = 0; i < s->max_streams; ++i) {
         if (!s->streams[i].open) continue;
         pcal_t h = nullptr;
@@ -598,8 +626,19 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
         free_resident(s);
         return rc;
     }
+    // Device memory of the loop: the scheduler's state, the completion cursor
+    // and the loop counters, each on a line of its own (256 B), then the
+    // per-slot and per-bank counters, the per-bank finalize arguments, the
+    // mailboxes (one 256-byte line per workgroup each way) and the device
+    // copies of the descriptors.
     const size_t nsb = 2 * static_cast<size_t>(s->max_streams);
-    const size_t dbytes = 16 + 4 * static_cast<size_t>(s->cap) + 2 * 4 * nsb;
+    const size_t cap = static_cast<size_t>(s->cap);
+    const size_t o_cnt = 3 * 256;
+    const size_t o_fin = (o_cnt + 4 * cap + 2 * 4 * nsb + 255) & ~static_cast<size_t>(255);
+    const size_t o_mail = (o_fin + sizeof(FinArgs) * nsb + 255) & ~static_cast<size_t>(255);
+    const size_t mail = 8 * kMailStride * static_cast<size_t>(workgroups);
+    const size_t o_ring = o_mail + 2 * mail;
+    const size_t dbytes = o_ring + sizeof(ServedDesc) * cap;
     {
         const hipError_t e = hipMalloc(&s->dmem, dbytes);
         if (e != hipSuccess) {
@@ -637,11 +676,18 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
     ServedArgs &a = s->args;
     a = ServedArgs{};
     unsigned char *dm = static_cast<unsigned char *>(s->dmem);
-    a.cursor = reinterpret_cast<unsigned long long *>(dm);
-    a.done_cursor = reinterpret_cast<unsigned long long *>(dm + 8);
-    a.slot_cnt = reinterpret_cast<unsigned *>(dm + 16);
+    a.sched = reinterpret_cast<unsigned long long *>(dm);
+    a.done_cursor = reinterpret_cast<unsigned long long *>(dm + 256);
+    a.stat = reinterpret_cast<unsigned long long *>(dm + 2 * 256);
+    static_assert(kServedStats * 8 <= 256, "loop counters fit their line");
+    a.slot_cnt = reinterpret_cast<unsigned *>(dm + o_cnt);
     a.task_done = a.slot_cnt + s->cap;
     a.fin_total = a.task_done + nsb;
+    a.fin_args = reinterpret_cast<FinArgs *>(dm + o_fin);
+    a.mail_assigned = reinterpret_cast<unsigned long long *>(dm + o_mail);
+    a.mail_done = reinterpret_cast<unsigned long long *>(dm + o_mail + mail);
+    a.dring = reinterpret_cast<ServedDesc *>(dm + o_ring);
+    s->mail_bytes = 2 * mail;
     if ((rc = device_address(s->ring, const_cast<ServedDesc **>(&a.ring))) ||
         (rc = device_address(s->slot_free, &a.slot_free)) || (rc = device_address(s->dn, &a.done)) ||
         (rc = device_address(s->ctl, &a.status)) ||
@@ -654,10 +700,23 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
     a.cap = s->cap;
     a.done_cap = s->done_cap;
     a.tasks = s->tasks;
-    a.spin_limit = kSpinLimit;
+    a.grid = workgroups;
+    {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+            khz = 100000;  // the documented 100 MHz
+        (void)hipGetLastError();
+        const int idle_ms = std::max(1, env_int("PCAL_SERVED_IDLE_MS", kIdleMs));
+        a.idle_ticks = static_cast<unsigned long long>(idle_ms) * static_cast<unsigned long long>(khz);
+        a.worker_ticks = static_cast<unsigned long long>(
+            std::max(kWorkerSeconds * 1e3, 4.0 * idle_ms) * static_cast<double>(khz));
+    }
     s->published = 0;
+    s->tasks_published = 0;
     s->done_next = 0;
     s->relaunches = 0;
+    s->have_stat = false;
     s->rgrid = workgroups;
     launch_served(a, kernel_prec(s->prec), workgroups, kServedThreads, kServedLds, hs);
     {
@@ -670,7 +729,7 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
         }
     }
     for (SrvStream &st : s->streams) {
-        st.integ_chunks = 0;
+        st.integ_tasks = 0;
         st.fin_inflight = false;
     }
     s->resident = true;
@@ -690,6 +749,33 @@ int pcal_server_stop(pcal_server_t s) {
         set_message("served loop: not every workgroup left at quit");
         return PCAL_EHIP;
     }
+    return PCAL_OK;
+}
+
+int pcal_server_loop_stats(pcal_server_t s, int64_t *out, int n) {
+    if (!s || !out || n < 0) return PCAL_EINVAL;
+    if (!s->have_stat && !s->resident) return PCAL_ESTATE;
+    unsigned long long dev[kServedStats] = {};
+    if (s->resident) {
+        // while the kernel runs: a copy on a non-blocking stream of our own,
+        // which does not wait for the persistent kernel's stream
+        if (!s->sstream) PCAL_HIP(hipStreamCreateWithFlags(&s->sstream, hipStreamNonBlocking));
+        PCAL_HIP(hipMemcpyAsync(dev, s->args.stat, sizeof(dev), hipMemcpyDeviceToHost, s->sstream));
+        PCAL_HIP(hipStreamSynchronize(s->sstream));
+    } else {
+        memcpy(dev, s->last_stat, sizeof(dev));
+    }
+    int khz = 0, devno = 0;
+    PCAL_HIP(hipGetDevice(&devno));
+    PCAL_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, devno));
+    const double ns_per_tick = khz > 0 ? 1e6 / khz : 10.0;
+    int64_t v[PCAL_LOOP_STATS];
+    v[0] = static_cast<int64_t>(s->published);
+    for (int k = 1; k < 8; ++k) v[k] = static_cast<int64_t>(dev[k]);
+    v[2] = static_cast<int64_t>(s->tasks_published);
+    v[6] = s->relaunches;
+    for (int k = 8; k < 12; ++k) v[k] = static_cast<int64_t>(static_cast<double>(dev[k]) * ns_per_tick);
+    for (int k = 0; k < n && k < PCAL_LOOP_STATS; ++k) out[k] = v[k];
     return PCAL_OK;
 }
 

@@ -109,6 +109,7 @@ _SIGS = {
     "pcal_server_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "pcal_server_start": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "pcal_server_stop": ([ctypes.c_void_p], ctypes.c_int),
+    "pcal_server_loop_stats": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "pcal_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "pcal_read_probe": ([ctypes.c_void_p, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -493,6 +494,16 @@ class PCalServer:
     def stop(self) -> None:
         """Leave the device-resident loop once the published work has ended (pcal_server_stop)."""
         _check(lib().pcal_server_stop(self._s), "pcal_server_stop")
+
+    LOOP_STATS = ("chunks_published", "tasks_run", "tasks_published", "descriptor_reads_from_host",
+                  "scheduler_rounds", "finalizes", "relaunches", "idle_rounds", "wait_ns", "descriptor_ns",
+                  "fold_ns", "count_finalize_ns")
+
+    def loop_stats(self) -> dict:
+        """Counters of the device-resident loop (pcal_server_loop_stats), by name."""
+        out = np.zeros(len(self.LOOP_STATS), dtype=np.int64)
+        _check(lib().pcal_server_loop_stats(self._s, out.ctypes.data, out.size), "pcal_server_loop_stats")
+        return {k: int(v) for k, v in zip(self.LOOP_STATS, out)}
 
     def stats(self) -> dict:
         q = ctypes.c_int64()

@@ -69,10 +69,12 @@ def _plain_integrations(buf, fs, fc, fo, nbits, integ, prec=0):
 ALONE_TOL = {0: F64_RTOL, 1: 1e-6, 2: 1e-5}
 
 
-@pytest.mark.parametrize("prec,resident", [(0, False), (1, False), (2, False), (0, True), (1, True)])
-def test_served_matches_plain_per_integration(prec, resident):
+@pytest.mark.parametrize("prec,resident,task_kib", [(0, False, None), (1, False, None), (2, False, None),
+                                                    (0, True, None), (1, True, None), (0, True, 8)])
+def test_served_matches_plain_per_integration(prec, resident, task_kib, monkeypatch):
     """Host-step form, and the device-resident form (one persistent kernel fed through the work
-    ring: 24 workgroups, fewer than a chunk's 32 tasks, so chunks also run one task after another)."""
+    ring: 24 workgroups, fewer than a chunk's 32 task indices, so chunks also run one task after
+    another; with 8 KiB per fold task, most tasks of a chunk read the descriptor's device copy)."""
     import time
 
     from paper_2501_05993_amd import pcal
@@ -84,6 +86,8 @@ def test_served_matches_plain_per_integration(prec, resident):
     for fs, fc, fo, nbits, integ in STREAMS:
         sids.append(srv.open(fs, fc, fo, nbits, integ))
     if resident:
+        if task_kib is not None:  # many fold tasks per chunk: most read the descriptor's device copy
+            monkeypatch.setenv("PCAL_SERVED_TASK_KIB", str(task_kib))
         srv.start(workgroups=24)
     # interleave the streams' chunks in a random order of arrival
     queue = []
@@ -129,19 +133,27 @@ def test_served_matches_plain_per_integration(prec, resident):
         srv.stop()
         for sid, integ in srv.poll():
             got[(sid, integ)] = srv.spectrum(sid, integ)
+        loop = srv.loop_stats()
+        say("loop counters: %s" % loop)
+        assert loop["tasks_run"] == loop["tasks_published"]
     torch.cuda.synchronize()
     for _ in range(100):
         for sid, integ in srv.poll():
             got[(sid, integ)] = srv.spectrum(sid, integ)
         if srv.stats()["inflight_finalizes"] == 0:
             break
+    bad = []
     for i, (fs, fc, fo, nbits, integ) in enumerate(STREAMS):
         want = _plain_integrations(bufs[i], fs, fc, fo, nbits, integ, prec)
         assert len(want) == TOTAL // integ
         for k2, w in enumerate(want):
             assert (sids[i], k2) in got, "integration %d of stream %d not reported" % (k2, i)
-            assert_spectra(got[(sids[i], k2)], w, amp_rtol=ALONE_TOL[prec], phase_atol=ALONE_TOL[prec],
-                           rel_floor=1e-6, what="stream %d integration %d" % (i, k2))
+            try:
+                assert_spectra(got[(sids[i], k2)], w, amp_rtol=ALONE_TOL[prec], phase_atol=ALONE_TOL[prec],
+                               rel_floor=1e-6, what="stream %d integration %d" % (i, k2))
+            except AssertionError as err:  # report every integration before failing
+                bad.append(str(err))
+    assert not bad, bad
     # one stream against the oracle: its second integration (global index continues)
     fs, fc, fo, nbits, integ = STREAMS[0]
     host = bufs[0].cpu().numpy()
@@ -231,4 +243,55 @@ def test_served_resident_states_and_limits():
         srv.start(workgroups=8)  # an open stream does not fit the resident form
     assert e.value.code == pcal.ENOTSUP
     srv.close_stream(a)
+    srv.close()
+
+
+def test_served_resident_relaunch_after_idle(monkeypatch):
+    """The device-resident loop leaves once idle for its limit (200 ms here) and the next step launches
+    it again where it stopped: integrations served before and after equal plain extraction, and the
+    loop counters add up (one relaunch at least, every fold task counted, one finalize per integration)."""
+    import time
+
+    from paper_2501_05993_amd import pcal
+
+    monkeypatch.setenv("PCAL_SERVED_IDLE_MS", "200")
+    bufs = _streams_on_device()
+    fs, fc, fo, nbits, integ = STREAMS[0]
+    spb = 8 // nbits
+    want = _plain_integrations(bufs[0], fs, fc, fo, nbits, integ, 0)
+    srv = pcal.PCalServer(mem_budget_bytes=1 << 30, max_streams=2, precision=0)
+    sid = srv.open(fs, fc, fo, nbits, integ)
+    srv.start(workgroups=16)
+    got = {}
+
+    def serve(k):
+        # integration k in three chunks of whole bytes, then wait (bounded) for its report
+        cuts = [k * integ, k * integ + integ // 3 // spb * spb, k * integ + 2 * integ // 3 // spb * spb,
+                (k + 1) * integ]
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            srv.submit([sid], [bufs[0].data_ptr() + a // spb], [b - a])
+        t_end = time.time() + 30.0
+        while (sid, k) not in got and time.time() < t_end:
+            srv.step()
+            for s_, k_ in srv.poll():
+                got[(s_, k_)] = srv.spectrum(s_, k_)
+        assert (sid, k) in got, "integration %d not reported" % k
+
+    say("resident loop: integration 0, 1 s idle, integration 1")
+    serve(0)
+    time.sleep(1.0)  # every workgroup leaves after 200 ms without work
+    serve(1)
+    srv.stop()
+    st = srv.loop_stats()
+    say("loop counters: %s" % st)
+    assert st["relaunches"] >= 1
+    assert st["finalizes"] == 2
+    assert st["tasks_run"] == st["tasks_published"] >= st["chunks_published"] == 6
+    assert st["descriptor_reads_from_host"] == 6  # the scheduler's copies, one per chunk
+    for k in range(2):
+        assert_spectra(got[(sid, k)], want[k], amp_rtol=F64_RTOL, phase_atol=F64_RTOL,
+                       what="integration %d around a relaunch" % k)
+    with pytest.raises(pcal.PcalError) as e:
+        srv.start(workgroups=1)  # the scheduler needs at least one worker
+    assert e.value.code == pcal.EINVAL
     srv.close()
