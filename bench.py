@@ -190,6 +190,7 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None,
     lat = []
     done_samples = 0
     served = mode in ("served", "resident")
+    queued = 0
     if served:
         srv = pcal.PCalServer(mem_budget_bytes=16 << 30, max_streams=S, precision=prec)
         ids = [srv.open(sp.fs, sp.f_comb, sp.f_offset, sp.nbits, sp.fs) for sp in specs]
@@ -246,9 +247,13 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None,
                 pos[s_] += n_
             if served:
                 srv.submit(sub_s, np.asarray(sub_p, dtype=np.uint64), sub_n)
+                queued += sum(sub_n)
             i = j
         if served:
-            srv.step()
+            # step only with work queued: a piece held back (ring full, or its stream's previous
+            # integration not yet reported) stays queued until a later step takes it
+            if queued > 0:
+                queued -= srv.step()
             for sv, k in srv.poll():
                 s_ = rev[sv]
                 lat.append(time.perf_counter() - t0 - last_arrival[(s_, k)])

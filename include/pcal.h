@@ -436,7 +436,7 @@ int pcal_server_destroy(pcal_server_t s);
  * are resident at once on the device is the useful range) on `stream`; from
  * then on pcal_server_step launches nothing: it publishes the queued pieces
  * (split at integration boundaries, every queued piece that fits, not one per
- * stream) as descriptors in a work ring of 256 chunks in pinned, coherent
+ * stream) as descriptors in a work ring of 512 chunks in pinned, coherent
  * host memory and returns.  Workgroup 0 of the kernel schedules: it reads the
  * count of published chunks, copies each new descriptor into device memory
  * and hands the chunks' fold tasks (one per 128 KiB of the chunk,
@@ -477,13 +477,13 @@ int pcal_server_stop(pcal_server_t s);
  *   kernel, [7] scheduler rounds that handed out nothing, then worker time
  *   summed over tasks, in ns: [8] waiting for the task (from the end of the
  *   previous one), [9] reading the descriptor, [10] folding, [11] counting
- *   and finalizing.
+ *   and finalizing, [12] of that, finalizing (summed over integrations).
  * The scheduler adds its counts ([3], [4], [7]) when the loop leaves; the
  * others are read while the kernel runs, each value on its own, so the set is
  * a consistent snapshot only after pcal_server_stop; it is kept until the
  * next pcal_server_start.
  * Errors: PCAL_EINVAL (null s or out, n < 0), PCAL_ESTATE (never started). */
-#define PCAL_LOOP_STATS 12
+#define PCAL_LOOP_STATS 13
 int pcal_server_loop_stats(pcal_server_t s, int64_t *out, int n);
 
 /* Streaming-read reference (not part of the extraction): reads `bytes`

@@ -259,10 +259,10 @@ struct ServedArgs {
     unsigned long long worker_ticks;  // ticks a worker waits for its scheduler before it leaves anyway
     unsigned long long *stat;    // device [kServedStats]: loop counters (pcal_server_loop_stats order from [1])
 };
-constexpr int kServedStats = 12;
+constexpr int kServedStats = 13;
 constexpr int kMailStride = 32;            // u64 words per mailbox (256 B: a line of its own)
 constexpr int kServedMaxWorkgroups = 2048;
-constexpr int kServedMaxRing = 256;        // ring slots the scheduler can look ahead over (<= its threads)
+constexpr int kServedMaxRing = 512;        // ring slots the scheduler can look ahead over (<= its threads)
 
 void launch_served(const ServedArgs &a, int prec, int grid, int threads, size_t lds, hipStream_t s);
 constexpr int kServedThreads = 512;          // the batched form's member workgroup size
@@ -270,6 +270,11 @@ constexpr size_t kServedLds = 61440;         // fold geometries up to 12800 posi
 static_assert(kServedLds >= 8 * kServedMaxWorkgroups + 4 * (2 * kServedMaxRing + 17), "scheduler state");
 static_assert(kServedMaxRing <= kServedThreads, "one scheduler thread per pending chunk");
 constexpr int kServedMaxTones = 1792;
+// The served loop's one-workgroup finalize keeps the bins, the phases and 256
+// scratch words in LDS, and the twiddles too up to this many tones.
+constexpr int kServedTwLdsTones = 1024;
+static_assert(kServedLds >= 40 * kServedTwLdsTones + 8 * 256 && kServedLds >= 24 * kServedMaxTones + 8 * 256,
+              "served finalize");
 
 // Work-lists of the batched kernels: item i owns workgroups [first[i],
 // first[i + 1]).  A list in device memory (copied there before the launch),

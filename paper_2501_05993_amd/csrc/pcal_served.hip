@@ -220,6 +220,197 @@ __device__ void schedule(const ServedArgs &sa, unsigned char *lds) {
     }
 }
 
+// The finalize of one integration in one workgroup (the served loop's worker),
+// every tone of the integration at once and the phases kept in LDS.  The
+// N-point DFT of the bins: for N a power of two, in the FP64 forms, a radix-2
+// FFT (decimation in time, bins loaded in bit-reversed order, twiddles from
+// the exact table: stage with half-length h uses tw[j N / 2h]), which needs
+// O(N log N) operations where the direct sum needs N^2 -- one workgroup's FP64
+// units take about 7 us for the direct sum at N = 512; otherwise the direct
+// sum as finalize_body computes it (four partial sums over the quarters of the
+// bins, added in quarter order), which also keeps the FP32 form's arithmetic
+// that of the other paths.  Slot sums, unwrap and least-squares delay are
+// finalize_body's.
+__device__ void finalize_wg(const FinArgs &a, unsigned char *lds) {
+    const int N = a.N, t = static_cast<int>(threadIdx.x), nt = static_cast<int>(blockDim.x);
+    const int lane = t & 63, wave = t >> 6;
+    const bool tw_lds = N <= kServedTwLdsTones;
+    double2 *P = reinterpret_cast<double2 *>(lds);
+    double2 *TW = tw_lds ? P + N : nullptr;
+    double *ph = reinterpret_cast<double *>(P + (tw_lds ? 2 * N : N));  // [N] phases
+    double *sh = ph + N;                                                // [256] scan and reduction scratch
+    const bool f32 = a.prec == 2;
+    const bool fft = !f32 && tw_lds && N >= 2 && (N & (N - 1)) == 0;
+    const int log2n = fft ? __builtin_ctz(static_cast<unsigned>(N)) : 0;
+    for (int i = t; i < N; i += nt) {
+        double re = 0.0, im = 0.0;
+        float fr = 0.f, fi = 0.f;
+#pragma unroll
+        for (int k = 0; k < kAccSlots; ++k) {
+            if (f32) {
+                fr += a.accf[k * N + i].x;
+                fi += a.accf[k * N + i].y;
+            } else {
+                re += a.acc[k * N + i].x;
+                im += a.acc[k * N + i].y;
+            }
+        }
+        const int at = fft ? static_cast<int>(__brev(static_cast<unsigned>(i)) >> (32 - log2n)) : i;
+        P[at] = f32 ? make_double2(fr, fi) : make_double2(re, im);
+        if (tw_lds) TW[i] = a.tw[i];
+    }
+    __syncthreads();
+    if (fft) {
+        for (int h = 1; h < N; h <<= 1) {
+            const int tw_step = N / (2 * h);
+            for (int q = t; q < N / 2; q += nt) {
+                const int j = q & (h - 1);
+                const int i0 = ((q - j) << 1) + j, i1 = i0 + h;
+                const double2 w = TW[j * tw_step];
+                const double2 u = P[i0], v = P[i1];
+                const double vr = v.x * w.x - v.y * w.y, vi = v.x * w.y + v.y * w.x;
+                P[i0] = make_double2(u.x + vr, u.y + vi);
+                P[i1] = make_double2(u.x - vr, u.y - vi);
+            }
+            __syncthreads();
+        }
+    }
+    const int qn = (N + 3) / 4;
+    for (int k = t; k < N; k += nt) {
+        double part_re[4], part_im[4];
+        if (fft) {  // the transform is in P: C_k = P[k] (partials unused)
+            part_re[0] = P[k].x;
+            part_im[0] = P[k].y;
+            part_re[1] = part_re[2] = part_re[3] = 0.0;
+            part_im[1] = part_im[2] = part_im[3] = 0.0;
+        } else
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int bb = w * qn;
+            const int be = (bb + qn) < N ? (bb + qn) : N;
+            double re = 0.0, im = 0.0;
+            if (bb < be) {
+                int idx = static_cast<int>((static_cast<int64_t>(k) * bb) % N);
+                if (f32) {
+                    float fr = 0.f, fi = 0.f;
+                    for (int b = bb; b < be; ++b) {
+                        const double2 p = P[b];
+                        const double2 w2 = tw_lds ? TW[idx] : a.tw[idx];
+                        const float pr = static_cast<float>(p.x), pi = static_cast<float>(p.y);
+                        const float wr = static_cast<float>(w2.x), wi = static_cast<float>(w2.y);
+                        fr += pr * wr - pi * wi;
+                        fi += pr * wi + pi * wr;
+                        idx += k;
+                        if (idx >= N) idx -= N;
+                    }
+                    re = fr;
+                    im = fi;
+                } else {
+                    for (int b = bb; b < be; ++b) {
+                        const double2 p = P[b];
+                        const double2 w2 = tw_lds ? TW[idx] : a.tw[idx];
+                        re += p.x * w2.x - p.y * w2.y;
+                        im += p.x * w2.y + p.y * w2.x;
+                        idx += k;
+                        if (idx >= N) idx -= N;
+                    }
+                }
+            }
+            part_re[w] = re;
+            part_im[w] = im;
+        }
+        double cr = 0.0, ci = 0.0;
+        float fr = 0.f, fi = 0.f;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            if (f32) {
+                fr += static_cast<float>(part_re[w]);
+                fi += static_cast<float>(part_im[w]);
+            } else {
+                cr += part_re[w];
+                ci += part_im[w];
+            }
+        }
+        if (f32) {
+            cr = fr;
+            ci = fi;
+        }
+        {  // known gain of a rounded rotator table, divided out
+            const double gr = cr * a.gain_re - ci * a.gain_im;
+            ci = cr * a.gain_im + ci * a.gain_re;
+            cr = gr;
+        }
+        if (a.sideband < 0) ci = -ci;
+        const double phase = atan2(ci, cr);
+        a.out[k] = sqrt(cr * cr + ci * ci) * a.inv_L;
+        a.out[N + k] = phase;
+        a.out[2 * N + k] = cr;
+        a.out[3 * N + k] = ci;
+        ph[k] = phase;
+    }
+    __syncthreads();
+    // delay: unwrap the in-band phases [k_lo, k_hi), fit phase = a + 2 pi t_d f
+    // (the first 256 threads, as finalize_body)
+    const bool me = t < 256;
+    const int n = a.k_hi - a.k_lo;
+    const double *php = ph + a.k_lo;
+    const int seg = (n + 255) / 256;
+    const int s0 = t * seg;
+    const int s1 = (s0 + seg) < n ? (s0 + seg) : n;
+    const double two_pi = 6.283185307179586476925286766559;
+    double dsum = 0.0;
+    for (int i = s0; me && i < s1; ++i) {
+        if (i == 0) continue;
+        const double d = php[i] - php[i - 1];
+        dsum += d - two_pi * rint(d / two_pi);
+    }
+    double incl = dsum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (me && lane == 63) sh[wave] = incl;
+    __syncthreads();
+    double before = 0.0;
+    for (int w = 0; w < wave && w < 4; ++w) before += sh[w];
+    const double excl = before + incl - dsum;
+    const double kbar = 0.5 * static_cast<double>(n - 1);
+    double unw = (n > 0 ? php[0] : 0.0) + excl;
+    double sxu = 0.0;
+    for (int i = s0; me && i < s1; ++i) {
+        if (i > 0) {
+            const double d = php[i] - php[i - 1];
+            unw += d - two_pi * rint(d / two_pi);
+        }
+        sxu += (static_cast<double>(i) - kbar) * unw;
+    }
+    __syncthreads();
+    if (me) sh[t] = sxu;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        double delay = 0.0;
+        if (n >= 2) {
+            const double dn = static_cast<double>(n);
+            const double sxx = dn * (dn * dn - 1.0) / 12.0;
+            delay = sh[0] / sxx / a.f_comb / two_pi;
+        }
+        a.out[4 * N] = delay;
+    }
+    if (a.clear) {
+        // start the next integration in this bank
+        for (int i = t; i < kAccSlots * N; i += nt) {
+            a.acc_clear[i] = make_double2(0.0, 0.0);
+            a.accf_clear[i] = make_float2(0.f, 0.f);
+            a.acc_int_clear[i] = 0;
+        }
+    }
+}
+
 // Workgroups 1 .. grid - 1: wait on the own mailbox for a task (or the word to
 // leave), fold the task into the stream's accumulator bank and count it; the
 // task whose count completes an integration finalizes it and writes its
@@ -319,11 +510,9 @@ __device__ void work(const ServedArgs &sa, unsigned char *lds) {
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __syncthreads();
-            const int nwg = (fa.N + 63) / 64;
-            for (int part = 0; part < nwg; ++part) {
-                finalize_body(fa, part, nwg, lds);
-                __syncthreads();
-            }
+            const unsigned long long t_f0 = wall_clock64();
+            finalize_wg(fa, lds);
+            __syncthreads();
             wait_memory();
             __syncthreads();
             if (t == 0) {
@@ -336,6 +525,7 @@ __device__ void work(const ServedArgs &sa, unsigned char *lds) {
                 __hip_atomic_store(&r->integ, d.integ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 __hip_atomic_store(&r->seq, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
                 add_stat(sa, 5, 1ull);
+                add_stat(sa, 12, wall_clock64() - t_f0);
             }
             __syncthreads();
         }

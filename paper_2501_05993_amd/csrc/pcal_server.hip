@@ -41,6 +41,7 @@ struct SrvStream {
     int64_t in_integ = 0;            // its samples dispatched so far
     int64_t device_bytes = 0;
     std::deque<Piece> queue;
+    int64_t queued = 0;              // samples in queue
     double *slots = nullptr;         // pinned [kResultDepth][4N + 1]
     double *slots_dev = nullptr;     // the same memory's device address (the finalize writes it)
     int64_t slot_integ[kResultDepth];  // integration held by each slot (-1: none)
@@ -118,7 +119,7 @@ bool valid_sid(const pcal_server_ctx *s, int sid) {
     return sid >= 0 && sid < static_cast<int>(s->streams.size()) && s->streams[sid].open;
 }
 
-constexpr int kRingSlots = 256;        // chunks in the work ring
+constexpr int kRingSlots = 512;        // chunks in the work ring
 constexpr int kDoneSlots = 4096;       // completion records
 constexpr int kTasksPerChunk = 32;     // largest number of fold tasks per chunk (PCAL_SERVED_TASKS)
 static_assert(kRingSlots <= kServedMaxRing, "the scheduler looks ahead over the whole ring");
@@ -316,6 +317,7 @@ int publish(pcal_server_ctx *s, int64_t *samples) {
             h->n_total += take;
             pc.ptr += take / st.spb;
             pc.n -= take;
+            st.queued -= take;
             if (pc.n == 0) st.queue.pop_front();
             st.in_integ += take;
             st.integ_tasks += d.ntasks;
@@ -411,6 +413,7 @@ int pcal_server_open(pcal_server_t s, int64_t fs_hz, int64_t f_comb_hz, int64_t 
     st.in_integ = 0;
     st.device_bytes = h->device_bytes;
     st.queue.clear();
+    st.queued = 0;
     st.integ_tasks = 0;
     st.fin_inflight = false;
     for (int i = 0; i < kResultDepth; ++i) {
@@ -437,6 +440,7 @@ int pcal_server_close(pcal_server_t s, int sid) {
     st.slots_dev = nullptr;
     st.open = false;
     st.queue.clear();
+    st.queued = 0;
     s->used -= st.device_bytes;
     return rc;
 }
@@ -450,8 +454,11 @@ int pcal_server_submit(pcal_server_t s, int count, const int *sids, const void *
         if (nsamples[i] < 0 || nsamples[i] % st.spb || (nsamples[i] > 0 && !dev_ptrs[i])) return PCAL_EINVAL;
     }
     for (int i = 0; i < count; ++i)
-        if (nsamples[i] > 0)
-            s->streams[sids[i]].queue.push_back(Piece{static_cast<const uint8_t *>(dev_ptrs[i]), nsamples[i]});
+        if (nsamples[i] > 0) {
+            SrvStream &st = s->streams[sids[i]];
+            st.queue.push_back(Piece{static_cast<const uint8_t *>(dev_ptrs[i]), nsamples[i]});
+            st.queued += nsamples[i];
+        }
     return PCAL_OK;
 }
 
@@ -485,6 +492,7 @@ int pcal_server_step(pcal_server_t s, pcal_stream_t stream, int64_t *samples_dis
         total += take;
         pc.ptr += take / st.spb;
         pc.n -= take;
+        st.queued -= take;
         if (pc.n == 0) st.queue.pop_front();
         st.in_integ += take;
         if (st.in_integ == st.integ_samples) {
@@ -588,8 +596,7 @@ int pcal_server_stats(pcal_server_t s, int64_t *queued_samples, int *inflight_fi
     if (queued_samples) {
         int64_t q = 0;
         for (const SrvStream &st : s->streams)
-            if (st.open)
-                for (const Piece &p : st.queue) q += p.n;
+            if (st.open) q += st.queued;
         *queued_samples = q;
     }
     if (inflight_finalizes) {
@@ -774,7 +781,7 @@ int pcal_server_loop_stats(pcal_server_t s, int64_t *out, int n) {
     for (int k = 1; k < 8; ++k) v[k] = static_cast<int64_t>(dev[k]);
     v[2] = static_cast<int64_t>(s->tasks_published);
     v[6] = s->relaunches;
-    for (int k = 8; k < 12; ++k) v[k] = static_cast<int64_t>(static_cast<double>(dev[k]) * ns_per_tick);
+    for (int k = 8; k < 13; ++k) v[k] = static_cast<int64_t>(static_cast<double>(dev[k]) * ns_per_tick);
     for (int k = 0; k < n && k < PCAL_LOOP_STATS; ++k) out[k] = v[k];
     return PCAL_OK;
 }

@@ -497,7 +497,7 @@ class PCalServer:
 
     LOOP_STATS = ("chunks_published", "tasks_run", "tasks_published", "descriptor_reads_from_host",
                   "scheduler_rounds", "finalizes", "relaunches", "idle_rounds", "wait_ns", "descriptor_ns",
-                  "fold_ns", "count_finalize_ns")
+                  "fold_ns", "count_finalize_ns", "finalize_ns")
 
     def loop_stats(self) -> dict:
         """Counters of the device-resident loop (pcal_server_loop_stats), by name."""

@@ -295,3 +295,46 @@ def test_served_resident_relaunch_after_idle(monkeypatch):
         srv.start(workgroups=1)  # the scheduler needs at least one worker
     assert e.value.code == pcal.EINVAL
     srv.close()
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_served_resident_wide_stream(prec):
+    """A stream of 1536 tones (twiddles beyond the served finalize's LDS share) through the device-
+    resident loop, FP64 and FP32 forms: each integration equals plain extraction.  In the FP32 form the
+    two differ by the order of their FP32 sums, an error of about FP32 rounding times the strongest
+    tone: tones more than 40 dB below it are compared by their absolute error against it."""
+    import time
+
+    import torch
+
+    from paper_2501_05993_amd import pcal
+
+    fs, fc, fo, nbits = 1_536_000_000, 1_000_000, 10_000, 2
+    integ, n_integ, spb = 1_536_000, 2, 4
+    spec = synth.CombSpec(fs, fc, fo, nbits, amp=0.3, t_d=5e-9, sigma=1.0, seed=(67, prec))
+    buf = synth.make_stream_device(spec, integ * n_integ)
+    torch.cuda.synchronize()
+    want = []
+    with pcal.PCal(fs, fc, fo, nbits, method=pcal.METHOD_PERIOD_FOLD, precision=prec) as h:
+        for k in range(n_integ):
+            h.extract(buf, integ, byte_offset=k * integ // spb)
+            want.append(h.spectrum())
+            h.reset()
+    srv = pcal.PCalServer(mem_budget_bytes=1 << 30, max_streams=1, precision=prec)
+    sid = srv.open(fs, fc, fo, nbits, integ)
+    srv.start(workgroups=32)
+    cuts = [0, 400_000, 1_536_000, 2_000_000, integ * n_integ]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        srv.submit([sid], [buf.data_ptr() + a // spb], [b - a])
+    got = {}
+    t_end = time.time() + 30.0
+    while len(got) < n_integ and time.time() < t_end:
+        srv.step()
+        for s_, k_ in srv.poll():
+            got[k_] = srv.spectrum(s_, k_)
+    srv.stop()
+    for k in range(n_integ):
+        assert k in got, "integration %d not reported" % k
+        assert_spectra(got[k], want[k], amp_rtol=ALONE_TOL[prec], phase_atol=ALONE_TOL[prec],
+                       rel_floor=1e-6 if prec == 0 else 1e-2, what="1536 tones, form %d, integration %d" % (prec, k))
+    srv.close()
