@@ -497,10 +497,9 @@ def precision_single(pcal, torch, synth):
 
 def per_sample_2bit_study(pcal, torch, synth, oracle=None):
     """2-bit stream with a long rotator period (fs = 64 MHz, f_offset = 10008 Hz: the rotator repeats only
-    after 8e6 samples, beyond the 2^22-sample fold periods AUTO folds, so AUTO takes the per-sample
-    recurrence): one 2^30-sample
-    integration through the per-sample forms, timed with events, HBM roofline at 0.25 B per sample, and
-    each form's spectrum against the oracle on two tones."""
+    after 8e6 samples, near the longest fold period AUTO folds): one 2^30-sample integration through AUTO's
+    choice (the period fold) and the per-sample forms, timed with events, HBM roofline at 0.25 B per
+    sample, and each form's spectrum against the oracle on two tones."""
     w = synth.WORKLOADS["osc2_64M_10008"]
     spec, L = w["spec"], w["nsamples"]
     print("[bench] per-sample 2-bit study (f_offset 10008 Hz)", file=sys.stderr, flush=True)
@@ -511,7 +510,8 @@ def per_sample_2bit_study(pcal, torch, synth, oracle=None):
     if oracle is not None:
         Co = oracle.correlate(buf.cpu().numpy(), 2, L, spec.fs, spec.f_comb, spec.f_offset, tones=tones)
     stream = torch.cuda.current_stream()
-    forms = (("auto_f64", pcal.METHOD_AUTO, pcal.PREC_F64), ("recurrence_mixed", pcal.METHOD_OSC, pcal.PREC_MIXED),
+    forms = (("auto_f64", pcal.METHOD_AUTO, pcal.PREC_F64), ("recurrence_f64", pcal.METHOD_OSC, pcal.PREC_F64),
+             ("recurrence_mixed", pcal.METHOD_OSC, pcal.PREC_MIXED),
              ("coupled_form_mixed", pcal.METHOD_CFO, pcal.PREC_MIXED), ("recurrence_f32", pcal.METHOD_OSC,
                                                                          pcal.PREC_F32))
     out = {}
@@ -531,7 +531,8 @@ def per_sample_2bit_study(pcal, torch, synth, oracle=None):
         us = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e3
         h.close()
         gbs = L / 4 / (us * 1e-6) / 1e9
-        entry = {"method": {1: "period_fold", 2: "table", 3: "recurrence", 4: "coupled_form"}[chosen],
+        entry = {"method": {1: "period_fold", 2: "table", 3: "recurrence", 4: "coupled_form", 5: "magic_circle",
+                            6: "error_feedback_dfr"}[chosen],
                  "kernel_us": round(us, 1), "gsamples_per_s": round(L / (us * 1e-6) / 1e9, 1),
                  "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(gbs / HBM_PEAK_GBS, 4)}}
@@ -543,8 +544,9 @@ def per_sample_2bit_study(pcal, torch, synth, oracle=None):
         out[name] = entry
     del buf
     torch.cuda.empty_cache()
-    return {"workload": "2-bit, fs 64 MHz, f_comb 1 MHz (N = 64), f_offset 10008 Hz (rotator period 8e6), "
-                        "2^30 samples, one launch per form (kernel-stamped)", **out}
+    return {"workload": "2-bit, fs 64 MHz, f_comb 1 MHz (N = 64), f_offset 10008 Hz (rotator period 8e6 = the "
+                        "fold period), 2^30 samples, one launch per form (kernel-stamped); AUTO folds",
+            **out}
 
 
 def rotator_study(pcal, torch, synth):
@@ -612,7 +614,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 64-stream per-stream precision report of the precision forms")
     ap.add_argument("--no-per-sample-study", action="store_true",
-                    help="skip the 2-bit long-period (f_offset 10008 Hz) per-sample forms")
+                    help="skip the 2-bit long-period (f_offset 10008 Hz) study of AUTO and the per-sample forms")
     ap.add_argument("--no-batched-study", action="store_true",
                     help="skip the 64-stream batched-form measurement")
     ap.add_argument("--no-rotator-study", action="store_true",

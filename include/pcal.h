@@ -74,7 +74,7 @@ enum pcal_status {
  *  DFR_EF: the direct-form resonator with truncation-error feedback (a remedy
  *      Section 2.2 names): state and coefficient in two terms each, every
  *      step's rounding error carried into the next.
- *  AUTO: PERIOD_FOLD when the joint period fits (at most 2^22 samples), else
+ *  AUTO: PERIOD_FOLD when the joint period fits (at most 2^23 samples), else
  *      OSC; CFO instead of OSC in the FP32-state forms (MIXED, F32) when no
  *      row length keeps |sin d| >= 0.1.
  * The recurrence forms (OSC, CFO, MCO, DFR_EF) share one row choice. */
@@ -525,7 +525,7 @@ int pcal_read_probe(const void *dev_ptr, int64_t bytes, int blocks, int threads,
  * Errors: PCAL_EINVAL (parameters as pcal_create; null dev_out; nsamples
  * negative or not a multiple of the samples per byte; tables and
  * accumulators larger than the array, with the sizes in pcal_last_error()),
- * PCAL_ENOTSUP (the stream needs a per-sample form: fold period over 2^22
+ * PCAL_ENOTSUP (the stream needs a per-sample form: fold period over 2^23
  * samples, or fs >= 2^32 Hz), PCAL_EHIP. */
 #define PCAL_NOALLOC_SCRATCH_BYTES (4 << 20)
 int pcal_extract_noalloc(int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband,

@@ -74,7 +74,14 @@ constexpr int kRotLanes = 16;                          // samples per thread-row
 constexpr int kTargetBlocks = 1024;
 constexpr int kRotTargetBlocks8 = 512;
 constexpr int kLutTargetBlocks8 = 768;
-constexpr int64_t kAutoFoldPeriod = int64_t(1) << 22;  // longest fold period AUTO folds
+// Longest fold period AUTO folds.  The fold's cost is the walk (HBM-bound)
+// plus an epilogue per period position; a per-sample recurrence costs VALU per
+// sample.  Measured on 2-bit fs = 64 MHz streams (one MI355X): an 8e6-sample
+// fold period folds 2^30 samples in 62 us (54 % of the HBM peak) against
+// 201 us for the FP64 recurrence, and wins at every launch length down to one
+// period (20 us against 33 us at 2^23 samples); a 64e6-sample period wins only
+// from about 2^29 samples per launch, so longer periods keep the recurrence.
+constexpr int64_t kAutoFoldPeriod = int64_t(1) << 23;
 
 int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int method, int prec, Plan *p,
               int force_threads = 0);

@@ -217,8 +217,8 @@ WORKLOADS = {
     "wide8_1024M_510k": dict(spec=CombSpec(1_024_000_000, 1_000_000, 510_000, 8, amp=1.0, t_d=125e-9,
                                            sigma=20.0, seed=(3, 0, 0)),
                              nsamples=1 << 33, chunk=1 << 28),
-    # fs=64 MHz, N=64, f_offset=10008 Hz (rotator period 8e6 samples: no fold period within 2^22 samples,
-    # so the per-sample forms run), 2-bit, 2^30 samples
+    # fs=64 MHz, N=64, f_offset=10008 Hz (rotator period 8e6 samples: the longest fold periods AUTO still
+    # folds; the per-sample forms run on it too), 2-bit, 2^30 samples
     "osc2_64M_10008": dict(spec=CombSpec(64_000_000, 1_000_000, 10_008, 2, amp=0.02, t_d=3.7e-9,
                                          jitter=0.1, seed=(6, 0, 0)),
                            nsamples=1 << 30),

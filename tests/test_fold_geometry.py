@@ -241,7 +241,12 @@ def test_per_sample_walk(method, fs, fc, fo, nbits, ns, addr, before):
 
 
 def test_auto_prefers_recurrence_for_long_periods():
+    """AUTO folds up to a 2^23-sample fold period and takes the recurrence beyond."""
     assert pcal.plan(64_000_000, 1_000_000, 10_000, 2)["method"] == pcal.METHOD_PERIOD_FOLD
+    p = pcal.plan(64_000_000, 1_000_000, 10_008, 2)  # R = 8e6 <= 2^23
+    assert p["fold_period"] == 8_000_000 and p["method"] == pcal.METHOD_PERIOD_FOLD
+    p = pcal.plan(64_000_000, 1_000_000, 10_004, 2)  # R = 16e6 > 2^23
+    assert p["fold_period"] == 16_000_000 and p["method"] == pcal.METHOD_OSC
     assert pcal.plan(64_000_000, 2_000_000, 10_007, 8)["method"] == pcal.METHOD_OSC
 
 

@@ -76,6 +76,25 @@ def test_fold2_per_sample_chunks(pc, method):
     assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="fold2 method %d" % method)
 
 
+def test_long_fold_period_auto(pc):
+    """f_offset = 10008 Hz at 64 MHz: an 8e6-sample fold period, the longest class AUTO still folds.
+    625 column tiles and 125000 rotator rows (read from global memory in the epilogue, beyond LDS), two
+    launches (the second starting mid-period, on a ragged byte count); FP64 against the oracle."""
+    spec = synth.CombSpec(64_000_000, 1_000_000, 10_008, 2, amp=0.05, t_d=3.7e-9, seed=(43,))
+    L = (1 << 25) + 4 * 333
+    packed = synth.make_stream(spec, L)
+    dev = torch.from_numpy(packed).cuda()
+    cut = 4 * 3_000_001
+    with pc.PCal(spec.fs, spec.f_comb, spec.f_offset, 2) as h:
+        info = h.info()
+        assert info["method"] == pc.METHOD_PERIOD_FOLD and info["fold_period"] == 8_000_000
+        h.extract(dev[: cut // 4], cut)
+        h.extract(dev[cut // 4:], L - cut)
+        C = h.spectrum()
+    Co = oracle.correlate(packed, 2, L, spec.fs, spec.f_comb, spec.f_offset)
+    assert_spectra(C, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, what="8e6-sample fold period")
+
+
 def test_prime_offset_recurrence(pc):
     """f_offset = 10007 Hz: rotator period = fs, no fold period or table; AUTO takes the recurrence."""
     spec = synth.CombSpec(64_000_000, 2_000_000, 10_007, 8, amp=2.0, t_d=4e-9, sigma=20.0, seed=(41,))
