@@ -94,9 +94,10 @@ def cpu_baseline(host_bytes, spec, target_s=12.0):
 
 
 def cpu_baseline_configs(torch, synth, target_s=4.0):
-    """The oracle on the host cores on the other single-stream and batched workloads, each on a bounded
-    sample sized for about target_s of work: the small 2-bit f_offset = 0 stream in full, a prefix of the
-    8-bit wide stream, and a prefix of every stream of the 64-stream batch."""
+    """The oracle on the host cores on the other single-stream, batched and served workloads, each on a
+    bounded sample sized for about target_s of work: the small 2-bit f_offset = 0 stream in full, a prefix
+    of the 8-bit wide stream, a prefix of every stream of the 64-stream batch and of 32 integrations of
+    the serving mix."""
     import oracle
 
     threads = oracle.max_threads()
@@ -134,6 +135,28 @@ def cpu_baseline_configs(torch, synth, target_s=4.0):
     dt = time.perf_counter() - t0
     out["batch64"] = {"value": round(len(specs) * per / dt / 1e9, 6), "unit": "Gsamples/s",
                       "sample": "first 2^18 samples of each of the 64 streams (N = 16-512 tones), %.1f s" % dt}
+    # the serving mix: 32 of its streams, stratified over (fs, sample width), one integration's first
+    # 2^19 samples each
+    served = synth.served_specs(256)
+    classes = {}
+    for s_ in served:
+        classes.setdefault((s_.fs, s_.nbits), []).append(s_)
+    keys = sorted(classes)
+    pick = []
+    while len(pick) < 32:
+        for k in keys:
+            if classes[k] and len(pick) < 32:
+                pick.append(classes[k].pop(0))
+    per = 1 << 19
+    packs = [synth.make_stream(s_, per) for s_ in pick]
+    t0 = time.perf_counter()
+    for s_, pk in zip(pick, packs):
+        oracle.correlate(pk, s_.nbits, per, s_.fs, s_.f_comb, s_.f_offset, nthreads=threads)
+    dt = time.perf_counter() - t0
+    out["served32"] = {"value": round(len(pick) * per / dt / 1e9, 6), "unit": "Gsamples/s",
+                       "sample": "first 2^19 samples of one integration of 32 streams of the serving mix, "
+                                 "stratified over (fs, sample width) (N = 32-512 tones), %.1f s; prefixes, not "
+                                 "whole 1 s integrations" % dt}
     out["cores"] = threads
     return out
 
