@@ -19,7 +19,8 @@ namespace {
 // descriptors are written and read with agent-scope atomics.  The one acquire
 // (before a finalize reads the bank that other workgroups' atomics filled)
 // and the one release (after it clears that bank with plain stores) come once
-// per integration.
+// per integration: without them the finalized spectra moved by 1e-7 from the
+// one-stream extraction's.
 
 __device__ __forceinline__ unsigned long long ld_agent(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -402,11 +403,12 @@ __device__ void finalize_wg(const FinArgs &a, unsigned char *lds) {
         a.out[4 * N] = delay;
     }
     if (a.clear) {
-        // start the next integration in this bank
+        // start the next integration in this bank: the accumulators the form
+        // adds into (null: not used, still zero)
         for (int i = t; i < kAccSlots * N; i += nt) {
-            a.acc_clear[i] = make_double2(0.0, 0.0);
-            a.accf_clear[i] = make_float2(0.f, 0.f);
-            a.acc_int_clear[i] = 0;
+            if (a.acc_clear) a.acc_clear[i] = make_double2(0.0, 0.0);
+            if (a.accf_clear) a.accf_clear[i] = make_float2(0.f, 0.f);
+            if (a.acc_int_clear) a.acc_int_clear[i] = 0;
         }
     }
 }

@@ -298,9 +298,11 @@ int publish(pcal_server_ctx *s, int64_t *samples) {
                 FinArgs f = fin_args(h, st.slots_dev + static_cast<size_t>(k) * (4 * st.N + 1));
                 f.acc = d.fold.acc;
                 f.accf = d.fold.accf;
-                f.acc_clear = d.fold.acc;
-                f.accf_clear = d.fold.accf;
-                f.acc_int_clear = d.fold.acc_int;
+                // clear only the accumulators the form adds into (the others stay zero)
+                const bool f32 = p.prec == PCAL_PREC_F32;
+                f.acc_clear = f32 ? nullptr : d.fold.acc;
+                f.accf_clear = f32 ? d.fold.accf : nullptr;
+                f.acc_int_clear = d.fold.int_bins ? d.fold.acc_int : nullptr;
                 f.counter = h->counters + bank;
                 f.inv_L = 1.0 / static_cast<double>(st.integ_samples);
                 f.clear = 1;
