@@ -450,7 +450,9 @@ int pcal_server_destroy(pcal_server_t s);
  * completes an integration is published only after the stream's previous
  * integration has been reported.  The loop leaves when pcal_server_stop sets
  * the quit flag, or about 4 s after its last work (PCAL_SERVED_IDLE_MS),
- * each time only with every published task ended, so the kernel always ends;
+ * each time with every published task ended (on quit, at most 1 s later
+ * even if not: pcal_server_stop sets quit only after the published work
+ * ended or its wait ran out, which it reports), so the kernel always ends;
  * pcal_server_step launches it again when every workgroup has left and work
  * comes.  The kernel runs on a non-blocking stream of the server's own (after
  * the work already enqueued on `stream`): a device-wide synchronisation

@@ -245,6 +245,7 @@ struct ServedArgs {
     const int *quit;             // host memory: nonzero asks the loop to leave once every published task ended
     int *status;                 // host memory: [0] workgroups that left, [1] of them after the idle limit
     unsigned long long *sched;   // device: [0] next chunk to hand out (kept across launches)
+    unsigned long long *heartbeat;  // device: the scheduler's round count, rewritten every round
     unsigned long long *done_cursor;  // device: next completion record
     unsigned *slot_cnt;          // device [cap]: tasks of the chunk in the slot that ended
     unsigned *task_done;         // device [streams][2]: tasks of the integration in the bank that ended
@@ -256,7 +257,9 @@ struct ServedArgs {
     int cap, done_cap, tasks;    // ring slots, completion records, task indices per chunk
     int grid;                    // workgroups of the launch (the scheduler and grid - 1 workers)
     unsigned long long idle_ticks;    // wall-clock ticks without work before the loop leaves
-    unsigned long long worker_ticks;  // ticks a worker waits for its scheduler before it leaves anyway
+    unsigned long long worker_ticks;  // ticks of a frozen heartbeat after which a waiting worker leaves
+    unsigned long long check_ticks;   // ticks between a waiting worker's looks at the heartbeat
+    unsigned long long quit_ticks;    // ticks after quit the scheduler still waits for pending work
     unsigned long long *stat;    // device [kServedStats]: loop counters (pcal_server_loop_stats order from [1])
 };
 constexpr int kServedStats = 13;

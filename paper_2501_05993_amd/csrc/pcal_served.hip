@@ -44,9 +44,12 @@ constexpr unsigned long long kLeave = 1ull;  // mailbox value: leave the loop (t
 // round: read the host's count of published tasks and its quit flag; copy the
 // descriptors of newly published chunks into device memory (complete before
 // any of their tasks is handed out); read every worker's mailbox; give the
-// k-th idle worker (in worker order) the k-th pending task.  It leaves, and
-// tells every worker to leave, when quit is set or idle_ticks pass without
-// work, in both cases only with no task pending and no worker busy.
+// k-th idle worker (in worker order) the k-th pending task; and rewrite its
+// heartbeat.  It leaves, and tells every worker to leave, after idle_ticks
+// without work, or on quit, in both cases with no task pending and no worker
+// busy -- or, on quit, once quit_ticks have passed (the host sets quit only
+// after the published work ended: a pending task then is a fault, and the
+// kernel still ends; busy workers finish their task first).
 //
 // The host publishes chunk c only after chunk c - cap has ended, so at most
 // cap chunks are pending and a slot's descriptor is replaced only after every
@@ -70,7 +73,7 @@ __device__ void schedule(const ServedArgs &sa, unsigned char *lds) {
     }
     __syncthreads();
     unsigned long long polls = 0, rounds_idle = 0, copies = 0;
-    unsigned long long t_work = wall_clock64();
+    unsigned long long t_work = wall_clock64(), t_quit = 0;
     for (;;) {
         if (t == 0) {
             const unsigned long long pub =
@@ -78,6 +81,7 @@ __device__ void schedule(const ServedArgs &sa, unsigned char *lds) {
             s_quit = __hip_atomic_load(sa.quit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             s_chunks = pub / static_cast<unsigned>(sa.tasks);
             ++polls;
+            st_agent(sa.heartbeat, polls);
         }
         __syncthreads();
         const unsigned long long chunks = s_chunks, copied = s_copied, next = s_next;
@@ -200,7 +204,8 @@ __device__ void schedule(const ServedArgs &sa, unsigned char *lds) {
         const bool quiet = s_pending == 0 && s_busy == 0 && nh == 0;
         const unsigned long long now = wall_clock64();
         if (!quiet) t_work = now;
-        if (quiet && (s_quit || now - t_work > sa.idle_ticks)) {
+        if (s_quit && t_quit == 0) t_quit = now;
+        if ((quiet && (s_quit || now - t_work > sa.idle_ticks)) || (s_quit && now - t_quit > sa.quit_ticks)) {
             for (int w = 1 + t; w < G; w += nt)
                 st_agent(sa.mail_assigned + static_cast<size_t>(w) * kMailStride, kLeave);
             if (t == 0) {
@@ -418,9 +423,12 @@ __device__ void finalize_wg(const FinArgs &a, unsigned char *lds) {
 // task whose count completes an integration finalizes it and writes its
 // completion record.  That task may belong to any chunk of the integration,
 // and only the last chunk's descriptor carries the finalize: its tasks leave
-// a copy per stream and bank in device memory before they count.  The wait is
-// bounded: worker_ticks is far beyond the scheduler's own idle limit, after
-// which the scheduler always sends the word to leave.
+// a copy per stream and bank in device memory before they count.  A worker
+// may wait for a task as long as the scheduler lives (a worker of high index
+// can stay idle long under partial load, and must still be there when handed
+// a task); the scheduler always sends the word to leave before it ends, and a
+// worker leaves on its own only once the scheduler's heartbeat has not moved
+// for worker_ticks, so every wait is bounded.
 template <int PREC>
 __device__ void work(const ServedArgs &sa, unsigned char *lds) {
     __shared__ __align__(16) ServedDesc d;
@@ -434,11 +442,19 @@ __device__ void work(const ServedArgs &sa, unsigned char *lds) {
     for (;;) {
         if (t == 0) {
             unsigned long long v = ld_agent(sa.mail_assigned + me);
-            const unsigned long long t0 = wall_clock64();
+            unsigned long long t_beat = wall_clock64(), t_look = t_beat, beat = ld_agent(sa.heartbeat);
             while (v == last || v == 0ull) {
-                if (wall_clock64() - t0 > sa.worker_ticks) {
-                    v = kLeave;
-                    break;
+                const unsigned long long now = wall_clock64();
+                if (now - t_look > sa.check_ticks) {
+                    t_look = now;
+                    const unsigned long long b = ld_agent(sa.heartbeat);
+                    if (b != beat) {
+                        beat = b;
+                        t_beat = now;
+                    } else if (now - t_beat > sa.worker_ticks) {
+                        v = kLeave;  // no scheduler round for worker_ticks
+                        break;
+                    }
                 }
                 __builtin_amdgcn_s_sleep(8);
                 v = ld_agent(sa.mail_assigned + me);

@@ -125,10 +125,12 @@ constexpr int kTasksPerChunk = 32;     // largest number of fold tasks per chunk
 static_assert(kRingSlots <= kServedMaxRing, "the scheduler looks ahead over the whole ring");
 // Time without work before the loop leaves (PCAL_SERVED_IDLE_MS), so that the
 // kernel ends even if the host never sets quit (the host launches it again
-// when work comes: keep_alive); a worker leaves on its own only after far
-// longer (the scheduler always tells it to leave first).
+// when work comes: keep_alive); a waiting worker leaves on its own only once
+// the scheduler's heartbeat has stood still for kWorkerSeconds
+// (PCAL_SERVED_WORKER_MS): the scheduler always tells it to leave first.
 constexpr int kIdleMs = 4000;
-constexpr double kWorkerSeconds = 60.0;
+constexpr double kWorkerSeconds = 60.0;  // a frozen scheduler heartbeat for this long: a waiting worker leaves
+constexpr double kQuitSeconds = 1.0;     // after quit, the scheduler waits this long for pending work
 // Bytes of a chunk per fold task of the resident loop (PCAL_SERVED_TASK_KIB):
 // a chunk gets ceil(bytes / this) tasks, at least its column tiles, at most
 // the tasks per chunk.
@@ -635,14 +637,14 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
         free_resident(s);
         return rc;
     }
-    // Device memory of the loop: the scheduler's state, the completion cursor
-    // and the loop counters, each on a line of its own (256 B), then the
+    // Device memory of the loop: the scheduler's state, the completion cursor,
+    // the loop counters and the heartbeat, each on a line of its own (256 B), then the
     // per-slot and per-bank counters, the per-bank finalize arguments, the
     // mailboxes (one 256-byte line per workgroup each way) and the device
     // copies of the descriptors.
     const size_t nsb = 2 * static_cast<size_t>(s->max_streams);
     const size_t cap = static_cast<size_t>(s->cap);
-    const size_t o_cnt = 3 * 256;
+    const size_t o_cnt = 4 * 256;
     const size_t o_fin = (o_cnt + 4 * cap + 2 * 4 * nsb + 255) & ~static_cast<size_t>(255);
     const size_t o_mail = (o_fin + sizeof(FinArgs) * nsb + 255) & ~static_cast<size_t>(255);
     const size_t mail = 8 * kMailStride * static_cast<size_t>(workgroups);
@@ -688,6 +690,7 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
     a.sched = reinterpret_cast<unsigned long long *>(dm);
     a.done_cursor = reinterpret_cast<unsigned long long *>(dm + 256);
     a.stat = reinterpret_cast<unsigned long long *>(dm + 2 * 256);
+    a.heartbeat = reinterpret_cast<unsigned long long *>(dm + 3 * 256);
     static_assert(kServedStats * 8 <= 256, "loop counters fit their line");
     a.slot_cnt = reinterpret_cast<unsigned *>(dm + o_cnt);
     a.task_done = a.slot_cnt + s->cap;
@@ -718,8 +721,10 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
         (void)hipGetLastError();
         const int idle_ms = std::max(1, env_int("PCAL_SERVED_IDLE_MS", kIdleMs));
         a.idle_ticks = static_cast<unsigned long long>(idle_ms) * static_cast<unsigned long long>(khz);
-        a.worker_ticks = static_cast<unsigned long long>(
-            std::max(kWorkerSeconds * 1e3, 4.0 * idle_ms) * static_cast<double>(khz));
+        const int worker_ms = std::max(1, env_int("PCAL_SERVED_WORKER_MS", static_cast<int>(kWorkerSeconds * 1e3)));
+        a.worker_ticks = static_cast<unsigned long long>(worker_ms) * static_cast<unsigned long long>(khz);
+        a.check_ticks = static_cast<unsigned long long>(khz);  // 1 ms
+        a.quit_ticks = static_cast<unsigned long long>(kQuitSeconds * 1e3 * static_cast<double>(khz));
     }
     s->published = 0;
     s->tasks_published = 0;

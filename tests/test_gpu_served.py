@@ -338,3 +338,41 @@ def test_served_resident_wide_stream(prec):
         assert_spectra(got[k], want[k], amp_rtol=ALONE_TOL[prec], phase_atol=ALONE_TOL[prec],
                        rel_floor=1e-6 if prec == 0 else 1e-2, what="1536 tones, form %d, integration %d" % (prec, k))
     srv.close()
+
+
+def test_served_resident_idle_workers_stay(monkeypatch):
+    """Workers that wait longer than their own time limit (150 ms here) stay while the scheduler's
+    heartbeat moves: after 1 s of idling (the loop itself stays, its idle limit being 4 s), a burst of
+    small chunks spread over many workers is served completely and equals plain extraction; no relaunch."""
+    import time
+
+    from paper_2501_05993_amd import pcal
+
+    monkeypatch.setenv("PCAL_SERVED_WORKER_MS", "150")
+    monkeypatch.setenv("PCAL_SERVED_TASK_KIB", "4")
+    bufs = _streams_on_device()
+    fs, fc, fo, nbits, integ = STREAMS[0]
+    spb = 8 // nbits
+    want = _plain_integrations(bufs[0], fs, fc, fo, nbits, integ, 0)
+    srv = pcal.PCalServer(mem_budget_bytes=1 << 30, max_streams=2, precision=0)
+    sid = srv.open(fs, fc, fo, nbits, integ)
+    srv.start(workgroups=64)
+    got = {}
+    for k in range(2):
+        if k:
+            time.sleep(1.0)  # every worker waits far past 150 ms; the heartbeat keeps them
+        srv.submit([sid], [bufs[0].data_ptr() + k * integ // spb], [integ])
+        t_end = time.time() + 30.0
+        while (sid, k) not in got and time.time() < t_end:
+            srv.step()
+            for s_, k_ in srv.poll():
+                got[(s_, k_)] = srv.spectrum(s_, k_)
+        assert (sid, k) in got, "integration %d not reported" % k
+    srv.stop()
+    st = srv.loop_stats()
+    say("loop counters: %s" % st)
+    assert st["relaunches"] == 0 and st["tasks_run"] == st["tasks_published"] and st["finalizes"] == 2
+    for k in range(2):
+        assert_spectra(got[(sid, k)], want[k], amp_rtol=F64_RTOL, phase_atol=F64_RTOL,
+                       what="integration %d after idle workers" % k)
+    srv.close()
