@@ -348,17 +348,21 @@ typedef struct pcal_batch_ctx *pcal_batch_t;
  * enum pcal_precision every member uses. */
 int pcal_batch_create(int max_streams, int precision, pcal_batch_t *out);
 
-/* Add a member stream (parameters as pcal_create; period-fold form).  *id is
- * its index.  PCAL_EAGAIN when the batch is full, PCAL_ENOTSUP when the
- * parameters need a per-sample form. */
+/* Add a member stream (parameters as pcal_create).  *id is its index.  The
+ * member takes the period fold, planned for the batch's workgroup size and
+ * folded in the batch's launches, whenever a fold period fits (at most 2^26
+ * samples and 2^20 rotator rows); else AUTO's per-sample form, which
+ * pcal_batch_extract runs in a launch of its own after the fold launches.
+ * PCAL_EAGAIN when the batch is full. */
 int pcal_batch_add(pcal_batch_t b, int64_t fs_hz, int64_t f_comb_hz, int64_t f_offset_hz, int nbits, int sideband,
                    int *id);
 
 /* The member handle with index id (owned by the batch). */
 int pcal_batch_handle(pcal_batch_t b, int id, pcal_t *h);
 
-/* One launch: for i < count, nsamples[i] samples of member ids[i] at
- * device address dev_ptrs[i] (each id at most once).  Asynchronous on
+/* One launch per sample width for the fold members: for i < count,
+ * nsamples[i] samples of member ids[i] at device address dev_ptrs[i] (each
+ * id at most once); then one launch per per-sample member.  Asynchronous on
  * stream, ordered after each member's previous work. */
 int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *const *dev_ptrs,
                        const int64_t *nsamples, pcal_stream_t stream);
@@ -399,9 +403,11 @@ int pcal_batch_destroy(pcal_batch_t b);
  * memory the caller keeps valid until a pcal_server_step that dispatched the
  * chunk's last samples has completed on its stream).  It never blocks.
  *
- * pcal_server_step dispatches, with one launch of the batched fused kernel,
- * the oldest queued piece of every stream that has one (a chunk crossing an
- * integration boundary is split there), then one batched finalize for the
+ * pcal_server_step dispatches, with one launch of the batched fused kernel
+ * per sample width, the oldest queued piece of every stream that has one (a
+ * chunk crossing an integration boundary is split there; a stream no fold
+ * period fits runs its piece in a per-sample launch of its own, see
+ * pcal_batch_add), then one batched finalize for the
  * streams whose integration it completed: it reads and clears their bins and
  * copies their results (amplitude, phase, C_k, delay) to pinned host memory.
  * All of it is asynchronous on `stream`; *samples_dispatched (may be NULL)
@@ -460,8 +466,9 @@ int pcal_server_destroy(pcal_server_t s);
  * pcal_server_stop waits (up to 30 s) for the published work, sets the quit
  * flag and waits for the kernel; the server continues in the host-step form.
  * pcal_server_close and pcal_server_destroy wait for published work first.
- * Streams need at most 1792 tones and a fold period of at most 32 column
- * tiles in this form (PCAL_ENOTSUP otherwise, at start or open), and the
+ * Streams need the period fold, at most 1792 tones and a fold period of at
+ * most 32 column tiles in this form (PCAL_ENOTSUP otherwise, at start or
+ * open), and the
  * batch workgroup size of 512 threads (PCAL_BATCH_THREADS unset).
  * Errors: PCAL_EINVAL (workgroups outside 2..2048), PCAL_ESTATE (already
  * started / not started), PCAL_ENOTSUP, PCAL_ENOMEM, PCAL_EHIP (a launch

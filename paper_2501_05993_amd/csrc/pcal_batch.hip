@@ -241,9 +241,11 @@ int pcal_batch_add(pcal_batch_t b, int64_t fs_hz, int64_t f_comb_hz, int64_t f_o
             break;
         }
     if (slot < 0 && static_cast<int>(b->members.size()) >= b->max_streams) return PCAL_EAGAIN;
+    // the period fold at the batch's workgroup size; a stream no fold period
+    // fits takes a per-sample form (AUTO's), run in launches of its own
     pcal_ctx *h = nullptr;
-    const int rc = create(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_PERIOD_FOLD, b->prec,
-                          b->threads, &h);
+    int rc = create(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_PERIOD_FOLD, b->prec, b->threads, &h);
+    if (rc == PCAL_ENOTSUP) rc = create(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_AUTO, b->prec, 0, &h);
     if (rc) return rc;
     if (slot < 0) {
         b->members.push_back(h);
@@ -274,14 +276,16 @@ int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *co
         std::fill(b->seen.begin(), b->seen.end(), 0u);
         b->stamp = 1;
     }
+    bool any = false;
     for (int i = 0; i < count; ++i) {
         const Plan &p = b->members[ids[i]]->plan;
         if (nsamples[i] < 0 || nsamples[i] % (8 / p.nbits) || (nsamples[i] > 0 && !dev_ptrs[i])) return PCAL_EINVAL;
         if (b->seen[ids[i]] == b->stamp) return PCAL_EINVAL;
         b->seen[ids[i]] = b->stamp;
-        total_bytes += nsamples[i] * p.nbits / 8;
+        any = any || nsamples[i] > 0;
+        if (p.method == PCAL_METHOD_PERIOD_FOLD) total_bytes += nsamples[i] * p.nbits / 8;  // the fold work-list
     }
-    if (total_bytes == 0) return PCAL_OK;
+    if (!any) return PCAL_OK;
     DeviceGuard guard(b->members[ids[0]]->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((rc = order_members(b, count, ids, s))) return rc;
@@ -289,22 +293,23 @@ int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *co
     // launch per sample width).  A short list travels in the kernel
     // arguments; a longer one is staged and copied.
     int n = 0, grid = 0, grid2 = 0, threads = 64, used = 0;
+    auto folded = [&](int i) { return nsamples[i] > 0 && b->members[ids[i]]->plan.method == PCAL_METHOD_PERIOD_FOLD; };
     for (int i = 0; i < count; ++i)
-        if (nsamples[i] > 0) {
+        if (folded(i)) {
             threads = std::max(threads, b->members[ids[i]]->plan.geom.threads);
             ++used;
         }
     FoldListInline il;
     Stage *st = nullptr;
     const bool inl = used <= kInlineFoldItems;
-    if (!inl && (rc = take_stage(b, &st))) return rc;
+    if (used > 0 && !inl && (rc = take_stage(b, &st))) return rc;
     FoldArgs *items = inl ? il.items : st->h_items;
     int *first = inl ? il.first : st->h_first;
     size_t lds[2] = {0, 0};
     for (int pass = 0; pass < 2; ++pass) {
         const int width = pass == 0 ? 2 : 8;
         for (int i = 0; i < count; ++i) {
-            if (nsamples[i] == 0 || b->members[ids[i]]->plan.nbits != width) continue;
+            if (!folded(i) || b->members[ids[i]]->plan.nbits != width) continue;
             pcal_ctx *h = b->members[ids[i]];
             const Plan &p = h->plan;
             const int64_t bytes = nsamples[i] * p.nbits / 8;
@@ -322,7 +327,9 @@ int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *co
         if (pass == 0) grid2 = grid;
     }
     first[n] = grid;
-    if (inl) {
+    if (used == 0) {
+        // no fold member in this call
+    } else if (inl) {
         il.n = n;
         launch_fold_batch(il, kernel_prec(b->prec), grid2, grid - grid2, threads, lds[0], lds[1], s);
         PCAL_HIP(hipGetLastError());
@@ -335,8 +342,14 @@ int pcal_batch_extract(pcal_batch_t b, int count, const int *ids, const void *co
         st->pending = true;
     }
     for (int i = 0; i < count; ++i) {
-        b->members[ids[i]]->n_total += nsamples[i];
-        b->members[ids[i]]->n_integ += nsamples[i];
+        pcal_ctx *h = b->members[ids[i]];
+        if (h->plan.method == PCAL_METHOD_PERIOD_FOLD) {
+            h->n_total += nsamples[i];
+            h->n_integ += nsamples[i];
+        } else if (nsamples[i] > 0) {
+            // a per-sample member: its own launch, after the fold's on the same stream
+            if ((rc = pcal_extract(h, dev_ptrs[i], nsamples[i], stream))) return rc;
+        }
     }
     return mark_members(b, count, ids, s);
 }

@@ -252,7 +252,7 @@ void free_resident(pcal_server_ctx *s) {
 
 // Resident form: whether a stream's plan fits the persistent kernel.
 bool resident_fits(const pcal_server_ctx *s, const Plan &p) {
-    return p.N <= kServedMaxTones && p.geom.col_tiles <= s->tasks;
+    return p.method == PCAL_METHOD_PERIOD_FOLD && p.N <= kServedMaxTones && p.geom.col_tiles <= s->tasks;
 }
 
 // Resident form: publish queued pieces as long as the ring has room; a piece
@@ -375,9 +375,12 @@ int pcal_server_open(pcal_server_t s, int64_t fs_hz, int64_t f_comb_hz, int64_t 
     if (slot < 0) return PCAL_EAGAIN;
     // admission, before anything is allocated: the device memory of the
     // stream's tables and accumulators, from its plan, must fit the budget left
+    // (the plan the batch will make: the period fold, else AUTO's per-sample form)
     Plan plan{};
     int rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_PERIOD_FOLD, s->prec, &plan,
                        batch_threads(s->batch));
+    if (rc == PCAL_ENOTSUP)
+        rc = make_plan(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_AUTO, s->prec, &plan, 0);
     if (rc) return rc;
     if (s->resident && !resident_fits(s, plan)) return PCAL_ENOTSUP;
     if (s->used + plan_device_bytes(plan) > s->budget) return PCAL_EAGAIN;

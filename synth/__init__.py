@@ -103,6 +103,23 @@ def comb_period(spec: CombSpec) -> np.ndarray:
     return spec.amp * out
 
 
+def comb_values(spec: CombSpec, start: int, count: int) -> np.ndarray:
+    """The noiseless comb of Eq. 1 at samples start .. start+count-1: the same values, to the bit, as
+    ``comb_period(spec)`` at those indices modulo the period (same integer reduction, same per-tone
+    summation order), without building a whole period -- for periods far longer than the range."""
+    _check(spec)
+    per = comb_period_length(spec)
+    g = spec.fs // per
+    n = np.arange(start, start + count, dtype=np.int64) % per
+    phi = tone_phases(spec)
+    out = np.zeros(count, dtype=np.float64)
+    for i in range(spec.ntones):
+        a = ((i * spec.f_comb + spec.f_offset) // g) % per
+        m = (a * n) % per
+        out += np.sin(2.0 * np.pi * m / per + phi[i])
+    return spec.amp * out
+
+
 def _quantise_host(x: np.ndarray, nbits: int) -> np.ndarray:
     if nbits == 2:
         t0, t1, t2 = TWO_BIT_THRESHOLDS
@@ -134,8 +151,10 @@ def make_stream(spec: CombSpec, nsamples: int, n0: int = 0, chunk: int = 1 << 22
     spb = spec.samples_per_byte
     if nsamples % spb or n0 % spb:
         raise ValueError("nsamples and n0 must be multiples of the samples per byte")
-    comb = comb_period(spec) if spec.amp != 0.0 else None
     per = comb_period_length(spec)
+    # a period longer than the range: evaluate the comb at the samples generated instead
+    direct = spec.amp != 0.0 and per > nsamples
+    comb = comb_period(spec) if spec.amp != 0.0 and not direct else None
     out = np.empty(nsamples // spb, dtype=np.uint8)
     blk = 1 << 16
     pos = 0
@@ -148,7 +167,9 @@ def make_stream(spec: CombSpec, nsamples: int, n0: int = 0, chunk: int = 1 << 22
         noise = rng.standard_normal(blk)
         off = g - b0 * blk
         x = spec.sigma * noise[off:off + take]
-        if comb is not None:
+        if direct:
+            x = x + comb_values(spec, g, take)
+        elif comb is not None:
             idx = (np.arange(g, g + take, dtype=np.int64)) % per
             x = x + comb[idx]
         q = _quantise_host(x, spec.nbits)
@@ -175,8 +196,12 @@ def make_stream_device(spec: CombSpec, nsamples: int, device: str = "cuda", chun
     if nsamples % spb:
         raise ValueError("nsamples must be a multiple of the samples per byte")
     per = comb_period_length(spec)
-    comb = torch.as_tensor(comb_period(spec) if spec.amp != 0.0 else np.zeros(per), dtype=torch.float32,
-                           device=device)
+    if spec.amp != 0.0 and per > nsamples:
+        # a period longer than the range: the comb at samples 0 .. nsamples-1 (indices stay below per)
+        host = comb_values(spec, 0, nsamples)
+    else:
+        host = comb_period(spec) if spec.amp != 0.0 else np.zeros(per)
+    comb = torch.as_tensor(host, dtype=torch.float32, device=device)
     seed = 0
     for s in spec.seed:
         seed = (seed * 1000003 + int(s) + 1) % (1 << 62)

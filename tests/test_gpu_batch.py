@@ -273,3 +273,39 @@ def test_batch_reduced_precision_alone_equals_mix(pc, prec):
         err = np.abs(C[i] - Cs).max() / scale
         say("alone vs mix prec %d member %d: %.2e" % (prec, i, err))
         assert err < (1e-6 if prec == 1 else 1e-5), (i, err)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_with_per_sample_members(pc, prec):
+    """Members no fold period fits (prime f_offset: rotator period = fs, beyond 2^26 samples or 2^20
+    rotator rows) take AUTO's per-sample form and run in launches of their own beside the batched
+    fold: a fold member and two per-sample members (2- and 8-bit) in two batched calls, each against
+    the oracle (FP64: 1e-10; mixed: the contract), and results reset between integrations."""
+    specs = [synth.CombSpec(64_000_000, 1_000_000, 10_000, 2, amp=0.3, t_d=4e-9, seed=(91, 0)),
+             synth.CombSpec(128_000_000, 2_000_000, 10_007, 2, amp=0.3, t_d=2e-9, seed=(91, 1)),
+             synth.CombSpec(64_000_000, 2_000_000, 10_007, 8, amp=4.0, t_d=6e-9, sigma=20.0, seed=(91, 2))]
+    L = 1 << 21
+    say("batch with per-sample members, precision form %d" % prec)
+    packed = [synth.make_stream(s, 2 * L) for s in specs]
+    devs = [torch.from_numpy(p).cuda() for p in packed]
+    spb = [8 // s.nbits for s in specs]
+    with pc.PCalBatch(4, precision=prec) as b:
+        ids = [b.add(s.fs, s.f_comb, s.f_offset, s.nbits) for s in specs]
+        methods = [b.member_info(i)["method"] for i in ids]
+        assert methods[0] == pc.METHOD_PERIOD_FOLD
+        assert methods[1] in (pc.METHOD_OSC, pc.METHOD_CFO) and methods[2] in (pc.METHOD_OSC, pc.METHOD_CFO)
+        for k in range(2):  # two integrations, two calls each (the second starting mid-row)
+            c1 = 4 * 123_457
+            b.extract(ids, [d.data_ptr() + k * L // q for d, q in zip(devs, spb)], [c1] * 3)
+            b.extract(ids, [d.data_ptr() + (k * L + c1) // q for d, q in zip(devs, spb)], [L - c1] * 3)
+            C = b.spectra(ids)
+            b.reset(ids)
+            for i, s in enumerate(specs):
+                sub = packed[i][k * L // spb[i]:(k + 1) * L // spb[i]]
+                Co = oracle.correlate(sub, s.nbits, L, s.fs, s.f_comb, s.f_offset, n0=k * L)
+                if prec == 0:
+                    assert_spectra(C[i], Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6,
+                                   what="member %d (%s), integration %d" % (i, methods[i], k))
+                else:
+                    assert_spectra(C[i], Co, amp_rtol=AMP_RTOL, phase_atol=PHASE_ATOL, rel_floor=1e-6,
+                                   what="mixed member %d, integration %d" % (i, k))

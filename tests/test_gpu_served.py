@@ -246,6 +246,107 @@ def test_served_resident_states_and_limits():
     srv.close()
 
 
+PER_SAMPLE_MIX = [
+    # fs, f_comb, f_offset, nbits, integration samples: one fold stream, two no fold period fits
+    (64_000_000, 1_000_000, 10_000, 2, 600_000),
+    (128_000_000, 2_000_000, 10_007, 2, 500_000),
+    (64_000_000, 2_000_000, 10_007, 8, 400_000),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_served_host_step_per_sample_streams(prec):
+    """Streams whose rotator has no fold period that fits (prime f_offset) are admitted by the host-step
+    form, which runs them in per-sample launches beside the batched fold: every integration of each
+    stream, arriving in random chunks, equals a plain AUTO handle's; the resident form refuses them
+    (PCAL_ENOTSUP), both at open on a started server and at start with one open."""
+    import torch
+
+    from paper_2501_05993_amd import pcal
+
+    bufs = []
+    for i, (fs, fc, fo, nbits, integ) in enumerate(PER_SAMPLE_MIX):
+        spec = synth.CombSpec(fs, fc, fo, nbits, amp=0.3 if nbits == 2 else 4.0, t_d=5e-9,
+                              sigma=1.0 if nbits == 2 else 20.0, seed=(71, i))
+        bufs.append(synth.make_stream_device(spec, TOTAL))
+    torch.cuda.synchronize()
+    srv = pcal.PCalServer(mem_budget_bytes=1 << 30, max_streams=4, precision=prec)
+    srv.start(workgroups=8)
+    with pytest.raises(pcal.PcalError) as e:
+        srv.open(*PER_SAMPLE_MIX[1])
+    assert e.value.code == pcal.ENOTSUP
+    srv.stop()
+    sids = [srv.open(*m) for m in PER_SAMPLE_MIX]
+    with pytest.raises(pcal.PcalError) as e:
+        srv.start(workgroups=8)
+    assert e.value.code == pcal.ENOTSUP
+    rng = np.random.default_rng(17)
+    arrivals = []
+    for i, (fs, fc, fo, nbits, integ) in enumerate(PER_SAMPLE_MIX):
+        off = 0
+        for c in _chunks(rng, TOTAL, 8 // nbits):
+            arrivals.append((rng.random(), i, off, c))
+            off += c
+    # a random arrival order across streams, each stream's chunks in order
+    arrivals.sort(key=lambda a: a[0])
+    nxt = {i: 0 for i in range(len(PER_SAMPLE_MIX))}
+    per = {i: sorted([a for a in arrivals if a[1] == i], key=lambda a: a[2]) for i in nxt}
+    order = []
+    for a in arrivals:
+        order.append(per[a[1]][nxt[a[1]]])
+        nxt[a[1]] += 1
+    say("served host-step with per-sample streams (precision form %d): %d chunks" % (prec, len(order)))
+    got = {}
+    k = 0
+    while k < len(order) or srv.stats()["queued_samples"] > 0:
+        burst = order[k:k + int(rng.integers(1, 6))]
+        k += len(burst)
+        if burst:
+            srv.submit([sids[i] for _, i, _, _ in burst],
+                       [bufs[i].data_ptr() + off // (8 // PER_SAMPLE_MIX[i][3]) for _, i, off, _ in burst],
+                       [c for _, _, _, c in burst])
+        srv.step()
+        for sid, integ in srv.poll():
+            got[(sid, integ)] = srv.spectrum(sid, integ)
+    torch.cuda.synchronize()
+    for _ in range(100):
+        for sid, integ in srv.poll():
+            got[(sid, integ)] = srv.spectrum(sid, integ)
+        if srv.stats()["inflight_finalizes"] == 0:
+            break
+    bad = []
+    for i, (fs, fc, fo, nbits, integ) in enumerate(PER_SAMPLE_MIX):
+        spb = 8 // nbits
+        with pcal.PCal(fs, fc, fo, nbits, precision=prec) as h:
+            if i:
+                assert h.info()["method"] != pcal.METHOD_PERIOD_FOLD
+            for k2 in range(TOTAL // integ):
+                h.extract(bufs[i], integ, byte_offset=k2 * integ // spb)
+                w = h.spectrum()
+                h.reset()
+                assert (sids[i], k2) in got, "integration %d of stream %d not reported" % (k2, i)
+                # a per-sample form in FP32 restarts its rotator recurrence at every launch: chunked
+                # and whole extraction differ by that FP32 recurrence error, within the contract
+                at, pt = (ALONE_TOL[prec],) * 2 if i == 0 or prec == 0 else (AMP_RTOL, PHASE_ATOL)
+                try:
+                    assert_spectra(got[(sids[i], k2)], w, amp_rtol=at, phase_atol=pt,
+                                   rel_floor=1e-6, what="stream %d integration %d" % (i, k2))
+                except AssertionError as err:
+                    bad.append(str(err))
+    assert not bad, bad
+    # a per-sample stream against the oracle: its second integration
+    fs, fc, fo, nbits, integ = PER_SAMPLE_MIX[2]
+    host = bufs[2].cpu().numpy()
+    want = oracle.correlate(host[integ:2 * integ], nbits, integ, fs, fc, fo, n0=integ)
+    if prec == 0:
+        assert_spectra(got[(sids[2], 1)], want, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6,
+                       what="per-sample stream vs oracle")
+    else:
+        assert_spectra(got[(sids[2], 1)], want, amp_rtol=AMP_RTOL, phase_atol=PHASE_ATOL, rel_floor=1e-6,
+                       what="per-sample stream, form %d, vs oracle" % prec)
+    srv.close()
+
+
 def test_served_resident_relaunch_after_idle(monkeypatch):
     """The device-resident loop leaves once idle for its limit (200 ms here) and the next step launches
     it again where it stopped: integrations served before and after equal plain extraction, and the

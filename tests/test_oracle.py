@@ -255,6 +255,21 @@ def test_packed_chunking(oracle_lib):
     np.testing.assert_array_equal(synth.make_stream(spec, L - cut, n0=cut), b[cut // 4:])
 
 
+def test_long_period_comb_evaluated_directly():
+    """For a comb period longer than the range generated, the generator evaluates the comb at the samples
+    themselves: the same values, to the bit, as the period table at those indices (and so the same bytes
+    for a sub-range cut out of a longer generation, across a period boundary too)."""
+    spec = synth.CombSpec(4_000_000, 1_000_000, 1_001, 2, amp=0.3, t_d=2e-9, seed=(9, 1))
+    per = synth.comb_period(spec)
+    assert per.size == 4_000_000
+    for start, count in [(0, 4096), (3_998_000, 5000), (123_457, 1)]:
+        idx = np.arange(start, start + count) % per.size
+        np.testing.assert_array_equal(synth.comb_values(spec, start, count), per[idx])
+    whole = synth.make_stream(spec, 8_000_000)            # two periods: the table path
+    part = synth.make_stream(spec, 1 << 16, n0=3_990_000)  # shorter than the period: the direct path
+    np.testing.assert_array_equal(part, whole[3_990_000 // 4:(3_990_000 + (1 << 16)) // 4])
+
+
 def test_conjugate_symmetry(oracle_lib):
     rng = np.random.default_rng(8)
     x = rng.standard_normal(7777)
