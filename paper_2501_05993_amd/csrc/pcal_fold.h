@@ -668,22 +668,14 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
     double2 *TW = tw_lds ? P + N : nullptr;
     double2 *red = P + (tw_lds ? 2 * N : N);
     const bool f32 = a.prec == 2;
-    for (int i = t; me && i < N; i += 256) {
-        // add the accumulator slots in slot order
-        double re = 0.0, im = 0.0;
-        float fr = 0.f, fi = 0.f;
-#pragma unroll
-        for (int k = 0; k < kAccSlots; ++k) {
-            if (f32) {
-                fr += a.accf[k * N + i].x;
-                fi += a.accf[k * N + i].y;
-            } else {
-                re += a.acc[k * N + i].x;
-                im += a.acc[k * N + i].y;
-            }
+    {
+        const double2 *acc = a.acc, *tw = a.tw;
+        const float2 *accf = a.accf;
+        for (int i = t; me && i < N; i += 256) {
+            const double2 w = tw[i];  // issued with the slot loads
+            P[i] = slot_sum(acc, accf, f32, N, i);
+            if (tw_lds) TW[i] = w;
         }
-        P[i] = f32 ? make_double2(fr, fi) : make_double2(re, im);
-        if (tw_lds) TW[i] = a.tw[i];
     }
     __syncthreads();
     const int k = wg * 64 + lane;
@@ -764,7 +756,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
 
     // Delay: unwrap phases over tones [k_lo, k_hi) and fit phase = a + 2 pi t_d f.
     const int n = a.k_hi - a.k_lo;
-    double *sh = reinterpret_cast<double *>(lds);  // reuse: [256] segment sums, [256] products
+    double *sh = reinterpret_cast<double *>(lds);  // reuse: [4] wave totals of the scan, [4] of the products
     const double *ph = (nwg == 1 ? s_ph : a.phases) + a.k_lo;
     const int seg = (n + 255) / 256;
     const int s0 = t * seg;
@@ -799,19 +791,20 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int wg, co
         }
         sxu += (static_cast<double>(i) - kbar) * unw;
     }
+    // the sum of the products: a fixed shuffle tree in each of the four waves,
+    // then the wave totals in wave order (sh[0..3] still hold the scan's)
+    double v = me ? sxu : 0.0;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
+    if (me && lane == 0) sh[4 + wave] = v;
     __syncthreads();
-    if (me) sh[t] = sxu;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w) sh[t] += sh[t + w];
-        __syncthreads();
-    }
     if (t == 0) {
         double delay = 0.0;
         if (n >= 2) {
             const double dn = static_cast<double>(n);
             const double sxx = dn * (dn * dn - 1.0) / 12.0;
-            delay = sh[0] / sxx / a.f_comb / two_pi;
+            const double sum = ((sh[4] + sh[5]) + sh[6]) + sh[7];
+            delay = sum / sxx / a.f_comb / two_pi;
         }
         a.out[4 * N] = delay;
     }

@@ -22,6 +22,35 @@ constexpr int kEpilogueScratch = 40;
 // Copies of the integration bins that fold workgroups add into (workgroup mod
 // kAccSlots), summed by the finalize: spreads same-address atomics.
 constexpr int kAccSlots = 16;
+
+// Bin i of [kAccSlots][N] accumulators, the slots added in slot order (FP32
+// sums for the FP32 form, FP64 otherwise).  Every slot is loaded before the
+// first add, with no branch between the loads, so the kAccSlots reads are in
+// flight together rather than one memory round trip after another.
+__device__ __forceinline__ double2 slot_sum(const double2 *acc, const float2 *accf, bool f32, int N, int i) {
+    if (f32) {
+        float2 v[kAccSlots];
+#pragma unroll
+        for (int k = 0; k < kAccSlots; ++k) v[k] = accf[k * N + i];
+        float fr = 0.f, fi = 0.f;
+#pragma unroll
+        for (int k = 0; k < kAccSlots; ++k) {
+            fr += v[k].x;
+            fi += v[k].y;
+        }
+        return make_double2(fr, fi);
+    }
+    double2 v[kAccSlots];
+#pragma unroll
+    for (int k = 0; k < kAccSlots; ++k) v[k] = acc[k * N + i];
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int k = 0; k < kAccSlots; ++k) {
+        re += v[k].x;
+        im += v[k].y;
+    }
+    return make_double2(re, im);
+}
 // Largest workgroup of the fold kernel.
 constexpr int kMaxFoldThreads = 768;
 // Largest workgroup of the per-sample rotation kernels (they keep 16 complex lanes
@@ -248,8 +277,8 @@ struct ServedArgs {
     unsigned long long *heartbeat;  // device: the scheduler's round count, rewritten every round
     unsigned long long *done_cursor;  // device: next completion record
     unsigned *slot_cnt;          // device [cap]: tasks of the chunk in the slot that ended
-    unsigned *task_done;         // device [streams][2]: tasks of the integration in the bank that ended
-    unsigned *fin_total;         // device [streams][2]: tasks of that integration, once its last chunk is known
+    unsigned long long *task_done;  // device [streams][2]: tasks of the integration in the bank that ended (low
+                                    // 32 bits) and its task total once its last chunk has counted (high 32 bits)
     FinArgs *fin_args;           // device [streams][2]: that integration's finalize, from its last chunk
     ServedDesc *dring;           // device [cap]: the scheduler's copy of each slot's descriptor
     unsigned long long *mail_assigned;  // device [grid][kMailStride]: task + 2 handed to the worker; 1: leave
@@ -274,9 +303,10 @@ static_assert(kServedLds >= 8 * kServedMaxWorkgroups + 4 * (2 * kServedMaxRing +
 static_assert(kServedMaxRing <= kServedThreads, "one scheduler thread per pending chunk");
 constexpr int kServedMaxTones = 1792;
 // The served loop's one-workgroup finalize keeps the bins, the phases and 256
-// scratch words in LDS, and the twiddles too up to this many tones.
+// scratch words in LDS, and the twiddles and the tone results too up to this
+// many tones.
 constexpr int kServedTwLdsTones = 1024;
-static_assert(kServedLds >= 40 * kServedTwLdsTones + 8 * 256 && kServedLds >= 24 * kServedMaxTones + 8 * 256,
+static_assert(kServedLds >= 56 * kServedTwLdsTones + 8 * 256 && kServedLds >= 24 * kServedMaxTones + 8 * 256,
               "served finalize");
 
 // Work-lists of the batched kernels: item i owns workgroups [first[i],

@@ -30,19 +30,7 @@ constexpr int kPulseThreads = 256;
 
 // Bin i with the accumulator slots added in slot order (as the finalize adds them).
 __device__ __forceinline__ double2 pulse_bin(const PulseArgs &a, int i) {
-    double re = 0.0, im = 0.0;
-    float fr = 0.f, fi = 0.f;
-#pragma unroll
-    for (int k = 0; k < kAccSlots; ++k) {
-        if (a.prec == PCAL_PREC_F32) {
-            fr += a.accf[k * a.N + i].x;
-            fi += a.accf[k * a.N + i].y;
-        } else {
-            re += a.acc[k * a.N + i].x;
-            im += a.acc[k * a.N + i].y;
-        }
-    }
-    return a.prec == PCAL_PREC_F32 ? make_double2(fr, fi) : make_double2(re, im);
+    return slot_sum(a.acc, a.accf, a.prec == PCAL_PREC_F32, a.N, i);
 }
 
 // Bin i times the form's known gain (the mixed form's table gain, the

@@ -37,6 +37,7 @@ constexpr int kWords = static_cast<int>(sizeof(ServedDesc) / 4);
 constexpr int kFinWords = static_cast<int>(sizeof(FinArgs) / 4);
 static_assert(sizeof(FinArgs) % 4 == 0, "finalize arguments are copied as words");
 constexpr int kNtasksWord = static_cast<int>(offsetof(ServedDesc, ntasks) / 4);
+constexpr int kScanEvery = 16;  // scheduler rounds with nothing pending between reads of the mailboxes
 constexpr unsigned long long kLeave = 1ull;  // mailbox value: leave the loop (tasks are handed out as task + 2)
 
 // Workgroup 0: hand the published tasks out, chunk after chunk and in task
@@ -63,13 +64,16 @@ __device__ void schedule(const ServedArgs &sa, unsigned char *lds) {
     int *s_pref = s_ntasks + kServedMaxRing;  // [kServedMaxRing + 1]: exclusive prefix of the pending tasks
     int *s_wave = s_pref + kServedMaxRing + 1;  // [16]: per-wave totals
     __shared__ unsigned long long s_chunks, s_copied, s_next;
-    __shared__ int s_next_wg, s_quit, s_pending, s_busy, s_handed;
+    __shared__ int s_next_wg, s_quit, s_pending, s_busy, s_handed, s_skip;
     for (int w = t; w < G; w += nt) s_assigned[w] = 1ull;  // a started, idle worker's mailbox reads 1
     if (t == 0) {
         // every chunk before s_next was handed out, and has ended, in an earlier launch
         s_next = ld_agent(sa.sched);
         s_copied = s_next;
         s_next_wg = 0;
+        s_skip = 0;
+        s_busy = 0;
+        s_pending = 0;
     }
     __syncthreads();
     unsigned long long polls = 0, rounds_idle = 0, copies = 0;
@@ -103,105 +107,113 @@ __device__ void schedule(const ServedArgs &sa, unsigned char *lds) {
         if (t == 0) s_copied = chunks;
         // pending tasks: chunks [next, chunks), the first one from task s_next_wg
         const int P = static_cast<int>(chunks - next);  // <= cap <= kServedMaxRing <= nt
-        int rem = 0;
-        if (t < P) {
-            const int slot = static_cast<int>((next + t) % static_cast<unsigned>(sa.cap));
-            rem = s_ntasks[slot] - (t == 0 ? s_next_wg : 0);
-        }
-        int incl = rem;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int o = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += o;
-        }
-        if (lane == 63) s_wave[wave] = incl;
-        __syncthreads();
-        int before = 0, total = 0;
-        for (int w = 0; w < nwaves; ++w) {
-            if (w < wave) before += s_wave[w];
-            total += s_wave[w];
-        }
-        if (t < P) s_pref[t + 1] = before + incl;
-        if (t == 0) s_pref[0] = 0;
-        __syncthreads();
-        // idle workers ranked in worker order: the k-th gets pending task k
-        int rank_base = 0, busy = 0, handed = 0;
-        for (int w0 = 1; w0 < G; w0 += nt) {
-            const int w = w0 + t;
-            bool idle = false;
-            if (w < G) {
-                const unsigned long long dv = ld_agent(sa.mail_done + static_cast<size_t>(w) * kMailStride);
-                idle = dv == s_assigned[w];
-                // not started yet (its mailbox still zero, nothing handed to it): neither idle nor busy
-                busy += (idle || (dv == 0ull && s_assigned[w] == 1ull)) ? 0 : 1;
+        // with nothing pending a round only watches the host's count: the
+        // workers' mailboxes are read again every kScanEvery such rounds (the
+        // busy count the idle exit needs)
+        const bool scan = P > 0 || s_skip >= kScanEvery;
+        int nh = 0;
+        if (scan) {
+            int rem = 0;
+            if (t < P) {
+                const int slot = static_cast<int>((next + t) % static_cast<unsigned>(sa.cap));
+                rem = s_ntasks[slot] - (t == 0 ? s_next_wg : 0);
             }
-            const unsigned long long mask = __ballot(idle);
-            __syncthreads();  // every read of s_wave above is done
-            if (lane == 0) s_wave[wave] = __popcll(mask);
+            int incl = rem;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int o = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += o;
+            }
+            if (lane == 63) s_wave[wave] = incl;
             __syncthreads();
-            int wb = 0, wt = 0;
-            for (int v = 0; v < nwaves; ++v) {
-                wt += s_wave[v];
-                if (v < wave) wb += s_wave[v];
+            int before = 0, total = 0;
+            for (int w = 0; w < nwaves; ++w) {
+                if (w < wave) before += s_wave[w];
+                total += s_wave[w];
             }
-            const int r = rank_base + wb + __popcll(mask & ((1ull << lane) - 1ull));
-            if (idle && r < total) {
-                // pending task r: chunk j with s_pref[j] <= r < s_pref[j + 1]
-                int lo = 0, hi = P - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_pref[mid] <= r)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
+            if (t < P) s_pref[t + 1] = before + incl;
+            if (t == 0) s_pref[0] = 0;
+            __syncthreads();
+            // idle workers ranked in worker order: the k-th gets pending task k
+            int rank_base = 0, busy = 0, handed = 0;
+            for (int w0 = 1; w0 < G; w0 += nt) {
+                const int w = w0 + t;
+                bool idle = false;
+                if (w < G) {
+                    const unsigned long long dv = ld_agent(sa.mail_done + static_cast<size_t>(w) * kMailStride);
+                    idle = dv == s_assigned[w];
+                    // not started yet (its mailbox still zero, nothing handed to it): neither idle nor busy
+                    busy += (idle || (dv == 0ull && s_assigned[w] == 1ull)) ? 0 : 1;
                 }
-                const int wg = (lo == 0 ? s_next_wg : 0) + (r - s_pref[lo]);
-                const unsigned long long task = (next + lo) * static_cast<unsigned>(sa.tasks) + wg;
-                s_assigned[w] = task + 2;
-                st_agent(sa.mail_assigned + static_cast<size_t>(w) * kMailStride, task + 2);
-                ++handed;
+                const unsigned long long mask = __ballot(idle);
+                __syncthreads();  // every read of s_wave above is done
+                if (lane == 0) s_wave[wave] = __popcll(mask);
+                __syncthreads();
+                int wb = 0, wt = 0;
+                for (int v = 0; v < nwaves; ++v) {
+                    wt += s_wave[v];
+                    if (v < wave) wb += s_wave[v];
+                }
+                const int r = rank_base + wb + __popcll(mask & ((1ull << lane) - 1ull));
+                if (idle && r < total) {
+                    // pending task r: chunk j with s_pref[j] <= r < s_pref[j + 1]
+                    int lo = 0, hi = P - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pref[mid] <= r)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                    const int wg = (lo == 0 ? s_next_wg : 0) + (r - s_pref[lo]);
+                    const unsigned long long task = (next + lo) * static_cast<unsigned>(sa.tasks) + wg;
+                    s_assigned[w] = task + 2;
+                    st_agent(sa.mail_assigned + static_cast<size_t>(w) * kMailStride, task + 2);
+                    ++handed;
+                }
+                rank_base += wt;
             }
-            rank_base += wt;
-        }
-        // tasks handed out and workers busy, summed over the workgroup
-        int h = handed, b = busy;
+            // tasks handed out and workers busy, summed over the workgroup
+            int h = handed, b = busy;
 #pragma unroll
-        for (int d = 32; d > 0; d >>= 1) {
-            h += __shfl_xor(h, d, 64);
-            b += __shfl_xor(b, d, 64);
-        }
-        if (t == 0) {
-            s_handed = 0;
-            s_busy = 0;
-        }
-        __syncthreads();
-        if (lane == 0) {
-            atomicAdd(&s_handed, h);
-            atomicAdd(&s_busy, b);
-        }
-        __syncthreads();
-        const int nh = s_handed;
-        if (t == 0) {
-            // move past the tasks handed out
-            if (nh >= total) {
-                s_next = chunks;
-                s_next_wg = 0;
-            } else if (nh > 0) {
-                int lo = 0, hi = P - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_pref[mid] <= nh)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
-                }
-                s_next_wg = (lo == 0 ? s_next_wg : 0) + (nh - s_pref[lo]);
-                s_next = next + lo;
+            for (int d = 32; d > 0; d >>= 1) {
+                h += __shfl_xor(h, d, 64);
+                b += __shfl_xor(b, d, 64);
             }
-            s_pending = total - nh;
+            if (t == 0) {
+                s_handed = 0;
+                s_busy = 0;
+            }
+            __syncthreads();
+            if (lane == 0) {
+                atomicAdd(&s_handed, h);
+                atomicAdd(&s_busy, b);
+            }
+            __syncthreads();
+            nh = s_handed;
+            if (t == 0) {
+                // move past the tasks handed out
+                if (nh >= total) {
+                    s_next = chunks;
+                    s_next_wg = 0;
+                } else if (nh > 0) {
+                    int lo = 0, hi = P - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pref[mid] <= nh)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                    s_next_wg = (lo == 0 ? s_next_wg : 0) + (nh - s_pref[lo]);
+                    s_next = next + lo;
+                }
+                s_pending = total - nh;
+            }
         }
         __syncthreads();
         const bool quiet = s_pending == 0 && s_busy == 0 && nh == 0;
+        if (t == 0) s_skip = scan ? 0 : s_skip + 1;
         const unsigned long long now = wall_clock64();
         if (!quiet) t_work = now;
         if (s_quit && t_quit == 0) t_quit = now;
@@ -243,27 +255,23 @@ __device__ void finalize_wg(const FinArgs &a, unsigned char *lds) {
     const bool tw_lds = N <= kServedTwLdsTones;
     double2 *P = reinterpret_cast<double2 *>(lds);
     double2 *TW = tw_lds ? P + N : nullptr;
-    double *ph = reinterpret_cast<double *>(P + (tw_lds ? 2 * N : N));  // [N] phases
-    double *sh = ph + N;                                                // [256] scan and reduction scratch
+    // with the twiddles in LDS the results wait there too, for one pass of
+    // writes to the (host) output at the end: one wait for their acknowledgement
+    double2 *C = tw_lds ? P + 2 * N : nullptr;
+    double *ph = reinterpret_cast<double *>(P + (tw_lds ? 3 * N : N));  // [N] phases
+    double *sh = ph + N;  // [4] wave totals of the scan, [4] of the products
     const bool f32 = a.prec == 2;
     const bool fft = !f32 && tw_lds && N >= 2 && (N & (N - 1)) == 0;
     const int log2n = fft ? __builtin_ctz(static_cast<unsigned>(N)) : 0;
-    for (int i = t; i < N; i += nt) {
-        double re = 0.0, im = 0.0;
-        float fr = 0.f, fi = 0.f;
-#pragma unroll
-        for (int k = 0; k < kAccSlots; ++k) {
-            if (f32) {
-                fr += a.accf[k * N + i].x;
-                fi += a.accf[k * N + i].y;
-            } else {
-                re += a.acc[k * N + i].x;
-                im += a.acc[k * N + i].y;
-            }
+    {
+        const double2 *acc = a.acc, *tw = a.tw;
+        const float2 *accf = a.accf;
+        for (int i = t; i < N; i += nt) {
+            const int at = fft ? static_cast<int>(__brev(static_cast<unsigned>(i)) >> (32 - log2n)) : i;
+            const double2 w = tw[i];  // issued with the slot loads
+            P[at] = slot_sum(acc, accf, f32, N, i);
+            if (tw_lds) TW[i] = w;
         }
-        const int at = fft ? static_cast<int>(__brev(static_cast<unsigned>(i)) >> (32 - log2n)) : i;
-        P[at] = f32 ? make_double2(fr, fi) : make_double2(re, im);
-        if (tw_lds) TW[i] = a.tw[i];
     }
     __syncthreads();
     if (fft) {
@@ -348,10 +356,14 @@ __device__ void finalize_wg(const FinArgs &a, unsigned char *lds) {
         }
         if (a.sideband < 0) ci = -ci;
         const double phase = atan2(ci, cr);
-        a.out[k] = sqrt(cr * cr + ci * ci) * a.inv_L;
-        a.out[N + k] = phase;
-        a.out[2 * N + k] = cr;
-        a.out[3 * N + k] = ci;
+        if (C) {
+            C[k] = make_double2(cr, ci);
+        } else {
+            a.out[k] = sqrt(cr * cr + ci * ci) * a.inv_L;
+            a.out[N + k] = phase;
+            a.out[2 * N + k] = cr;
+            a.out[3 * N + k] = ci;
+        }
         ph[k] = phase;
     }
     __syncthreads();
@@ -391,21 +403,31 @@ __device__ void finalize_wg(const FinArgs &a, unsigned char *lds) {
         }
         sxu += (static_cast<double>(i) - kbar) * unw;
     }
+    // the sum of the products: a fixed shuffle tree in each of the four waves,
+    // then the wave totals in wave order (sh[0..3] still hold the scan's)
+    double v = me ? sxu : 0.0;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
+    if (me && lane == 0) sh[4 + wave] = v;
     __syncthreads();
-    if (me) sh[t] = sxu;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w) sh[t] += sh[t + w];
-        __syncthreads();
-    }
     if (t == 0) {
         double delay = 0.0;
         if (n >= 2) {
             const double dn = static_cast<double>(n);
             const double sxx = dn * (dn * dn - 1.0) / 12.0;
-            delay = sh[0] / sxx / a.f_comb / two_pi;
+            const double sum = ((sh[4] + sh[5]) + sh[6]) + sh[7];
+            delay = sum / sxx / a.f_comb / two_pi;
         }
         a.out[4 * N] = delay;
+    }
+    if (C) {  // each thread writes the tones it computed
+        for (int k = t; k < N; k += nt) {
+            const double2 c = C[k];
+            a.out[k] = sqrt(c.x * c.x + c.y * c.y) * a.inv_L;
+            a.out[N + k] = ph[k];
+            a.out[2 * N + k] = c.x;
+            a.out[3 * N + k] = c.y;
+        }
     }
     if (a.clear) {
         // start the next integration in this bank: the accumulators the form
@@ -433,7 +455,7 @@ template <int PREC>
 __device__ void work(const ServedArgs &sa, unsigned char *lds) {
     __shared__ __align__(16) ServedDesc d;
     __shared__ __align__(16) FinArgs fa;
-    __shared__ unsigned long long s_val;
+    __shared__ unsigned long long s_val, s_rec;
     __shared__ int s_fin;
     const int t = static_cast<int>(threadIdx.x);
     const size_t me = static_cast<size_t>(blockIdx.x) * kMailStride;
@@ -494,21 +516,25 @@ __device__ void work(const ServedArgs &sa, unsigned char *lds) {
         __syncthreads();
         const unsigned long long t_fold = wall_clock64();
         if (t == 0) {
-            unsigned *done = sa.task_done + bank_ix;
-            unsigned *total = sa.fin_total + bank_ix;
-            if (d.fin_total > 0) {
-                __hip_atomic_store(total, static_cast<unsigned>(d.fin_total), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                wait_memory();  // the total is in place before the count
-            }
-            const unsigned v = __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-            wait_memory();  // the count has landed before the total is read
-            const unsigned want = __hip_atomic_load(total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_fin = (want != 0u && v == want) ? 1 : 0;
-            // the ring slot is free for the host once every task of its chunk
-            // ended (their reads of the slot are complete: the waits above)
+            // one atomic counts the task (low 32 bits) and, from the first
+            // task of the integration's last chunk, brings the integration's
+            // task total (high 32 bits): the task whose count makes the two
+            // equal finalizes (the total is there by then: that first task has
+            // counted).  The ring slot's count goes out beside it: the slot is
+            // free for the host once every task of its chunk ended (their
+            // reads of the slot are complete: the waits above).
+            const unsigned long long add =
+                1ull + (d.fin_total > 0 && wg == 0 ? static_cast<unsigned long long>(d.fin_total) << 32 : 0ull);
+            const unsigned long long v =
+                __hip_atomic_fetch_add(sa.task_done + bank_ix, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + add;
             const unsigned c = __hip_atomic_fetch_add(sa.slot_cnt + slot, 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            const unsigned long long want = v >> 32;
+            s_fin = (want != 0ull && (v & 0xffffffffull) == want) ? 1 : 0;
+            // the finalizing task's completion record, claimed now
+            unsigned long long rec = 0ull;
+            if (s_fin) rec = atomicAdd(sa.done_cursor, 1ull);
+            s_rec = rec;
             if (c == static_cast<unsigned>(d.ntasks)) {
                 __hip_atomic_store(sa.slot_cnt + slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 wait_memory();
@@ -534,14 +560,15 @@ __device__ void work(const ServedArgs &sa, unsigned char *lds) {
             wait_memory();
             __syncthreads();
             if (t == 0) {
-                __hip_atomic_store(sa.task_done + bank_ix, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(sa.fin_total + bank_ix, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-                const unsigned long long k = atomicAdd(sa.done_cursor, 1ull);
+                __hip_atomic_store(sa.task_done + bank_ix, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long k = s_rec;
                 ServedDone *r = sa.done + k % static_cast<unsigned>(sa.done_cap);
                 __hip_atomic_store(&r->sid, d.sid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 __hip_atomic_store(&r->integ, d.integ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                __hip_atomic_store(&r->seq, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                // one release for all of it (results, cleared bank, counters,
+                // the record's fields): the host reads seq, then the rest
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+                __hip_atomic_store(&r->seq, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 add_stat(sa, 5, 1ull);
                 add_stat(sa, 12, wall_clock64() - t_f0);
             }

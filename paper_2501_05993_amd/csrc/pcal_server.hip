@@ -648,7 +648,8 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
     const size_t nsb = 2 * static_cast<size_t>(s->max_streams);
     const size_t cap = static_cast<size_t>(s->cap);
     const size_t o_cnt = 4 * 256;
-    const size_t o_fin = (o_cnt + 4 * cap + 2 * 4 * nsb + 255) & ~static_cast<size_t>(255);
+    const size_t o_done = (o_cnt + 4 * cap + 7) & ~static_cast<size_t>(7);
+    const size_t o_fin = (o_done + 8 * nsb + 255) & ~static_cast<size_t>(255);
     const size_t o_mail = (o_fin + sizeof(FinArgs) * nsb + 255) & ~static_cast<size_t>(255);
     const size_t mail = 8 * kMailStride * static_cast<size_t>(workgroups);
     const size_t o_ring = o_mail + 2 * mail;
@@ -696,8 +697,7 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
     a.heartbeat = reinterpret_cast<unsigned long long *>(dm + 3 * 256);
     static_assert(kServedStats * 8 <= 256, "loop counters fit their line");
     a.slot_cnt = reinterpret_cast<unsigned *>(dm + o_cnt);
-    a.task_done = a.slot_cnt + s->cap;
-    a.fin_total = a.task_done + nsb;
+    a.task_done = reinterpret_cast<unsigned long long *>(dm + o_done);
     a.fin_args = reinterpret_cast<FinArgs *>(dm + o_fin);
     a.mail_assigned = reinterpret_cast<unsigned long long *>(dm + o_mail);
     a.mail_done = reinterpret_cast<unsigned long long *>(dm + o_mail + mail);

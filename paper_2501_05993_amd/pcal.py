@@ -432,6 +432,10 @@ class PCalServer:
         self.ntones = {}
         self._poll_sid = np.zeros(4096, dtype=np.int32)
         self._poll_int = np.zeros(4096, dtype=np.int64)
+        # poll and step run once per turn of a serving loop: their arguments are made once
+        self._poll_args = (self._poll_sid.size, self._poll_sid.ctypes.data, self._poll_int.ctypes.data)
+        self._n = ctypes.c_int()
+        self._dispatched = ctypes.c_int64()
 
     def open(self, fs: int, f_comb: int, f_offset: int, nbits: int, integration_samples: int,
              sideband: int = 1) -> int:
@@ -448,26 +452,32 @@ class PCalServer:
 
     def submit(self, sids, ptrs, nsamples) -> None:
         """Queue chunks: sids, raw device addresses (or tensors) and sample counts, one per chunk."""
-        sv = np.ascontiguousarray(np.asarray(sids, dtype=np.int32))
-        pv = np.ascontiguousarray(np.asarray([p.data_ptr() if isinstance(p, torch.Tensor) else int(p)
-                                              for p in ptrs] if not isinstance(ptrs, np.ndarray) else ptrs,
-                                             dtype=np.uint64))
-        nv = np.ascontiguousarray(np.asarray(nsamples, dtype=np.int64))
-        _check(lib().pcal_server_submit(self._s, sv.size, sv.ctypes.data, pv.ctypes.data, nv.ctypes.data),
-               "pcal_server_submit")
+        n = len(sids)
+        if len(ptrs) != n or len(nsamples) != n:
+            raise ValueError("sids, ptrs and nsamples differ in length")
+        if n == 0:
+            return
+        # plain ctypes arrays: cheaper to build than numpy arrays and their ctypes views
+        sv = (ctypes.c_int32 * n)(*(sids.tolist() if isinstance(sids, np.ndarray) else sids))
+        pv = (ctypes.c_uint64 * n)(*(ptrs.tolist() if isinstance(ptrs, np.ndarray) else
+                                     [p.data_ptr() if isinstance(p, torch.Tensor) else int(p) for p in ptrs]))
+        nv = (ctypes.c_int64 * n)(*(nsamples.tolist() if isinstance(nsamples, np.ndarray) else nsamples))
+        _check(lib().pcal_server_submit(self._s, n, ctypes.addressof(sv), ctypes.addressof(pv),
+                                        ctypes.addressof(nv)), "pcal_server_submit")
 
     def step(self, stream=None) -> int:
-        n = ctypes.c_int64()
-        _check(lib().pcal_server_step(self._s, ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(n)),
-               "pcal_server_step")
+        n = self._dispatched
+        _check(lib().pcal_server_step(self._s, _stream_handle(stream), ctypes.byref(n)), "pcal_server_step")
         return n.value
 
     def poll(self):
         """[(sid, integration), ...] whose results have reached the host."""
-        n = ctypes.c_int()
-        _check(lib().pcal_server_poll(self._s, self._poll_sid.size, self._poll_sid.ctypes.data,
-                                      self._poll_int.ctypes.data, ctypes.byref(n)), "pcal_server_poll")
-        return list(zip(self._poll_sid[:n.value].tolist(), self._poll_int[:n.value].tolist()))
+        n = self._n
+        _check(lib().pcal_server_poll(self._s, *self._poll_args, ctypes.byref(n)), "pcal_server_poll")
+        k = n.value
+        if k == 0:
+            return []
+        return list(zip(self._poll_sid[:k].tolist(), self._poll_int[:k].tolist()))
 
     def result(self, sid: int, integration: int):
         N = self.ntones[sid]
