@@ -436,6 +436,7 @@ class PCalServer:
         self._poll_args = (self._poll_sid.size, self._poll_sid.ctypes.data, self._poll_int.ctypes.data)
         self._n = ctypes.c_int()
         self._dispatched = ctypes.c_int64()
+        self._resident = False
 
     def open(self, fs: int, f_comb: int, f_offset: int, nbits: int, integration_samples: int,
              sideband: int = 1) -> int:
@@ -467,7 +468,9 @@ class PCalServer:
 
     def step(self, stream=None) -> int:
         n = self._dispatched
-        _check(lib().pcal_server_step(self._s, _stream_handle(stream), ctypes.byref(n)), "pcal_server_step")
+        # the device-resident loop launches nothing on the caller's stream
+        handle = None if self._resident and stream is None else _stream_handle(stream)
+        _check(lib().pcal_server_step(self._s, handle, ctypes.byref(n)), "pcal_server_step")
         return n.value
 
     def poll(self):
@@ -500,10 +503,12 @@ class PCalServer:
         """Switch to the device-resident loop: one persistent kernel on `stream` (pcal_server_start)."""
         _check(lib().pcal_server_start(self._s, workgroups, ctypes.c_void_p(_stream_handle(stream))),
                "pcal_server_start")
+        self._resident = True
 
     def stop(self) -> None:
         """Leave the device-resident loop once the published work has ended (pcal_server_stop)."""
         _check(lib().pcal_server_stop(self._s), "pcal_server_stop")
+        self._resident = False
 
     LOOP_STATS = ("chunks_published", "tasks_run", "tasks_published", "descriptor_reads_from_host",
                   "scheduler_rounds", "finalizes", "relaunches", "idle_rounds", "wait_ns", "descriptor_ns",
