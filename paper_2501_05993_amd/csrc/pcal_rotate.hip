@@ -96,7 +96,16 @@ struct RowVec<2> {
     }
     template <class T>
     __device__ __forceinline__ T get(int i) const {
-        return static_cast<T>((q[i & 3] >> (8 * (i >> 2))) & 0xFFu);
+        uint32_t w = q[i & 3];
+        if constexpr (std::is_same<T, float>::value) {
+            // An empty statement the optimiser cannot see through: knowing that
+            // every byte of w is below 4, it would extract the code with a
+            // bit-field extract before a byte-0 conversion (two instructions)
+            // instead of the one conversion of byte b (v_cvt_f32_ubyte<b>).
+            // (The FP64 forms convert through integers either way.)
+            __asm__("" : "+v"(w));
+        }
+        return static_cast<T>((w >> (8 * (i >> 2))) & 0xFFu);
     }
 };
 
