@@ -228,6 +228,9 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None,
         integ_no = [0] * S
         pending = deque()
     torch.cuda.synchronize()
+    # the host-step form launches on the caller's stream: named once here rather than looked up per step
+    # (the device-resident loop runs on a stream of its own and takes none)
+    step_stream = torch.cuda.current_stream() if mode == "served" else None
     if mode == "resident":  # after the device-wide synchronisation: that would wait for the persistent kernel
         srv.start(workgroups=workgroups)
     t0 = time.perf_counter()
@@ -276,7 +279,7 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None,
             # step only with work queued: a piece held back (ring full, or its stream's previous
             # integration not yet reported) stays queued until a later step takes it
             if queued > 0:
-                queued -= srv.step()
+                queued -= srv.step(step_stream)
             for sv, k in srv.poll():
                 s_ = rev[sv]
                 lat.append(time.perf_counter() - t0 - last_arrival[(s_, k)])
