@@ -88,7 +88,10 @@ __device__ void schedule(const ServedArgs &sa, unsigned char *lds) {
             st_agent(sa.heartbeat, polls);
         }
         __syncthreads();
+        // every shared value thread 0 rewrites at the top of a round is read
+        // here, between that round's first and last barriers
         const unsigned long long chunks = s_chunks, copied = s_copied, next = s_next;
+        const bool quit = s_quit != 0;
         // copy the new descriptors (the host wrote each before raising the
         // count): word w of chunk copied + c, all threads
         const int ncopy = static_cast<int>(chunks - copied);
@@ -216,8 +219,8 @@ __device__ void schedule(const ServedArgs &sa, unsigned char *lds) {
         if (t == 0) s_skip = scan ? 0 : s_skip + 1;
         const unsigned long long now = wall_clock64();
         if (!quiet) t_work = now;
-        if (s_quit && t_quit == 0) t_quit = now;
-        if ((quiet && (s_quit || now - t_work > sa.idle_ticks)) || (s_quit && now - t_quit > sa.quit_ticks)) {
+        if (quit && t_quit == 0) t_quit = now;
+        if ((quiet && (quit || now - t_work > sa.idle_ticks)) || (quit && now - t_quit > sa.quit_ticks)) {
             for (int w = 1 + t; w < G; w += nt)
                 st_agent(sa.mail_assigned + static_cast<size_t>(w) * kMailStride, kLeave);
             if (t == 0) {
@@ -227,7 +230,7 @@ __device__ void schedule(const ServedArgs &sa, unsigned char *lds) {
                 add_stat(sa, 7, rounds_idle);
                 wait_memory();
                 __hip_atomic_fetch_add(sa.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                if (!s_quit) __hip_atomic_fetch_add(sa.status + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (!quit) __hip_atomic_fetch_add(sa.status + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             }
             return;
         }
