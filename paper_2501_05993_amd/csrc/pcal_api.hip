@@ -502,6 +502,11 @@ int build(pcal_ctx *h) {
             set_error("hipHostMalloc", e);
             return PCAL_ENOMEM;
         }
+        void *d = nullptr;
+        if (hipHostGetDevicePointer(&d, h->host_out, 0) == hipSuccess)
+            h->host_out_dev = static_cast<double *>(d);
+        else
+            (void)hipGetLastError();  // not mapped: results go through a device copy
     }
     // Rotator factors from exact integer phase indices, in FP64 (Eq. 3-5):
     //   u[m] = exp(-j 2 pi (f_o N m mod fs) / fs),  v[b] = exp(-j 2 pi (f_o b mod fs) / fs),
@@ -637,11 +642,19 @@ FinArgs fin_args(const pcal_ctx *h, double *out) {
     return f;
 }
 
-int run_finalize(pcal_ctx *h) {
+int run_finalize(pcal_ctx *h, bool device_results) {
     const Plan &p = h->plan;
     hipStream_t s = h->last_stream;
     int rc = flush_pending(h, s);
     if (rc) return rc;
+    if (!device_results && h->host_out_dev) {
+        // results for the host only: the finalize writes the pinned copy
+        // itself (no device-to-host copy after it)
+        launch_finalize(fin_args(h, h->host_out_dev), s);
+        PCAL_HIP(hipGetLastError());
+        PCAL_HIP(hipStreamSynchronize(s));
+        return PCAL_OK;
+    }
     launch_finalize(fin_args(h, h->out), s);
     PCAL_HIP(hipGetLastError());
     PCAL_HIP(hipMemcpyAsync(h->host_out, h->out, sizeof(double) * (4 * p.N + 1), hipMemcpyDeviceToHost, s));
@@ -862,7 +875,7 @@ int pcal_extract_timed(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_str
 int pcal_results(pcal_t h, double *amp, double *phase, double *delay) {
     if (!h) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
-    int rc = run_finalize(h);
+    int rc = run_finalize(h, false);
     if (rc) return rc;
     const size_t N = static_cast<size_t>(h->plan.N);
     if (amp) memcpy(amp, h->host_out, sizeof(double) * N);
@@ -930,7 +943,7 @@ int pcal_sync(pcal_t h) {
 int pcal_spectrum(pcal_t h, double *re, double *im) {
     if (!h) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
-    int rc = run_finalize(h);
+    int rc = run_finalize(h, false);
     if (rc) return rc;
     const size_t N = static_cast<size_t>(h->plan.N);
     if (re) memcpy(re, h->host_out + 2 * N, sizeof(double) * N);
@@ -1006,7 +1019,7 @@ int pcal_bandpass(pcal_t h, double *amp, double *phase, double *delay) {
     if (!h) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
     // the finalize leaves amp, phase, re, im and the slope delay in h->out
-    int rc = run_finalize(h);
+    int rc = run_finalize(h, true);
     if (rc) return rc;
     const size_t N = static_cast<size_t>(h->plan.N);
     std::vector<double> out(3 * N + 4);
@@ -1021,7 +1034,7 @@ int pcal_refine(pcal_t h, int iters, double *delays, double *resid) {
     if (!h || iters < 1 || iters > kMaxRefinePasses) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
     // the finalize leaves the reported spectrum in h->out, the pulse readout its peak delay in h->pulse
-    int rc = run_finalize(h);
+    int rc = run_finalize(h, true);
     if (rc) return rc;
     hipStream_t s = h->last_stream;
     launch_pulse(pulse_args(h, false, nullptr), s);

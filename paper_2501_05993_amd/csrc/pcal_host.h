@@ -128,6 +128,7 @@ struct pcal_ctx {
     unsigned *counters = nullptr;  // [0] finalize of bank 0's pending form / plain, [1] bank 1
     double *out = nullptr;         // device results [2][4N + 1]
     double *host_out = nullptr;    // pinned copy
+    double *host_out_dev = nullptr;  // its device address (the finalize of pcal_results writes it directly)
     double2 *rot64 = nullptr;      // rotator table of the table method, in the precision form's
     __half2 *rot16 = nullptr;      // arithmetic (RotArgs): only the one the form reads is allocated
     float2 *rot32 = nullptr;
