@@ -179,7 +179,24 @@ int pcal_results(pcal_t h, double *amp, double *phase, double *delay);
  *   work on the new integration's bank and leave it pending.  With host_out
  *   in pinned host memory (hipHostMalloc)
  *   the finalize writes host_out directly; otherwise a device copy is
- *   enqueued after it. */
+ *   enqueued after it.
+ * reset == PCAL_RESET_OVERLAP: pipelined integrations on two streams.  The
+ *   integration finishes as with reset != 0, and the handle takes the next
+ *   one in a second lane: accumulators, result buffers, pending finalize and
+ *   stream order of its own (allocated at the first such call, about
+ *   16 * 32 * N bytes more; the rotator tables are shared).  Integrations then
+ *   alternate between the lanes, each lane's calls ordered after that lane's
+ *   previous work only, so a caller that feeds them on two streams in turn has
+ *   consecutive integrations run side by side on the GPU; each lane's finalize
+ *   runs inside that lane's next fold launch (pcal_flush runs both lanes'
+ *   at once; pcal_sync and pcal_destroy wait for both).  The global sample
+ *   index runs on across the lanes in call order.  A reset other than
+ *   PCAL_RESET_OVERLAP ends the alternation: the other lane's pending
+ *   finalize runs at once and the next integration stays in the current lane.
+ *   The calls that read the current integration (pcal_results,
+ *   pcal_spectrum, pcal_bins, pcal_pulse, pcal_bandpass, pcal_refine,
+ *   pcal_reset) act on the lane of the current integration. */
+#define PCAL_RESET_OVERLAP 2
 int pcal_results_async(pcal_t h, double *host_out, int reset);
 
 /* Run any pending finalize and wait until all work enqueued on the handle has

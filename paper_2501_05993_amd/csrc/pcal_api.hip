@@ -336,10 +336,16 @@ int dalloc(pcal_ctx *h, T **p, size_t count) {
 }
 
 void release(pcal_ctx *h) {
-    void *ptrs[] = {h->u64, h->u32, h->u16, h->v, h->tw, h->acc_mem, h->acc_int_mem, h->accf_mem, h->counters,
-                    h->out, h->phases, h->pulse, h->pulse_int, h->refine_out, h->rot64, h->rot32, h->rot16, h->w, h->uq};
-    for (void *p : ptrs)
+    if (h->twin) release(h->twin);
+    void *lane[] = {h->acc_mem, h->acc_int_mem, h->accf_mem, h->counters, h->out, h->phases, h->pulse, h->pulse_int,
+                    h->refine_out};
+    for (void *p : lane)
         if (p) (void)hipFree(p);
+    if (!h->shares_tables) {
+        void *tables[] = {h->u64, h->u32, h->u16, h->v, h->tw, h->rot64, h->rot32, h->rot16, h->w, h->uq};
+        for (void *p : tables)
+            if (p) (void)hipFree(p);
+    }
     if (h->host_out) (void)hipHostFree(h->host_out);
     if (h->ev) (void)hipEventDestroy(h->ev);
     delete h;
@@ -489,25 +495,8 @@ int build(pcal_ctx *h) {
         }
     }
     if ((rc = dalloc(h, &h->u64, M)) || (rc = dalloc(h, &h->u32, M)) || (rc = dalloc(h, &h->u16, 2 * M)) ||
-        (rc = dalloc(h, &h->v, N)) || (rc = dalloc(h, &h->tw, N)) || (rc = dalloc(h, &h->acc_mem, 2 * kAccSlots * N)) ||
-        (rc = dalloc(h, &h->acc_int_mem, 2 * kAccSlots * N)) || (rc = dalloc(h, &h->accf_mem, 2 * kAccSlots * N)) ||
-        (rc = dalloc(h, &h->counters, 2)) || (rc = dalloc(h, &h->out, 2 * (4 * N + 1))) ||
-        (rc = dalloc(h, &h->phases, N)) || (rc = dalloc(h, &h->pulse, 3 * N + 4)) ||
-        (rc = dalloc(h, &h->pulse_int, N)) || (rc = dalloc(h, &h->refine_out, kMaxRefinePasses + 3)))
+        (rc = dalloc(h, &h->v, N)) || (rc = dalloc(h, &h->tw, N)) || (rc = alloc_lane(h)))
         return rc;
-    {
-        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->host_out), sizeof(double) * (4 * N + 1),
-                                     hipHostMallocDefault);
-        if (e != hipSuccess) {
-            set_error("hipHostMalloc", e);
-            return PCAL_ENOMEM;
-        }
-        void *d = nullptr;
-        if (hipHostGetDevicePointer(&d, h->host_out, 0) == hipSuccess)
-            h->host_out_dev = static_cast<double *>(d);
-        else
-            (void)hipGetLastError();  // not mapped: results go through a device copy
-    }
     // Rotator factors from exact integer phase indices, in FP64 (Eq. 3-5):
     //   u[m] = exp(-j 2 pi (f_o N m mod fs) / fs),  v[b] = exp(-j 2 pi (f_o b mod fs) / fs),
     //   tw[j] = exp(-j 2 pi j / N)  (DFT twiddles).
@@ -566,12 +555,85 @@ int build(pcal_ctx *h) {
     PCAL_HIP(hipMemcpy(h->u16, uh.data(), sizeof(__half2) * 2 * M, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemcpy(h->v, v.data(), sizeof(double2) * N, hipMemcpyHostToDevice));
     PCAL_HIP(hipMemcpy(h->tw, tw.data(), sizeof(double2) * N, hipMemcpyHostToDevice));
+    return clear_lane(h);
+}
+
+// A lane's own device memory: the accumulators of its two banks, finalize
+// counters and results, readout buffers, and its pinned result copy.
+int alloc_lane(pcal_ctx *h) {
+    const int64_t N = h->plan.N;
+    int rc;
+    if ((rc = dalloc(h, &h->acc_mem, 2 * kAccSlots * N)) || (rc = dalloc(h, &h->acc_int_mem, 2 * kAccSlots * N)) ||
+        (rc = dalloc(h, &h->accf_mem, 2 * kAccSlots * N)) || (rc = dalloc(h, &h->counters, 2)) ||
+        (rc = dalloc(h, &h->out, 2 * (4 * N + 1))) || (rc = dalloc(h, &h->phases, N)) ||
+        (rc = dalloc(h, &h->pulse, 3 * N + 4)) || (rc = dalloc(h, &h->pulse_int, N)) ||
+        (rc = dalloc(h, &h->refine_out, kMaxRefinePasses + 3)))
+        return rc;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->host_out), sizeof(double) * (4 * N + 1),
+                                 hipHostMallocDefault);
+    if (e != hipSuccess) {
+        set_error("hipHostMalloc", e);
+        return PCAL_ENOMEM;
+    }
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, h->host_out, 0) == hipSuccess)
+        h->host_out_dev = static_cast<double *>(d);
+    else
+        (void)hipGetLastError();  // not mapped: results go through a device copy
+    return PCAL_OK;
+}
+
+// Zeroed accumulators and counters, bank 0, and the lane's event.
+int clear_lane(pcal_ctx *h) {
+    const size_t N = static_cast<size_t>(h->plan.N);
     PCAL_HIP(hipMemset(h->acc_mem, 0, sizeof(double2) * 2 * kAccSlots * N));
     PCAL_HIP(hipMemset(h->acc_int_mem, 0, sizeof(long long) * 2 * kAccSlots * N));
     PCAL_HIP(hipMemset(h->accf_mem, 0, sizeof(float2) * 2 * kAccSlots * N));
     PCAL_HIP(hipMemset(h->counters, 0, 2 * sizeof(unsigned)));
     set_bank(h, 0);
     PCAL_HIP(hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
+    return PCAL_OK;
+}
+
+// The second lane of a handle (pipelined integrations): a copy of the
+// primary's plan, tables and scalars with lane state of its own.
+int make_twin(pcal_ctx *h) {
+    pcal_ctx *t = new (std::nothrow) pcal_ctx();
+    if (!t) return PCAL_ENOMEM;
+    *t = *h;
+    t->acc_mem = nullptr;
+    t->acc_int_mem = nullptr;
+    t->accf_mem = nullptr;
+    t->acc = nullptr;
+    t->acc_int = nullptr;
+    t->accf = nullptr;
+    t->counters = nullptr;
+    t->out = nullptr;
+    t->phases = nullptr;
+    t->pulse = nullptr;
+    t->pulse_int = nullptr;
+    t->refine_out = nullptr;
+    t->host_out = nullptr;
+    t->host_out_dev = nullptr;
+    t->ev = nullptr;
+    t->wait_ev = nullptr;
+    t->have_ev = false;
+    t->dirty = false;
+    t->last_stream = nullptr;
+    t->fin_pending = false;
+    t->n_integ = 0;
+    t->device_bytes = 0;
+    t->twin = nullptr;
+    t->on_twin = false;
+    t->shares_tables = true;
+    int rc = alloc_lane(t);
+    if (!rc) rc = clear_lane(t);
+    if (rc) {
+        release(t);
+        return rc;
+    }
+    h->device_bytes += t->device_bytes;
+    h->twin = t;
     return PCAL_OK;
 }
 
@@ -789,8 +851,8 @@ int pcal_extract(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t 
     return pcal_extract_timed(h, dev_ptr, nsamples, stream, nullptr, nullptr);
 }
 
-int pcal_extract_timed(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t stream, void *start_event,
-                       void *stop_event) {
+static int extract_lane(pcal_ctx *h, const void *dev_ptr, int64_t nsamples, pcal_stream_t stream, void *start_event,
+                        void *stop_event) {
     if (!h || nsamples < 0) return PCAL_EINVAL;
     hipEvent_t t0 = static_cast<hipEvent_t>(start_event), t1 = static_cast<hipEvent_t>(stop_event);
     const Plan &p = h->plan;
@@ -872,7 +934,7 @@ int pcal_extract_timed(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_str
     return mark(h, s);
 }
 
-int pcal_results(pcal_t h, double *amp, double *phase, double *delay) {
+static int results_lane(pcal_ctx *h, double *amp, double *phase, double *delay) {
     if (!h) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
     int rc = run_finalize(h, false);
@@ -884,7 +946,7 @@ int pcal_results(pcal_t h, double *amp, double *phase, double *delay) {
     return PCAL_OK;
 }
 
-int pcal_results_async(pcal_t h, double *host_out, int reset) {
+static int results_async_lane(pcal_ctx *h, double *host_out, int reset) {
     if (!h || !host_out) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
     const Plan &p = h->plan;
@@ -917,8 +979,7 @@ int pcal_results_async(pcal_t h, double *host_out, int reset) {
     return PCAL_OK;
 }
 
-int pcal_flush(pcal_t h) {
-    if (!h) return PCAL_EINVAL;
+static int flush_lane(pcal_ctx *h) {
     if (!h->fin_pending) return PCAL_OK;
     DeviceGuard guard(h->device);
     const int rc = flush_pending(h, h->last_stream);
@@ -926,8 +987,7 @@ int pcal_flush(pcal_t h) {
     return rc ? rc : mark(h, h->last_stream);
 }
 
-int pcal_sync(pcal_t h) {
-    if (!h) return PCAL_EINVAL;
+static int sync_lane(pcal_ctx *h) {
     DeviceGuard guard(h->device);
     if (h->fin_pending) {
         const int rc = flush_pending(h, h->last_stream);
@@ -940,7 +1000,7 @@ int pcal_sync(pcal_t h) {
     return PCAL_OK;
 }
 
-int pcal_spectrum(pcal_t h, double *re, double *im) {
+static int spectrum_lane(pcal_ctx *h, double *re, double *im) {
     if (!h) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
     int rc = run_finalize(h, false);
@@ -986,7 +1046,7 @@ static int read_pulse(pcal_ctx *h, double *host, long long *host_int, const doub
     return PCAL_OK;
 }
 
-int pcal_bins(pcal_t h, double *re, double *im, int64_t *int_bins) {
+static int bins_lane(pcal_ctx *h, double *re, double *im, int64_t *int_bins) {
     if (!h) return PCAL_EINVAL;
     if (int_bins && (h->plan.fo != 0 || h->plan.method != PCAL_METHOD_PERIOD_FOLD)) return PCAL_ESTATE;
     DeviceGuard guard(h->device);
@@ -1001,7 +1061,7 @@ int pcal_bins(pcal_t h, double *re, double *im, int64_t *int_bins) {
     return PCAL_OK;
 }
 
-int pcal_pulse(pcal_t h, double *re, double *im, double *delay, double *peak) {
+static int pulse_lane(pcal_ctx *h, double *re, double *im, double *delay, double *peak) {
     if (!h) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
     const size_t N = static_cast<size_t>(h->plan.N);
@@ -1015,7 +1075,7 @@ int pcal_pulse(pcal_t h, double *re, double *im, double *delay, double *peak) {
     return PCAL_OK;
 }
 
-int pcal_bandpass(pcal_t h, double *amp, double *phase, double *delay) {
+static int bandpass_lane(pcal_ctx *h, double *amp, double *phase, double *delay) {
     if (!h) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
     // the finalize leaves amp, phase, re, im and the slope delay in h->out
@@ -1030,7 +1090,7 @@ int pcal_bandpass(pcal_t h, double *amp, double *phase, double *delay) {
     return PCAL_OK;
 }
 
-int pcal_refine(pcal_t h, int iters, double *delays, double *resid) {
+static int refine_lane(pcal_ctx *h, int iters, double *delays, double *resid) {
     if (!h || iters < 1 || iters > kMaxRefinePasses) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
     // the finalize leaves the reported spectrum in h->out, the pulse readout its peak delay in h->pulse
@@ -1060,7 +1120,7 @@ int pcal_refine(pcal_t h, int iters, double *delays, double *resid) {
     return PCAL_OK;
 }
 
-int pcal_reset(pcal_t h) {
+static int reset_lane(pcal_ctx *h) {
     if (!h) return PCAL_EINVAL;
     DeviceGuard guard(h->device);
     hipStream_t s = h->last_stream;
@@ -1072,13 +1132,92 @@ int pcal_reset(pcal_t h) {
     return mark(h, s);
 }
 
+static void drain_lane(pcal_ctx *h) {
+    if (h->fin_pending && flush_pending(h, h->last_stream) == PCAL_OK) (void)hipStreamSynchronize(h->last_stream);
+    if (settle(h) == PCAL_OK && h->have_ev) (void)hipEventSynchronize(h->wait_ev);
+}
+
+// The lane of the current integration, and the other one (null without a twin).
+static pcal_ctx *cur_lane(pcal_ctx *h) { return h->on_twin ? h->twin : h; }
+static pcal_ctx *other_lane(pcal_ctx *h) { return h->twin ? (h->on_twin ? h : h->twin) : nullptr; }
+
+int pcal_extract_timed(pcal_t h, const void *dev_ptr, int64_t nsamples, pcal_stream_t stream, void *start_event,
+                       void *stop_event) {
+    if (!h) return PCAL_EINVAL;
+    pcal_ctx *L = cur_lane(h);
+    if (L == h) return extract_lane(h, dev_ptr, nsamples, stream, start_event, stop_event);
+    L->n_total = h->n_total;  // the global sample index runs on across lanes
+    const int rc = extract_lane(L, dev_ptr, nsamples, stream, start_event, stop_event);
+    h->n_total = L->n_total;
+    return rc;
+}
+
+int pcal_results(pcal_t h, double *amp, double *phase, double *delay) {
+    return h ? results_lane(cur_lane(h), amp, phase, delay) : PCAL_EINVAL;
+}
+
+int pcal_results_async(pcal_t h, double *host_out, int reset) {
+    if (!h || !host_out) return PCAL_EINVAL;
+    pcal_ctx *L = cur_lane(h);
+    if (reset != PCAL_RESET_OVERLAP) {
+        int rc = results_async_lane(L, host_out, reset);
+        pcal_ctx *O = other_lane(h);
+        // a plain reset ends the pipelining: the other lane's pending finalize runs now
+        if (!rc && reset && O) rc = flush_lane(O);
+        return rc;
+    }
+    // finish this integration on its lane (its finalize rides in that lane's
+    // next fold) and take the next one on the other lane
+    int rc = results_async_lane(L, host_out, 1);
+    if (rc) return rc;
+    if (!h->twin) {
+        DeviceGuard guard(h->device);
+        if ((rc = make_twin(h))) return rc;
+    }
+    h->on_twin = !h->on_twin;
+    return PCAL_OK;
+}
+
+int pcal_flush(pcal_t h) {
+    if (!h) return PCAL_EINVAL;
+    int rc = flush_lane(h);
+    if (!rc && h->twin) rc = flush_lane(h->twin);
+    return rc;
+}
+
+int pcal_sync(pcal_t h) {
+    if (!h) return PCAL_EINVAL;
+    int rc = sync_lane(h);
+    if (!rc && h->twin) rc = sync_lane(h->twin);
+    return rc;
+}
+
+int pcal_spectrum(pcal_t h, double *re, double *im) { return h ? spectrum_lane(cur_lane(h), re, im) : PCAL_EINVAL; }
+
+int pcal_bins(pcal_t h, double *re, double *im, int64_t *int_bins) {
+    return h ? bins_lane(cur_lane(h), re, im, int_bins) : PCAL_EINVAL;
+}
+
+int pcal_pulse(pcal_t h, double *re, double *im, double *delay, double *peak) {
+    return h ? pulse_lane(cur_lane(h), re, im, delay, peak) : PCAL_EINVAL;
+}
+
+int pcal_bandpass(pcal_t h, double *amp, double *phase, double *delay) {
+    return h ? bandpass_lane(cur_lane(h), amp, phase, delay) : PCAL_EINVAL;
+}
+
+int pcal_refine(pcal_t h, int iters, double *delays, double *resid) {
+    return h ? refine_lane(cur_lane(h), iters, delays, resid) : PCAL_EINVAL;
+}
+
+int pcal_reset(pcal_t h) { return h ? reset_lane(cur_lane(h)) : PCAL_EINVAL; }
+
 int pcal_destroy(pcal_t h) {
     if (!h) return PCAL_EINVAL;
     {
         DeviceGuard guard(h->device);
-        if (h->fin_pending && flush_pending(h, h->last_stream) == PCAL_OK)
-            (void)hipStreamSynchronize(h->last_stream);
-        if (settle(h) == PCAL_OK && h->have_ev) (void)hipEventSynchronize(h->wait_ev);
+        drain_lane(h);
+        if (h->twin) drain_lane(h->twin);
         release(h);
     }
     return PCAL_OK;
@@ -1094,7 +1233,7 @@ int pcal_info(pcal_t h, pcal_info_t *info) {
     if (!h || !info) return PCAL_EINVAL;
     fill_info(h->plan, info);
     info->samples_total = h->n_total;
-    info->samples_integ = h->n_integ;
+    info->samples_integ = cur_lane(h)->n_integ;
     info->device_bytes = static_cast<int64_t>(h->device_bytes);
     return PCAL_OK;
 }

@@ -145,12 +145,25 @@ struct pcal_ctx {
     hipEvent_t wait_ev = nullptr;  // the recorded event marking the handle's last work
     bool have_ev = false;
     size_t device_bytes = 0;
+    // Pipelined integrations (pcal_results_async with PCAL_RESET_OVERLAP): a
+    // second lane with its own accumulators, result buffers, pending finalize
+    // and stream bookkeeping, and the primary's read-only tables, takes every
+    // other integration, so that consecutive integrations fed on two streams
+    // run side by side (each lane's finalize rides in its own next fold).
+    pcal_ctx *twin = nullptr;
+    bool on_twin = false;         // the current integration is the twin's
+    bool shares_tables = false;   // this is a twin: its tables are the primary's
 };
 
 namespace pcal {
 namespace host {
 
 int build(pcal_ctx *h);
+// A lane's own device memory (accumulators, counters, results, readouts) and
+// its zeroed state; the second lane of pipelined integrations.
+int alloc_lane(pcal_ctx *h);
+int clear_lane(pcal_ctx *h);
+int make_twin(pcal_ctx *h);
 // Point acc / acc_int / accf at bank b.
 void set_bank(pcal_ctx *h, int b);
 // Run a pending finalize on its own (on s).

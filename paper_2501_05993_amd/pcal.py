@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libpcal.so")
 
 OK, EINVAL, ENOMEM, EHIP, EAGAIN, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 METHOD_AUTO, METHOD_PERIOD_FOLD, METHOD_LUT, METHOD_OSC, METHOD_CFO, METHOD_MCO, METHOD_DFR_EF = 0, 1, 2, 3, 4, 5, 6
+RESET_OVERLAP = 2  # pcal_results_async: finish the integration, take the next in the other lane (two streams)
 PREC_F64, PREC_MIXED, PREC_F32, PREC_F16, PREC_Q17 = 0, 1, 2, 3, 4
 
 _i64 = ctypes.c_int64
@@ -260,10 +261,12 @@ class PCal:
                "pcal_results")
         return amp, phase, float(delay[0])
 
-    def results_async(self, host_out, reset: bool = False) -> None:
-        """Enqueue finalize + copy into host_out (4N+1 doubles, ideally pinned); see pcal_results_async."""
+    def results_async(self, host_out, reset=False) -> None:
+        """Enqueue finalize + copy into host_out (4N+1 doubles, ideally pinned); see pcal_results_async.
+        reset: False, True, or RESET_OVERLAP (pipelined integrations on two streams in turn)."""
         ptr = host_out.data_ptr() if isinstance(host_out, torch.Tensor) else host_out.ctypes.data
-        _check(lib().pcal_results_async(self._h, ctypes.c_void_p(ptr), 1 if reset else 0), "pcal_results_async")
+        flag = RESET_OVERLAP if reset == RESET_OVERLAP else (1 if reset else 0)
+        _check(lib().pcal_results_async(self._h, ctypes.c_void_p(ptr), flag), "pcal_results_async")
 
     def sync(self) -> None:
         _check(lib().pcal_sync(self._h), "pcal_sync")
