@@ -195,7 +195,9 @@ int pcal_results(pcal_t h, double *amp, double *phase, double *delay);
  *   finalize runs at once and the next integration stays in the current lane.
  *   The calls that read the current integration (pcal_results,
  *   pcal_spectrum, pcal_bins, pcal_pulse, pcal_bandpass, pcal_refine,
- *   pcal_reset) act on the lane of the current integration. */
+ *   pcal_reset) act on the lane of the current integration.  PCAL_ENOTSUP
+ *   for a member of a batch (pcal_batch_handle), which the batch folds in its
+ *   one lane. */
 #define PCAL_RESET_OVERLAP 2
 int pcal_results_async(pcal_t h, double *host_out, int reset);
 

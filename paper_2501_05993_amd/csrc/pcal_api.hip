@@ -1166,6 +1166,7 @@ int pcal_results_async(pcal_t h, double *host_out, int reset) {
         if (!rc && reset && O) rc = flush_lane(O);
         return rc;
     }
+    if (h->batch_member) return PCAL_ENOTSUP;  // the batch folds its members in one lane
     // finish this integration on its lane (its finalize rides in that lane's
     // next fold) and take the next one on the other lane
     int rc = results_async_lane(L, host_out, 1);

@@ -247,6 +247,7 @@ int pcal_batch_add(pcal_batch_t b, int64_t fs_hz, int64_t f_comb_hz, int64_t f_o
     int rc = create(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_PERIOD_FOLD, b->prec, b->threads, &h);
     if (rc == PCAL_ENOTSUP) rc = create(fs_hz, f_comb_hz, f_offset_hz, nbits, sideband, PCAL_METHOD_AUTO, b->prec, 0, &h);
     if (rc) return rc;
+    h->batch_member = true;
     if (slot < 0) {
         b->members.push_back(h);
         slot = static_cast<int>(b->members.size()) - 1;

@@ -153,6 +153,7 @@ struct pcal_ctx {
     pcal_ctx *twin = nullptr;
     bool on_twin = false;         // the current integration is the twin's
     bool shares_tables = false;   // this is a twin: its tables are the primary's
+    bool batch_member = false;    // folded by a batch (pcal_batch_*), which uses its one lane
 };
 
 namespace pcal {

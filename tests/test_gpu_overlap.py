@@ -134,3 +134,18 @@ def test_overlap_mixed_sequences(pc):
         g = (pageable[k][2 * N:3 * N] + 1j * pageable[k][3 * N:4 * N]) if page else got[k]
         assert_spectra(g, want[k], amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6,
                        what="integration %d (stream %d, %s reset)" % (k, si, how))
+
+
+def test_overlap_refused_for_batch_members(pc):
+    """A batch folds its members in one lane: the overlap reset on a member handle is PCAL_ENOTSUP
+    (the plain reset stays available)."""
+    import ctypes
+
+    with pc.PCalBatch(2) as b:
+        i = b.add(64_000_000, 1_000_000, 10_000, 2)
+        h = ctypes.c_void_p()
+        assert pc.lib().pcal_batch_handle(b._b, i, ctypes.byref(h)) == pc.OK
+        out = torch.zeros(4 * 64 + 1, dtype=torch.float64, pin_memory=True)
+        assert pc.lib().pcal_results_async(h, ctypes.c_void_p(out.data_ptr()), pc.RESET_OVERLAP) == pc.ENOTSUP
+        assert pc.lib().pcal_results_async(h, ctypes.c_void_p(out.data_ptr()), 1) == pc.OK
+        assert pc.lib().pcal_sync(h) == pc.OK
