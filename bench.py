@@ -10,8 +10,8 @@ per integration is measured separately with synchronised calls.  Inputs are resi
 HBM before timing starts and rotate over four distinct 256 MiB buffers so
 the 256 MB last-level cache cannot serve them.
 
-Prints one JSON line (see the keys below).  ``--gpus N`` with N > 1 exits:
-this build runs on one GPU.
+Prints one JSON line (see the keys below).  ``--gpus N`` with N > 1 exits
+with a message: the benchmark runs on one GPU.
 """
 import argparse
 import hashlib
@@ -701,8 +701,8 @@ def main():
                          "scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the extraction of one stream does not span GPUs in this build "
-              "(see DESIGN.md, 'More than one GPU')", file=sys.stderr)
+        print("bench.py runs on one GPU only: the extraction of one stream does not span GPUs, and more than "
+              "one is not supported", file=sys.stderr)
         sys.exit(2)
 
     global np
