@@ -184,7 +184,7 @@ int pcal_results(pcal_t h, double *amp, double *phase, double *delay);
  *   integration finishes as with reset != 0, and the handle takes the next
  *   one in a second lane: accumulators, result buffers, pending finalize and
  *   stream order of its own (allocated at the first such call, about
- *   16 * 32 * N bytes more; the rotator tables are shared).  Integrations then
+ *   1.1 KB per tone of device memory more; the rotator tables are shared).  Integrations then
  *   alternate between the lanes, each lane's calls ordered after that lane's
  *   previous work only, so a caller that feeds them on two streams in turn has
  *   consecutive integrations run side by side on the GPU; each lane's finalize
@@ -202,11 +202,12 @@ int pcal_results(pcal_t h, double *amp, double *phase, double *delay);
 int pcal_results_async(pcal_t h, double *host_out, int reset);
 
 /* Run any pending finalize and wait until all work enqueued on the handle has
- * finished. */
+ * finished (both lanes' after PCAL_RESET_OVERLAP). */
 int pcal_sync(pcal_t h);
 
 /* Enqueue a finalize left pending by pcal_results_async(reset != 0) now, on
- * the handle's last stream, instead of inside the next pcal_extract; returns
+ * the handle's last stream (with two lanes, each lane's on that lane's last
+ * stream), instead of inside the next pcal_extract; returns
  * at once (host_out is complete when that stream reaches this point).  For
  * callers that want each integration's results without waiting for the next
  * chunk.  No-op when nothing is pending.  Errors: PCAL_EINVAL (null handle),
