@@ -149,3 +149,46 @@ def test_overlap_refused_for_batch_members(pc):
         assert pc.lib().pcal_results_async(h, ctypes.c_void_p(out.data_ptr()), pc.RESET_OVERLAP) == pc.ENOTSUP
         assert pc.lib().pcal_results_async(h, ctypes.c_void_p(out.data_ptr()), 1) == pc.OK
         assert pc.lib().pcal_sync(h) == pc.OK
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_overlap_random_sequences(pc, seed):
+    """Seeded random sequences: each integration in one to three chunks on one of three streams,
+    ended by an overlapped or a plain reset, with synchronous readouts of the integration so far
+    between chunks now and then; every integration equals the plain one-stream sequence's."""
+    rng = np.random.default_rng(seed)
+    spec = synth.CombSpec(32_000_000, 1_000_000, 10_000, 2, amp=0.3, t_d=3e-9, seed=(99, seed))
+    n_int = 10
+    Li = 1 << 22
+    buf = _stream_data(spec, n_int * Li)
+    N = spec.ntones
+    spb = 8 // spec.nbits
+    ref = torch.zeros((n_int, 4 * N + 1), dtype=torch.float64, pin_memory=True)
+    with pc.PCal(spec.fs, spec.f_comb, spec.f_offset, spec.nbits) as h:
+        for k in range(n_int):
+            h.extract(buf, Li, byte_offset=k * Li // spb)
+            h.results_async(ref[k], reset=True)
+        h.sync()
+    want = _spectra(ref, N)
+    s = [torch.cuda.Stream() for _ in range(3)]
+    ring = torch.zeros((n_int, 4 * N + 1), dtype=torch.float64, pin_memory=True)
+    say("overlap: random sequence, seed %d" % seed)
+    with pc.PCal(spec.fs, spec.f_comb, spec.f_offset, spec.nbits) as h:
+        for k in range(n_int):
+            cuts = sorted(set(int(c) * spb for c in rng.integers(1, Li // spb, size=int(rng.integers(0, 3)))))
+            edges = [0] + cuts + [Li]
+            st = s[int(rng.integers(0, 3))]
+            for a, b in zip(edges[:-1], edges[1:]):
+                h.extract(buf, b - a, byte_offset=(k * Li + a) // spb, stream=st)
+                if rng.random() < 0.2:
+                    part = h.spectrum()
+                    Co = oracle.correlate(buf[k * Li // spb:(k * Li + b) // spb].cpu().numpy(), spec.nbits, b,
+                                          spec.fs, spec.f_comb, spec.f_offset, n0=k * Li)
+                    assert_spectra(part, Co, amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6,
+                                   what="integration %d so far" % k)
+            h.results_async(ring[k], reset=pc.RESET_OVERLAP if rng.random() < 0.7 else True)
+        h.sync()
+    got = _spectra(ring, N)
+    for k in range(n_int):
+        assert_spectra(got[k], want[k], amp_rtol=F64_RTOL, phase_atol=F64_RTOL, rel_floor=1e-6,
+                       what="random sequence %d, integration %d" % (seed, k))
