@@ -1167,14 +1167,14 @@ int pcal_results_async(pcal_t h, double *host_out, int reset) {
         return rc;
     }
     if (h->batch_member) return PCAL_ENOTSUP;  // the batch folds its members in one lane
-    // finish this integration on its lane (its finalize rides in that lane's
-    // next fold) and take the next one on the other lane
-    int rc = results_async_lane(L, host_out, 1);
-    if (rc) return rc;
-    if (!h->twin) {
+    int rc = PCAL_OK;
+    if (!h->twin) {  // the second lane first: a failure leaves the integration going on
         DeviceGuard guard(h->device);
         if ((rc = make_twin(h))) return rc;
     }
+    // finish this integration on its lane (its finalize rides in that lane's
+    // next fold) and take the next one on the other lane
+    if ((rc = results_async_lane(L, host_out, 1))) return rc;
     h->on_twin = !h->on_twin;
     return PCAL_OK;
 }
