@@ -466,8 +466,10 @@ int pcal_server_destroy(pcal_server_t s);
  * host memory and returns.  Workgroup 0 of the kernel schedules: it reads the
  * count of published chunks, copies each new descriptor into device memory
  * and hands the chunks' fold tasks (one per 128 KiB of the chunk,
- * PCAL_SERVED_TASK_KIB, at least its column tiles, at most 32,
- * PCAL_SERVED_TASKS) in order to idle workgroups through per-workgroup
+ * PCAL_SERVED_TASK_KIB, or per 2 MiB, PCAL_SERVED_BACKLOG_TASK_KIB, when
+ * the chunk published 32 chunks earlier, PCAL_SERVED_BACKLOG, has not yet
+ * ended; at least its column tiles, at most 32, PCAL_SERVED_TASKS) in
+ * order to idle workgroups through per-workgroup
  * mailboxes in device memory.  The other workgroups fold their task into the
  * stream's accumulator bank in HBM (two banks per stream, alternating by
  * integration); the task that completes an integration runs its FP64

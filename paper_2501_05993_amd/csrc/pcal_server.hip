@@ -85,6 +85,8 @@ struct pcal_server_ctx {
     hipStream_t rstream = nullptr;
     int rgrid = 0, tasks = 0, cap = 0, done_cap = 0;
     int64_t task_bytes = 0;   // chunk bytes per fold task
+    int64_t backlog_task_bytes = 0;  // the same under a backlog of backlog_chunks chunks
+    int backlog_chunks = 0;
     size_t mail_bytes = 0;    // both mailbox arrays (cleared before a relaunch)
     unsigned long long tasks_published = 0;  // fold tasks of the chunks published
     hipStream_t sstream = nullptr;           // reads of the loop counters while the kernel runs
@@ -135,6 +137,13 @@ constexpr double kQuitSeconds = 1.0;     // after quit, the scheduler waits this
 // a chunk gets ceil(bytes / this) tasks, at least its column tiles, at most
 // the tasks per chunk.
 constexpr int kTaskKib = 128;
+// Under a backlog -- the chunk published kBacklogChunks chunks before this one
+// has not ended (PCAL_SERVED_BACKLOG) -- every worker is busy and a new chunk
+// waits for its turn anyway: its tasks then take kBacklogTaskKib of the chunk
+// each (PCAL_SERVED_BACKLOG_TASK_KIB), fewer hand-outs for the scheduler at no
+// cost in latency.
+constexpr int kBacklogChunks = 32;
+constexpr int kBacklogTaskKib = 2048;
 
 template <class T>
 int coherent_alloc(T **host, size_t count) {
@@ -283,7 +292,13 @@ int publish(pcal_server_ctx *s, int64_t *samples) {
             const int bank = static_cast<int>(st.integ & 1);
             const size_t NS = static_cast<size_t>(kAccSlots) * static_cast<size_t>(p.N);
             ServedDesc &d = s->ring[slot];
-            const int64_t want = (take / st.spb + s->task_bytes - 1) / s->task_bytes;
+            const unsigned long long back = static_cast<unsigned>(s->backlog_chunks);
+            const bool backlog =
+                back > 0 && c >= back &&
+                __atomic_load_n(s->slot_free + (c - back) % static_cast<unsigned>(s->cap), __ATOMIC_RELAXED) <
+                    c - back + 1;
+            const int64_t tb = backlog ? s->backlog_task_bytes : s->task_bytes;
+            const int64_t want = (take / st.spb + tb - 1) / tb;
             const int target = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, s->tasks)));
             const pcal_launch_t L = plan_launch(p, reinterpret_cast<uintptr_t>(pc.ptr), h->n_total, take, target);
             d.fold = fold_args(h, L, pc.ptr);
@@ -622,6 +637,9 @@ int pcal_server_start(pcal_server_t s, int workgroups, pcal_stream_t stream) {
     s->args = ServedArgs{};
     s->tasks = std::max(1, env_int("PCAL_SERVED_TASKS", kTasksPerChunk));
     s->task_bytes = static_cast<int64_t>(std::max(1, env_int("PCAL_SERVED_TASK_KIB", kTaskKib))) << 10;
+    s->backlog_task_bytes =
+        static_cast<int64_t>(std::max(1, env_int("PCAL_SERVED_BACKLOG_TASK_KIB", kBacklogTaskKib))) << 10;
+    s->backlog_chunks = std::min(kRingSlots - 1, std::max(0, env_int("PCAL_SERVED_BACKLOG", kBacklogChunks)));
     for (int i = 0; i < s->max_streams; ++i) {
         if (!s->streams[i].open) continue;
         pcal_t h = nullptr;

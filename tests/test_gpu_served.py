@@ -70,11 +70,14 @@ ALONE_TOL = {0: F64_RTOL, 1: 1e-6, 2: 1e-5}
 
 
 @pytest.mark.parametrize("prec,resident,task_kib", [(0, False, None), (1, False, None), (2, False, None),
-                                                    (0, True, None), (1, True, None), (0, True, 8)])
+                                                    (0, True, None), (1, True, None), (0, True, 8),
+                                                    (0, True, "backlog")])
 def test_served_matches_plain_per_integration(prec, resident, task_kib, monkeypatch):
     """Host-step form, and the device-resident form (one persistent kernel fed through the work
     ring: 24 workgroups, fewer than a chunk's 32 task indices, so chunks also run one task after
-    another; with 8 KiB per fold task, most tasks of a chunk read the descriptor's device copy)."""
+    another; with 8 KiB per fold task, most tasks of a chunk read the descriptor's device copy;
+    "backlog": 8 KiB per task, 64 KiB whenever the chunk before has not ended, so the chunks of
+    one integration come with task counts of both sizes)."""
     import time
 
     from paper_2501_05993_amd import pcal
@@ -86,7 +89,11 @@ def test_served_matches_plain_per_integration(prec, resident, task_kib, monkeypa
     for fs, fc, fo, nbits, integ in STREAMS:
         sids.append(srv.open(fs, fc, fo, nbits, integ))
     if resident:
-        if task_kib is not None:  # many fold tasks per chunk: most read the descriptor's device copy
+        if task_kib == "backlog":
+            monkeypatch.setenv("PCAL_SERVED_TASK_KIB", "8")
+            monkeypatch.setenv("PCAL_SERVED_BACKLOG", "1")
+            monkeypatch.setenv("PCAL_SERVED_BACKLOG_TASK_KIB", "64")
+        elif task_kib is not None:  # many fold tasks per chunk: most read the descriptor's device copy
             monkeypatch.setenv("PCAL_SERVED_TASK_KIB", str(task_kib))
         srv.start(workgroups=24)
     # interleave the streams' chunks in a random order of arrival
