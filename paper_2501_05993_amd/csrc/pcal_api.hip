@@ -174,6 +174,16 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
     if (method == PCAL_METHOD_PERIOD_FOLD) {
         p->geom = plan_geom(p->Sp, spv_of(nbits), kMaxLdsPositions, kMaxFoldThreads, force_threads,
                             kMinFoldThreads, kAimFoldThreads);
+        if (p->geom.col_tiles > 1 && !force_threads && env_int("PCAL_FOLD_THREADS", 0) == 0) {
+            // A period split into column tiles: one row of a tile per workgroup
+            // (the smallest workgroup that covers a tile), so that more
+            // workgroups, each ending with an epilogue over its tile, are
+            // resident at once (measured at 2-bit, fold period 8e6, 625 tiles
+            // of 200 vectors: 256 threads 53 us per 2^30 samples against 62 us
+            // with 640; period 64e6: 104 against 160 us).
+            p->geom = plan_geom(p->Sp, spv_of(nbits), kMaxLdsPositions, kMaxFoldThreads,
+                                (p->geom.tile_vecs + 63) / 64 * 64, kMinFoldThreads, kAimFoldThreads);
+        }
     } else {
         // rows of a multiple of lcm(N, 16) samples: every lane keeps its bin
         const int64_t per = p->N / gcd64(p->N, kRotLanes) * kRotLanes;

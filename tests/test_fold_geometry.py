@@ -262,7 +262,9 @@ def test_fold_plan_rules(fs, fo, nbits):
     distinct positions) and the first such multiple; split tiles are whole
     128-byte lines wide and hold at most 12800 positions; workgroups are at
     least 448 threads, waste the fewest lanes, and among equal sizes take the
-    one nearest 640."""
+    one nearest 640 -- except for a period split into tiles, whose workgroups
+    are the smallest multiple of 64 threads that covers one tile (one row of
+    the tile each)."""
     info = pcal.plan(fs, 1_000_000, fo, nbits, method=pcal.METHOD_PERIOD_FOLD)
     spv = 64 if nbits == 2 else 16
     S, Sp = info["joint_period"], info["fold_period"]
@@ -276,6 +278,9 @@ def test_fold_plan_rules(fs, fo, nbits):
     assert info["lds_positions"] == tile * spv <= 12800
     if tiles > 1:
         assert tile % 8 == 0
+    if tiles > 1:
+        assert thr == (tile + 63) // 64 * 64 and info["row_vectors"] == W
+        return
     assert 448 <= thr <= 768 and thr % 64 == 0 and thr >= tile
     eff = lambda t: (t // tile) * tile / t
     best = max(eff(t) for t in range(448, 769, 64) if t >= tile)
