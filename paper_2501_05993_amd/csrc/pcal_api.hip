@@ -174,13 +174,17 @@ int make_plan(int64_t fs, int64_t fc, int64_t fo, int nbits, int sideband, int m
     if (method == PCAL_METHOD_PERIOD_FOLD) {
         p->geom = plan_geom(p->Sp, spv_of(nbits), kMaxLdsPositions, kMaxFoldThreads, force_threads,
                             kMinFoldThreads, kAimFoldThreads);
-        if (p->geom.col_tiles > 1 && !force_threads && env_int("PCAL_FOLD_THREADS", 0) == 0) {
-            // A period split into column tiles: one row of a tile per workgroup
-            // (the smallest workgroup that covers a tile), so that more
-            // workgroups, each ending with an epilogue over its tile, are
-            // resident at once (measured at 2-bit, fold period 8e6, 625 tiles
-            // of 200 vectors: 256 threads 53 us per 2^30 samples against 62 us
-            // with 640; period 64e6: 104 against 160 us).
+        if (p->geom.col_tiles > kSmallTileWgTiles && !force_threads && env_int("PCAL_FOLD_THREADS", 0) == 0) {
+            // More column tiles than the larger workgroups have resident slots
+            // (one per compute unit): one row of a tile per workgroup (the
+            // smallest workgroup that covers a tile), so that all tiles, each
+            // ending with an epilogue of its own, run at once (measured at
+            // 2-bit, fold period 8e6, 625 tiles of 200 vectors: 256 threads 53
+            // us per 2^30 samples against 62 us with 640; period 64e6, 5000
+            // tiles: 104 against 160 us).  With fewer tiles the larger
+            // workgroups win (2-8 tiles: 48-50 us against 52-71 us): the
+            // smaller ones split each tile over more workgroups, each adding
+            // an epilogue over the whole tile.
             p->geom = plan_geom(p->Sp, spv_of(nbits), kMaxLdsPositions, kMaxFoldThreads,
                                 (p->geom.tile_vecs + 63) / 64 * 64, kMinFoldThreads, kAimFoldThreads);
         }

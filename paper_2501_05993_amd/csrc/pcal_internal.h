@@ -15,6 +15,10 @@ constexpr int spv_of(int nbits) { return nbits == 2 ? 64 : 16; }
 // 200 vectors of 2-bit samples, with the skew, the spare column and a 512-row
 // FP64 table under 64 KiB.
 constexpr int kMaxLdsPositions = 12800;
+// Column tiles beyond which a tiled fold period gets one tile row per
+// workgroup (the compute units of the device: one larger fold workgroup is
+// resident on each).
+constexpr int kSmallTileWgTiles = 256;
 // Rotator rows (u table) kept in LDS by the fold kernel when the table is at most this long.
 constexpr int kLdsTableRows = 512;
 // Per-thread LDS scratch of the fold epilogue (a partial bin sum in every precision).

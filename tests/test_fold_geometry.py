@@ -253,6 +253,8 @@ def test_auto_prefers_recurrence_for_long_periods():
 # fs, f_offset, nbits across the paper's and the serving mix's configurations
 _PLAN_CASES = [(fs * 1_000_000, fo, nb) for fs in (16, 32, 64, 128, 256, 512, 1024)
                for fo in (0, 10_000, 250_000, 500_000, 510_000) for nb in (2, 8)]
+# long fold periods: 625 and 5000 column tiles at 2-bit
+_PLAN_CASES += [(64_000_000, 10_008, 2), (64_000_000, 10_007, 2), (64_000_000, 10_008, 8)]
 
 
 @pytest.mark.parametrize("fs,fo,nbits", _PLAN_CASES)
@@ -262,9 +264,9 @@ def test_fold_plan_rules(fs, fo, nbits):
     distinct positions) and the first such multiple; split tiles are whole
     128-byte lines wide and hold at most 12800 positions; workgroups are at
     least 448 threads, waste the fewest lanes, and among equal sizes take the
-    one nearest 640 -- except for a period split into tiles, whose workgroups
-    are the smallest multiple of 64 threads that covers one tile (one row of
-    the tile each)."""
+    one nearest 640 -- except for a period split into more than 256 tiles,
+    whose workgroups are the smallest multiple of 64 threads that covers one
+    tile (one row of the tile each)."""
     info = pcal.plan(fs, 1_000_000, fo, nbits, method=pcal.METHOD_PERIOD_FOLD)
     spv = 64 if nbits == 2 else 16
     S, Sp = info["joint_period"], info["fold_period"]
@@ -278,7 +280,7 @@ def test_fold_plan_rules(fs, fo, nbits):
     assert info["lds_positions"] == tile * spv <= 12800
     if tiles > 1:
         assert tile % 8 == 0
-    if tiles > 1:
+    if tiles > 256:
         assert thr == (tile + 63) // 64 * 64 and info["row_vectors"] == W
         return
     assert 448 <= thr <= 768 and thr % 64 == 0 and thr >= tile
